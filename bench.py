@@ -1,0 +1,163 @@
+"""Throughput of the SDPD-DEM hot path on one MI355X.
+
+Workload: the dam break with rigid particles at 1M moving particles
+(1,028,576 SDPD fluid + 20,000 DEM spheres of diameter 3dx, 485,592 wall
+particles, 1,534,168 in all), seeded synthetic inputs.  A step is one
+iteration of Algorithm 1: two velocity-Verlet passes, each running the
+whole force evaluation of Algorithm 2, with the cell sort, neighbour
+build, density and pressure smoothing once per step.
+
+Prints one JSON line: particle-steps/s of the moving particles, the
+roofline of the dominant kernel (the SDPD pair-force kernel), measured with
+HIP events on its launch stream over the timed region, and the FP64 CPU
+oracle timed on a bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# plain (unpacked) VALU issue: 256 CUs x 64 lanes x 2.4 GHz, one op per lane-cycle
+VALU_PEAK_GOPS = 256 * 64 * 2.4
+
+
+def pair_kernel_bytes(n, n_act, nnz_act, noise):
+    """Algorithmic HBM bytes of one launch of the pair-force kernel: every
+    particle's type and its 9 FP32 outputs; for each fluid/inner-wall
+    particle its own FP64 position, the two FP32 pair records, its row
+    length and its neighbour indices (plus its id with noise).  Neighbour
+    records themselves come from cache and are not counted."""
+    return n * (1 + 36) + n_act * (32 + 16 + 16 + 4 + (4 if noise else 0)) + 4 * nnz_act
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--kT", type=float, default=0.0, help="thermal energy (0: the dam break as defined)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target length of the CPU-oracle sample (0 disables it)")
+    ap.add_argument("--small", action="store_true", help="a small tank, for quick checks")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not "
+                                   "part of it (see the sharding notes in the design)",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2002_03120_amd import sdpdem as S
+    from paper_2002_03120_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    if args.small:
+        p, parts, info = W.dam_break(tank=(64, 32, 48), column=(32, 32, 32), n_rigid=600,
+                                     kBT=args.kT)
+    else:
+        p, parts, info = W.dam_break(kBT=args.kT)
+    print(f"# workload {info}", file=sys.stderr, flush=True)
+    sysm = S.System(p, parts)
+    sysm.step(args.warmup)
+    torch.cuda.synchronize()
+    noise = args.kT > 0
+
+    # timed region: exactly `steps` steps, the pair kernel timed by events
+    sysm.set_profiling("fluid_forces")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sysm.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k_ms, k_launches = sysm.kernel_time()
+    sysm.set_profiling("none")
+    wall = t1 - t0
+
+    inf = sysm.info()
+    typ = parts["type"]
+    n = int(info["n"])
+    n_act = int(((typ == W.FLUID) | (typ == W.INNER_WALL)).sum())
+    nnz = int(inf[9])
+    value = info["n_moving"] * args.steps / wall
+    pair_rate = 2 * nnz * args.steps / wall
+    k_avg_s = (k_ms / max(k_launches, 1)) / 1e3
+    kbytes = pair_kernel_bytes(n, n_act, nnz, noise)
+    achieved = kbytes / k_avg_s / 1e9
+    roof = {
+        "kernel": "fluid_forces",
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "avg_launch_ms": round(k_avg_s * 1e3, 4),
+        "launches": k_launches,
+        "bytes_per_launch": kbytes,
+    }
+    tot = sysm.totals()
+    result = {
+        "metric": "particle-steps/s at 1M SDPD+20k DEM",
+        "value": round(value, 1),
+        "unit": "moving-particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32 pair forces, fp64 state",
+        "data": "synthetic",
+        "config": {
+            "workload": "dam break with rigid particles" + (" (small)" if args.small else ""),
+            "n_fluid": info["n_fluid"], "n_rigid": info["n_rigid"],
+            "n_wall": info["n_inner_wall"] + info["n_outer_wall"], "n_total": n,
+            "kT": args.kT, "dt": p["dt"], "h": p["h"],
+        },
+        "pair_interactions_per_s": round(pair_rate, 1),
+        "roofline": roof,
+        "status_after": {"max_speed": float(tot[8]), "rho_min": float(tot[9]),
+                         "rho_max": float(tot[10])},
+    }
+
+    if args.cpu_seconds > 0:
+        from oracle import oracle as O
+        O.build()
+        o = O.Oracle(p, parts)
+        t0 = time.perf_counter()
+        o.step(1)
+        one = time.perf_counter() - t0
+        more = max(0, int(args.cpu_seconds / max(one, 1e-9)) - 1)
+        more = min(more, 50)
+        t0 = time.perf_counter()
+        if more:
+            o.step(more)
+        t_more = time.perf_counter() - t0
+        steps_cpu = 1 + more
+        t_cpu = one + t_more
+        result["cpu_baseline"] = {
+            "value": round(info["n_moving"] * steps_cpu / t_cpu, 1),
+            "unit": "moving-particle-steps/s",
+            "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"{steps_cpu} step(s) of the same workload from its initial state "
+                      f"({t_cpu:.1f} s, FP64 oracle, OpenMP)",
+        }
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

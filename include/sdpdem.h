@@ -1,0 +1,199 @@
+/*
+ * sdpdem.h -- C ABI of the MI355X (gfx950) SDPD-DEM hot path.
+ *
+ * The library advances the particle system of Tsuzuki, "DEMocritus: an open
+ * source framework for simulating slurry flows using an SDPD-DEM coupled
+ * model" (arXiv 2002.03120): fluid particles under the SDPD+a pair forces
+ * (Sec. 2.1, Eqs. FijC, FijD, FijR, FijT), rigid DEM spheres with
+ * spring-dashpot contacts and lubrication (Secs. 2.2, 2.3), the two-way
+ * drag coupling between them (Sec. 2.4), wall and periodic boundaries
+ * (Sec. 2.5) and the two-pass velocity-Verlet loop of Algorithms 1 and 2.
+ * The calls mirror the paper's program structure (Sec. 3): construct a
+ * particle system from the parameter table and the particles, run the
+ * steps itr_start..itr_stop, read particle fields.
+ *
+ * Conventions shared by every call:
+ *  - Return value: SDPDEM_OK (0) or a negative SDPDEM_E_* code; no call
+ *    throws.  sdpdem_status_string() names a code.
+ *  - Memory: the caller allocates ONE device workspace of
+ *    sdpdem_workspace_bytes() bytes and keeps it alive until
+ *    sdpdem_destroy(); the library never allocates device memory.  Host
+ *    arrays passed in are copied before the call returns.  The
+ *    sdpdem_system handle is a small host object owned by the library.
+ *  - Streams: every call takes a hipStream_t as void*.  sdpdem_step and
+ *    sdpdem_compute_forces only enqueue work, then synchronise once on the
+ *    stream to read the device status word; the read calls synchronise.
+ *  - Order: particles are identified by ids that must be a permutation of
+ *    0..n-1; every array crossing the ABI is in id order, whatever order
+ *    the library keeps internally.
+ *  - Types: 0 fluid, 1 rigid, 2 inner wall, 3 outer wall (Sec. 2.5).
+ */
+#ifndef SDPDEM_H
+#define SDPDEM_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SDPDEM_OK 0
+#define SDPDEM_E_INVALID_ARG (-1)
+#define SDPDEM_E_WORKSPACE_TOO_SMALL (-2)
+#define SDPDEM_E_NBR_OVERFLOW (-3)      /* a neighbour row exceeded max_neighbors */
+#define SDPDEM_E_CONTACT_OVERFLOW (-4)  /* a rigid contact row exceeded max_contacts */
+#define SDPDEM_E_NONFINITE (-5)         /* a position, velocity or spin became non-finite */
+#define SDPDEM_E_OUT_OF_DOMAIN (-6)     /* a particle left the cell grid / wall box */
+#define SDPDEM_E_HIP (-7)               /* a HIP runtime call failed */
+
+enum sdpdem_type {
+  SDPDEM_FLUID = 0,
+  SDPDEM_RIGID = 1,
+  SDPDEM_INNER_WALL = 2,
+  SDPDEM_OUTER_WALL = 3
+};
+
+/* Parameter table (Sec. 3.2, Table ipparam); field order is part of the
+ * ABI.  All lengths, times and masses in the caller's units. */
+typedef struct sdpdem_params {
+  double org[3];           /* --orgx/y/z: lower corner of the domain              */
+  double L[3];             /* --Lx/y/z: domain size; periodic axes need L >= 3h   */
+  int32_t periodic[3];     /* --periodic_type, one flag per axis (8 combinations) */
+  int32_t noslip;          /* --slipcond_type: 1 reverse all of v at a wall face,
+                              0 reverse its normal component only                 */
+  double dx;               /* --dx: lattice spacing; fluid torque lever is dx/2   */
+  double h;                /* --h: support radius of the Lucy kernel (Eq. kernel) */
+  double rho0, p0, alpha, beta_eos; /* Eq. prtcpres: p = p0 (rho/rho0)^alpha - beta */
+  double eta, xi, kBT;     /* shear and bulk viscosity, thermal energy (Sec. 2.1) */
+  double dt;               /* time step                                           */
+  double g[3], f[3];       /* --gx.. and --fx..: body accelerations, summed       */
+  int32_t gravity_type;    /* 0 uniform; 1 sign flipped where x[axis]-org < L/2   */
+  int32_t gravity_axis;    /* axis splitting the two halves for gravity_type 1    */
+  double coeff_c, coeff_d, coeff_r, coeff_t; /* --Coeff_fcij..ftij switches       */
+  double E_dem, nu_dem, mu_fric; /* Young modulus, Poisson ratio, friction (2.2) */
+  double dem_damping;      /* multiplier on c_n, c_t of Eqs. deminputE/F (1)      */
+  double mass_fluid, inertia_fluid; /* --mass --iner of fluid and wall particles  */
+  int32_t enable_kernel_norm;  /* normalise the kernel so a lattice gives rho0     */
+  int32_t enable_pres_smooth;  /* Shepard filter of the pressure                   */
+  int32_t enable_neg_p_clamp;  /* p < 0 -> 0 at free surfaces                      */
+  int32_t enable_lub;          /* lubrication of Eq. lubri                         */
+  double eps_min;          /* lower clamp of the fluid volume fraction            */
+  double lub_gap_min;      /* floor of the lubrication gap                        */
+  int64_t itr_start;       /* first step number (also the noise counter)          */
+  int64_t itr_actv_rigid;  /* rigid particles move and couple from this step on   */
+  uint64_t seed;           /* key of the Philox4x32-10 noise                      */
+  int32_t max_neighbors;   /* capacity of a neighbour row                         */
+  int32_t max_contacts;    /* capacity of a rigid contact row                     */
+} sdpdem_params;
+
+/* Particles, host memory, n rows in any order (ids must cover 0..n-1).
+ * mass/inertia/radius are read for rigid particles only; fluid and wall
+ * particles take mass_fluid and inertia_fluid. */
+typedef struct sdpdem_particles {
+  int64_t n;
+  const int64_t* id;
+  const uint8_t* type;
+  const double* pos;      /* [n*3] */
+  const double* vel;      /* [n*3] */
+  const double* angvel;   /* [n*3] */
+  const double* mass;     /* [n]   */
+  const double* inertia;  /* [n]   */
+  const double* radius;   /* [n]   */
+} sdpdem_particles;
+
+/* Fields readable with sdpdem_read_field: n rows in id order, 1 or 3
+ * doubles per row.  Force fields hold the last force evaluation. */
+enum sdpdem_field {
+  SDPDEM_POS = 0, SDPDEM_VEL, SDPDEM_ANGVEL,
+  SDPDEM_DENS,        /* rho, Eq. compdens (FP64)                         */
+  SDPDEM_PRES,        /* p, Eq. prtcpres (FP64)                           */
+  SDPDEM_PRES_SMOOTH, /* filtered pressure (FP32)                         */
+  SDPDEM_F_SDPD,      /* sum_j F^C+F^D+F^R+F^T, fluid and inner walls     */
+  SDPDEM_F_CD,        /* sum_j F^C+F^D (input of F^PG)                    */
+  SDPDEM_N_SDPD,      /* torque of F^SDPD                                 */
+  SDPDEM_F_DG,        /* drag on rigid particles, Eq. F_fpi_DG            */
+  SDPDEM_F_PG,        /* pressure-gradient force, Eq. F_fpi_PG            */
+  SDPDEM_F_RXN,       /* drag reaction on fluid, Eq. F_fpi_DG_reac        */
+  SDPDEM_F_DEM,       /* contact force on rigid particles (Sec. 2.2)      */
+  SDPDEM_F_LUB,       /* lubrication force (Eq. lubri)                    */
+  SDPDEM_N_DEM,       /* contact torque                                   */
+  SDPDEM_F_TOTAL,     /* total force of Eq. newton1 at the current state  */
+  SDPDEM_N_TOTAL,     /* total torque of Eq. newton2                      */
+  SDPDEM_EPS,         /* fluid volume fraction of rigid particles          */
+  SDPDEM_NUM_FIELDS
+};
+
+/* Kernel ids for sdpdem_set_profiling. */
+enum sdpdem_kernel {
+  SDPDEM_K_NONE = 0, SDPDEM_K_BIN, SDPDEM_K_SORT, SDPDEM_K_PERMUTE,
+  SDPDEM_K_NEIGHBORS_DENSITY, SDPDEM_K_SMOOTH, SDPDEM_K_FLUID_FORCES,
+  SDPDEM_K_FPI_ACTION, SDPDEM_K_FPI_REACTION, SDPDEM_K_DEM, SDPDEM_K_INTEGRATE,
+  SDPDEM_K_RIGID_GRID, SDPDEM_NUM_KERNELS
+};
+
+typedef struct sdpdem_system sdpdem_system;
+
+/* Bytes of device workspace needed for these parameters and particles. */
+int sdpdem_workspace_bytes(const sdpdem_params* params,
+                           const sdpdem_particles* particles, size_t* bytes);
+
+/* Validate, upload and build the system in the caller's workspace.
+ * Rejects (SDPDEM_E_INVALID_ARG): ids not a permutation of 0..n-1, unknown
+ * types, non-positive h, dx, dt, rho0, masses or rigid radii, xi outside
+ * [40 eta/51, 5 eta/3] (gamma^a, gamma^b of Sec. 2.1 must stay >= 0),
+ * periodic L below 3h, max_neighbors/max_contacts < 1. */
+int sdpdem_create(const sdpdem_params* params, const sdpdem_particles* particles,
+                  void* d_workspace, size_t workspace_bytes, void* hip_stream,
+                  sdpdem_system** out);
+
+/* Algorithm 1: nsteps steps of two velocity-Verlet passes each.  Returns the
+ * device status (overflow, non-finite, out of domain) seen at the end. */
+int sdpdem_step(sdpdem_system* sys, int64_t nsteps, void* hip_stream);
+
+/* One evaluation of every force at the current state (Alg. 2), no update. */
+int sdpdem_compute_forces(sdpdem_system* sys, void* hip_stream);
+
+/* Copy a field to host memory (dst holds n*comps doubles, id order). */
+int sdpdem_read_field(sdpdem_system* sys, int field, double* dst, size_t bytes,
+                      void* hip_stream);
+int sdpdem_field_comps(int field);
+
+/* Neighbour sets of the last build as CSR: row i = neighbours of id i,
+ * columns ascending; outer walls have empty rows.  With cols == NULL only
+ * row_ptr (n+1 entries) and *nnz are written. */
+int sdpdem_read_neighbors(sdpdem_system* sys, int64_t* row_ptr, int32_t* cols,
+                          int64_t cap, int64_t* nnz, void* hip_stream);
+
+/* Rigid contact table: pairs (i < j) and the tangential displacement held
+ * by i (the row of j holds its negative).  pairs == NULL: count only. */
+int sdpdem_read_contacts(sdpdem_system* sys, int32_t* pairs, double* delta_t,
+                         int64_t cap, int64_t* n_contacts, void* hip_stream);
+/* Replace the contact table (restart); each pair fills both rows. */
+int sdpdem_load_contacts(sdpdem_system* sys, const int32_t* pairs,
+                         const double* delta_t, int64_t n_contacts,
+                         void* hip_stream);
+
+/* FP64 totals over all non-outer-wall particles:
+ * out = [P(3), L(3) about the origin, KE_trans, KE_rot, max|v|, min rho,
+ *        max rho, total mass, step, 0, 0, 0].  Synchronises. */
+int sdpdem_totals(sdpdem_system* sys, double out[16], void* hip_stream);
+
+int64_t sdpdem_get_step(const sdpdem_system* sys);
+
+/* Diagnostics: out = [n, n_rigid, cells x, y, z, rigid cells x, y, z,
+ * max neighbour count of the last build, pairs of the last build, 0...]. */
+int sdpdem_info(sdpdem_system* sys, int64_t out[16], void* hip_stream);
+
+/* Time every launch of one kernel (enum sdpdem_kernel) with HIP events on
+ * the launch stream; SDPDEM_K_NONE switches timing off.  sdpdem_kernel_time
+ * returns the accumulated milliseconds and launch count and resets them. */
+int sdpdem_set_profiling(sdpdem_system* sys, int kernel);
+int sdpdem_kernel_time(sdpdem_system* sys, double* total_ms, int64_t* launches);
+
+void sdpdem_destroy(sdpdem_system* sys);
+const char* sdpdem_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,912 @@
+// sdpdem_api.hip -- host side of the C ABI declared in include/sdpdem.h:
+// validation, workspace layout, the per-step launch sequence of
+// Algorithms 1 and 2, read-out and diagnostics.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <utility>
+#include <vector>
+
+#include "sdpdem_internal.h"
+
+using namespace sdpdem;
+
+struct sdpdem_system {
+  sdpdem_params P;
+  Dev d;
+  D4* pos[2];
+  D4* vel[2];
+  D4* om[2];
+  uint8_t* type[2];
+  int* gid[2];
+  int cur = 0;
+  int* ct_cnt[2];
+  int* ct_partner[2];
+  double* ct_dt[2];
+  int ct_cur = 0;
+  int* block_sums;
+  int* rblock_sums;
+  double* field_buf;
+  double* tot_part;
+  double* tot_out;
+  int64_t step = 0;
+  bool cache_valid = false;
+  bool noise = false;
+  std::vector<int> h_gid2slot;
+  // profiling
+  int prof_kernel = SDPDEM_K_NONE;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  size_t ev_used = 0;
+  double prof_ms = 0.0;
+  int64_t prof_n = 0;
+};
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct Bump {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
+    off += std::max<size_t>(count, 1) * sizeof(T);
+    return p;
+  }
+};
+
+bool valid_params(const sdpdem_params* P) {
+  if (!P) return false;
+  if (!(P->h > 0) || !(P->dx > 0) || !(P->dt > 0) || !(P->rho0 > 0) || !(P->mass_fluid > 0) ||
+      !(P->inertia_fluid > 0) || !(P->kBT >= 0) || !(P->eta >= 0))
+    return false;
+  if (P->max_neighbors < 1 || P->max_contacts < 1) return false;
+  if (P->xi < 40.0 * P->eta / 51.0 || P->xi > 5.0 * P->eta / 3.0) return false;
+  if (P->gravity_axis < 0 || P->gravity_axis > 2) return false;
+  for (int a = 0; a < 3; ++a) {
+    if (!(P->L[a] > 0)) return false;
+    if (P->periodic[a] && P->L[a] < 3.0 * P->h * (1.0 + 1e-6)) return false;
+  }
+  return true;
+}
+
+bool valid_particles(const sdpdem_particles* q, std::vector<int>* slot_of, int* nrig,
+                     double* rmax) {
+  if (!q || q->n < 1 || q->n > (int64_t)1 << 30 || !q->id || !q->type || !q->pos || !q->vel ||
+      !q->angvel || !q->mass || !q->inertia || !q->radius)
+    return false;
+  int64_t n = q->n;
+  std::vector<char> seen((size_t)n, 0);
+  int nr = 0;
+  double rm = 0.0;
+  for (int64_t k = 0; k < n; ++k) {
+    int64_t g = q->id[k];
+    if (g < 0 || g >= n || seen[(size_t)g] || q->type[k] > SDPDEM_OUTER_WALL) return false;
+    seen[(size_t)g] = 1;
+    if (q->type[k] == SDPDEM_RIGID) {
+      if (!(q->mass[k] > 0) || !(q->inertia[k] > 0) || !(q->radius[k] > 0)) return false;
+      ++nr;
+      rm = std::max(rm, q->radius[k]);
+    }
+  }
+  if (slot_of) {
+    std::vector<uint8_t> t_by_id((size_t)n);
+    for (int64_t k = 0; k < n; ++k) t_by_id[(size_t)q->id[k]] = q->type[k];
+    slot_of->assign((size_t)n, -1);
+    int s = 0;
+    for (int64_t g = 0; g < n; ++g)
+      if (t_by_id[(size_t)g] == SDPDEM_RIGID) (*slot_of)[(size_t)g] = s++;
+  }
+  *nrig = nr;
+  *rmax = rm;
+  return true;
+}
+
+// Cell grid: periodic axes are split into floor(L/cs0) equal cells; wall
+// axes cover the domain and every particle with one cell of slack.
+bool make_grid(const sdpdem_params& P, const sdpdem_particles& q, double cs0, Grid& g) {
+  double total = 1.0;
+  for (int a = 0; a < 3; ++a) {
+    g.per[a] = P.periodic[a] ? 1 : 0;
+    if (g.per[a]) {
+      int nc = (int)std::floor(P.L[a] / cs0);
+      if (nc < 1) nc = 1;
+      g.lo[a] = P.org[a];
+      g.nc[a] = nc;
+      g.cs[a] = P.L[a] / nc;
+    } else {
+      double mn = P.org[a], mx = P.org[a] + P.L[a];
+      for (int64_t k = 0; k < q.n; ++k) {
+        double x = q.pos[3 * k + a];
+        if (!std::isfinite(x)) return false;
+        mn = std::min(mn, x);
+        mx = std::max(mx, x);
+      }
+      g.lo[a] = mn - cs0;
+      g.cs[a] = cs0;
+      double ncd = std::floor((mx - g.lo[a]) / cs0) + 2.0;
+      if (ncd > 1e8) return false;
+      g.nc[a] = (int)ncd;
+    }
+    g.inv_cs[a] = 1.0 / g.cs[a];
+    total *= g.nc[a];
+  }
+  if (total > 2.0e9) return false;
+  g.ncells = g.nc[0] * g.nc[1] * g.nc[2];
+  return true;
+}
+
+double lucy(double r, double h) {
+  if (r >= h) return 0.0;
+  double q = r / h, om = 1.0 - q;
+  return 105.0 / (16.0 * kPi * h * h * h) * (1.0 + 3.0 * q) * om * om * om;
+}
+
+// sum of W(|k| dx) over the simple cubic lattice, the particle itself included
+double lattice_sum(double h, double dx) {
+  int K = (int)std::ceil(h / dx) + 1;
+  double s = 0.0;
+  for (int a = -K; a <= K; ++a)
+    for (int b = -K; b <= K; ++b)
+      for (int c = -K; c <= K; ++c) s += lucy(dx * std::sqrt((double)(a * a + b * b + c * c)), h);
+  return s;
+}
+
+struct Sizes {
+  int64_t n, npad, nr;
+  int maxn, maxc;
+  Grid g, rg;
+};
+
+// Carve the workspace (base == nullptr: only measure it).
+size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
+  Bump b{base};
+  size_t n = (size_t)z.n, np = (size_t)z.npad, nr = (size_t)z.nr;
+  size_t nc = (size_t)z.g.ncells, rnc = (size_t)z.rg.ncells;
+  D4 *pos0 = b.take<D4>(np), *pos1 = b.take<D4>(np);
+  D4 *vel0 = b.take<D4>(np), *vel1 = b.take<D4>(np);
+  D4 *om0 = b.take<D4>(np), *om1 = b.take<D4>(np);
+  uint8_t *ty0 = b.take<uint8_t>(np), *ty1 = b.take<uint8_t>(np);
+  int *gid0 = b.take<int>(np), *gid1 = b.take<int>(np);
+  uint32_t* key = b.take<uint32_t>(np);
+  int* count = b.take<int>(nc);
+  int* cstart = b.take<int>(nc + 1);
+  int* cursor = b.take<int>(nc);
+  int* perm = b.take<int>(np);
+  int* bsum = b.take<int>((size_t)scan_block_sums_size((int)nc) + 1);
+  int* nbr = b.take<int>((size_t)z.maxn * np);
+  int* nbr_cnt = b.take<int>(np);
+  double* rho = b.take<double>(np);
+  double* p = b.take<double>(np);
+  float* ps = b.take<float>(np);
+  F4* vrec = b.take<F4>(np);
+  F4* wrec = b.take<F4>(np);
+  float* fout = b.take<float>(12 * np);
+  int* gid2slot = b.take<int>(np);
+  int* rig_sorted = b.take<int>(nr);
+  int* rig_gid = b.take<int>(nr);
+  double* f_dg = b.take<double>(3 * nr);
+  double* f_pg = b.take<double>(3 * nr);
+  double* f_dem = b.take<double>(3 * nr);
+  double* f_lub = b.take<double>(3 * nr);
+  double* n_dem = b.take<double>(3 * nr);
+  double* eps = b.take<double>(nr);
+  double* omega = b.take<double>(nr);
+  uint32_t* rkey = b.take<uint32_t>(nr);
+  int* rcount = b.take<int>(rnc);
+  int* rstart = b.take<int>(rnc + 1);
+  int* rcursor = b.take<int>(rnc);
+  int* ritems = b.take<int>(nr);
+  int* rbsum = b.take<int>((size_t)scan_block_sums_size((int)rnc) + 1);
+  int *ctc0 = b.take<int>(nr), *ctc1 = b.take<int>(nr);
+  int *ctp0 = b.take<int>(nr * z.maxc), *ctp1 = b.take<int>(nr * z.maxc);
+  double *ctd0 = b.take<double>(3 * nr * z.maxc), *ctd1 = b.take<double>(3 * nr * z.maxc);
+  int* status = b.take<int>(64);
+  double* field_buf = b.take<double>(3 * n);
+  double* tot_part = b.take<double>(13 * (size_t)totals_partial_blocks((int)n));
+  double* tot_out = b.take<double>(16);
+  size_t total = b.off + 256;
+  if (s) {
+    s->pos[0] = pos0;
+    s->pos[1] = pos1;
+    s->vel[0] = vel0;
+    s->vel[1] = vel1;
+    s->om[0] = om0;
+    s->om[1] = om1;
+    s->type[0] = ty0;
+    s->type[1] = ty1;
+    s->gid[0] = gid0;
+    s->gid[1] = gid1;
+    s->ct_cnt[0] = ctc0;
+    s->ct_cnt[1] = ctc1;
+    s->ct_partner[0] = ctp0;
+    s->ct_partner[1] = ctp1;
+    s->ct_dt[0] = ctd0;
+    s->ct_dt[1] = ctd1;
+    s->block_sums = bsum;
+    s->rblock_sums = rbsum;
+    s->field_buf = field_buf;
+    s->tot_part = tot_part;
+    s->tot_out = tot_out;
+    Dev& d = s->d;
+    d.key = key;
+    d.count = count;
+    d.cstart = cstart;
+    d.cursor = cursor;
+    d.perm = perm;
+    d.nbr = nbr;
+    d.nbr_cnt = nbr_cnt;
+    d.rho = rho;
+    d.p = p;
+    d.ps = ps;
+    d.vrec = vrec;
+    d.wrec = wrec;
+    d.fout = fout;
+    d.gid2slot = gid2slot;
+    d.rig_sorted = rig_sorted;
+    d.rig_gid = rig_gid;
+    d.f_dg = f_dg;
+    d.f_pg = f_pg;
+    d.f_dem = f_dem;
+    d.f_lub = f_lub;
+    d.n_dem = n_dem;
+    d.eps = eps;
+    d.omega = omega;
+    d.rkey = rkey;
+    d.rcount = rcount;
+    d.rstart = rstart;
+    d.rcursor = rcursor;
+    d.ritems = ritems;
+    d.status = status;
+  }
+  return total;
+}
+
+bool plan(const sdpdem_params* P, const sdpdem_particles* q, Sizes& z,
+          std::vector<int>* slot_of) {
+  if (!valid_params(P)) return false;
+  int nr = 0;
+  double rmax = 0.0;
+  if (!valid_particles(q, slot_of, &nr, &rmax)) return false;
+  z.n = q->n;
+  z.npad = (q->n + 63) / 64 * 64;
+  z.nr = nr;
+  z.maxn = P->max_neighbors;
+  z.maxc = P->max_contacts;
+  if (!make_grid(*P, *q, P->h * (1.0 + 1e-6), z.g)) return false;
+  for (int a = 0; a < 3; ++a)
+    if (P->periodic[a] && z.g.nc[a] < 3) return false;
+  double rcs = std::max(2.0 * rmax + P->h, P->h) * (1.0 + 1e-6);
+  if (!make_grid(*P, *q, rcs, z.rg)) return false;
+  return true;
+}
+
+void fill_constants(sdpdem_system* s, const Sizes& z) {
+  const sdpdem_params& P = s->P;
+  Dev& d = s->d;
+  d.n = (int)z.n;
+  d.nr = (int)z.nr;
+  d.npad = (int)z.npad;
+  d.maxn = z.maxn;
+  d.maxc = z.maxc;
+  d.have_rxn = 0;
+  for (int a = 0; a < 3; ++a) {
+    d.org[a] = P.org[a];
+    d.L[a] = P.L[a];
+    d.halfL[a] = 0.5 * P.L[a];
+    d.per[a] = P.periodic[a] ? 1 : 0;
+    d.body[a] = P.g[a] + P.f[a];
+  }
+  d.noslip = P.noslip;
+  d.h = P.h;
+  d.h2 = P.h * P.h;
+  d.dx = P.dx;
+  d.lever = 0.5 * P.dx;
+  d.rho0 = P.rho0;
+  d.p0 = P.p0;
+  d.alpha = P.alpha;
+  d.beta = P.beta_eos;
+  d.clamp = P.enable_neg_p_clamp ? 1 : 0;
+  d.smooth = P.enable_pres_smooth ? 1 : 0;
+  double pref = P.p0 * std::pow(1.0, P.alpha) - P.beta_eos;
+  if (d.clamp && pref < 0.0) pref = 0.0;
+  d.p_ref = pref;
+  d.m_f = P.mass_fluid;
+  d.I_f = P.inertia_fluid;
+  d.cw_m = P.enable_kernel_norm ? P.rho0 / lattice_sum(P.h, P.dx) : P.mass_fluid;
+  d.w_norm = 105.0 / (16.0 * kPi * P.h * P.h * P.h);
+  d.W0 = d.w_norm;
+  d.eta = P.eta;
+  d.dt = P.dt;
+  d.gtype = P.gravity_type;
+  d.gaxis = P.gravity_axis;
+  d.E = P.E_dem;
+  d.nu = P.nu_dem;
+  d.mu = P.mu_fric;
+  d.damp = P.dem_damping;
+  d.eps_min = P.eps_min;
+  d.lub_gap_min = P.lub_gap_min;
+  d.lub = P.enable_lub ? 1 : 0;
+  d.hf = (float)P.h;
+  d.inv_hf = (float)(1.0 / P.h);
+  d.cFf = (float)(315.0 / (4.0 * kPi * std::pow(P.h, 5)));
+  d.CAf = (float)(20.0 * P.eta / 3.0 - 4.0 * P.xi);
+  d.CBf = (float)(17.0 * P.xi - 40.0 * P.eta / 3.0);
+  d.kTf = (float)P.kBT;
+  d.inv_sqrt_dtf = (float)(1.0 / std::sqrt(P.dt));
+  d.cC = (float)P.coeff_c;
+  d.cD = (float)P.coeff_d;
+  d.cR = (float)P.coeff_r;
+  d.cT = (float)P.coeff_t;
+  d.leverf = (float)(0.5 * P.dx);
+  d.key0 = (uint32_t)(P.seed & 0xffffffffu);
+  d.key1 = (uint32_t)(P.seed >> 32);
+  d.g = z.g;
+  d.rg = z.rg;
+  s->noise = P.kBT > 0.0 && P.coeff_t != 0.0;
+}
+
+void bind_current(sdpdem_system* s) {
+  Dev& d = s->d;
+  d.pos = s->pos[s->cur];
+  d.vel = s->vel[s->cur];
+  d.om = s->om[s->cur];
+  d.type = s->type[s->cur];
+  d.gid = s->gid[s->cur];
+  d.ct_cnt = s->ct_cnt[s->ct_cur];
+  d.ct_partner = s->ct_partner[s->ct_cur];
+  d.ct_dt = s->ct_dt[s->ct_cur];
+}
+
+// ---- profiling: bracket the launches of one kernel with events ----------
+
+void prof_flush(sdpdem_system* s) {
+  if (s->ev_used == 0) return;
+  hipEventSynchronize(s->ev[s->ev_used - 1].second);
+  for (size_t k = 0; k < s->ev_used; ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, s->ev[k].first, s->ev[k].second) == hipSuccess) {
+      s->prof_ms += ms;
+      s->prof_n += 1;
+    }
+  }
+  s->ev_used = 0;
+}
+
+struct Prof {
+  sdpdem_system* s;
+  hipStream_t st;
+  bool on;
+  Prof(sdpdem_system* s_, int kid, hipStream_t st_) : s(s_), st(st_), on(s_->prof_kernel == kid) {
+    if (!on) return;
+    if (s->ev_used == s->ev.size()) {
+      if (s->ev.size() < 4096) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess) {
+          on = false;
+          return;
+        }
+        if (hipEventCreate(&b) != hipSuccess) {
+          hipEventDestroy(a);
+          on = false;
+          return;
+        }
+        s->ev.emplace_back(a, b);
+      } else {
+        prof_flush(s);
+      }
+    }
+    hipEventRecord(s->ev[s->ev_used].first, st);
+  }
+  ~Prof() {
+    if (!on) return;
+    hipEventRecord(s->ev[s->ev_used].second, st);
+    s->ev_used += 1;
+  }
+};
+
+// ---- the per-step launch sequence ----------------------------------------
+
+// (a1)-(a4): sort by cell, permute the state, neighbours + density +
+// pressure, smoothing, and the rigid grid.
+void run_build(sdpdem_system* s, hipStream_t st) {
+  Dev& d = s->d;
+  const int nc = d.g.ncells;
+  {
+    Prof pr(s, SDPDEM_K_BIN, st);
+    launch_fill_i32(d.count, 0, (size_t)nc, st);
+    launch_bin(d, st);
+  }
+  {
+    Prof pr(s, SDPDEM_K_SORT, st);
+    launch_scan(d.count, nc, d.cstart, d.cursor, s->block_sums, st);
+    launch_scatter(d.key, d.n, d.cursor, d.perm, st);
+    launch_cell_sort(d.cstart, nc, d.perm, s->gid[s->cur], st);
+  }
+  const int src = s->cur;
+  s->cur ^= 1;
+  bind_current(s);
+  {
+    Prof pr(s, SDPDEM_K_PERMUTE, st);
+    launch_permute(d, s->pos[src], s->vel[src], s->om[src], s->type[src], s->gid[src], st);
+  }
+  {
+    Prof pr(s, SDPDEM_K_NEIGHBORS_DENSITY, st);
+    launch_build_density(d, st);
+  }
+  {
+    Prof pr(s, SDPDEM_K_SMOOTH, st);
+    launch_smooth(d, st);
+  }
+  if (d.nr > 0) {
+    Prof pr(s, SDPDEM_K_RIGID_GRID, st);
+    launch_fill_i32(d.rcount, 0, (size_t)d.rg.ncells, st);
+    launch_bin_rigid(d, st);
+    launch_scan(d.rcount, d.rg.ncells, d.rstart, d.rcursor, s->rblock_sums, st);
+    launch_scatter(d.rkey, d.nr, d.rcursor, d.ritems, st);
+    launch_cell_sort(d.rstart, d.rg.ncells, d.ritems, nullptr, st);
+  }
+}
+
+bool rigid_active(const sdpdem_system* s) {
+  return s->d.nr > 0 && s->step >= s->P.itr_actv_rigid;
+}
+
+// (a5)-(a9): one force evaluation (Alg. 2) and, if asked, the update.
+void run_pass(sdpdem_system* s, int velver, int commit, bool integrate, hipStream_t st) {
+  Dev& d = s->d;
+  {
+    Prof pr(s, SDPDEM_K_FLUID_FORCES, st);
+    launch_fluid_forces(d, (uint32_t)s->step, s->noise, st);
+  }
+  const bool act = rigid_active(s);
+  if (act) {
+    {
+      Prof pr(s, SDPDEM_K_FPI_ACTION, st);
+      launch_fpi_action(d, st);
+    }
+    {
+      Prof pr(s, SDPDEM_K_FPI_REACTION, st);
+      launch_fpi_reaction(d, st);
+    }
+    {
+      Prof pr(s, SDPDEM_K_DEM, st);
+      int nx = s->ct_cur ^ 1;
+      launch_dem(d, commit, s->ct_cnt[nx], s->ct_partner[nx], s->ct_dt[nx], st);
+    }
+    if (commit) {
+      s->ct_cur ^= 1;
+      bind_current(s);
+    }
+    d.have_rxn = 1;
+  } else {
+    d.have_rxn = 0;
+  }
+  if (integrate) {
+    Prof pr(s, SDPDEM_K_INTEGRATE, st);
+    launch_integrate(d, velver, act ? 1 : 0, st);
+  }
+}
+
+int status_code(int bits) {
+  if (bits & ST_NONFINITE) return SDPDEM_E_NONFINITE;
+  if (bits & ST_NBR_OVERFLOW) return SDPDEM_E_NBR_OVERFLOW;
+  if (bits & ST_CONTACT_OVERFLOW) return SDPDEM_E_CONTACT_OVERFLOW;
+  if (bits & ST_OUT_OF_DOMAIN) return SDPDEM_E_OUT_OF_DOMAIN;
+  return SDPDEM_OK;
+}
+
+int sync_status(sdpdem_system* s, hipStream_t st) {
+  int bits = 0;
+  if (hipMemcpyAsync(&bits, s->d.status, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
+    return SDPDEM_E_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return SDPDEM_E_HIP;
+  if (hipGetLastError() != hipSuccess) return SDPDEM_E_HIP;
+  return status_code(bits);
+}
+
+}  // namespace
+
+namespace sdpdem {
+
+__global__ void k_nbr_cols(Dev d, int k0, int kn, int* out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  int cnt = d.nbr_cnt[i];
+  const size_t np = (size_t)d.npad;
+  for (int k = 0; k < kn; ++k) {
+    int kk = k0 + k;
+    out[(size_t)k * np + i] = kk < cnt ? d.gid[d.nbr[(size_t)kk * np + i]] : -1;
+  }
+}
+
+void launch_nbr_cols(const Dev& d, int k0, int kn, int* out, hipStream_t st) {
+  k_nbr_cols<<<(d.n + 255) / 256, 256, 0, st>>>(d, k0, kn, out);
+}
+
+}  // namespace sdpdem
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+int sdpdem_field_comps(int field) {
+  switch (field) {
+    case SDPDEM_DENS:
+    case SDPDEM_PRES:
+    case SDPDEM_PRES_SMOOTH:
+    case SDPDEM_EPS:
+      return 1;
+    default:
+      return (field >= 0 && field < SDPDEM_NUM_FIELDS) ? 3 : 0;
+  }
+}
+
+int sdpdem_workspace_bytes(const sdpdem_params* params, const sdpdem_particles* particles,
+                           size_t* bytes) {
+  if (!bytes) return SDPDEM_E_INVALID_ARG;
+  Sizes z;
+  if (!plan(params, particles, z, nullptr)) return SDPDEM_E_INVALID_ARG;
+  *bytes = layout(z, nullptr, nullptr);
+  return SDPDEM_OK;
+}
+
+int sdpdem_create(const sdpdem_params* params, const sdpdem_particles* q, void* d_workspace,
+                  size_t workspace_bytes, void* hip_stream, sdpdem_system** out) {
+  if (!out) return SDPDEM_E_INVALID_ARG;
+  *out = nullptr;
+  Sizes z;
+  std::vector<int> slot_of;
+  if (!plan(params, q, z, &slot_of)) return SDPDEM_E_INVALID_ARG;
+  size_t need = layout(z, nullptr, nullptr);
+  if (!d_workspace) return SDPDEM_E_INVALID_ARG;
+  if (workspace_bytes < need) return SDPDEM_E_WORKSPACE_TOO_SMALL;
+  char* base = reinterpret_cast<char*>(((uintptr_t)d_workspace + 255) & ~(uintptr_t)255);
+  if ((size_t)(base - (char*)d_workspace) + need - 256 > workspace_bytes)
+    return SDPDEM_E_WORKSPACE_TOO_SMALL;
+  sdpdem_system* s = new (std::nothrow) sdpdem_system();
+  if (!s) return SDPDEM_E_INVALID_ARG;
+  s->P = *params;
+  layout(z, base, s);
+  fill_constants(s, z);
+  s->step = params->itr_start;
+  s->cur = 0;
+  s->ct_cur = 0;
+  s->h_gid2slot = slot_of;
+  bind_current(s);
+  hipStream_t st = (hipStream_t)hip_stream;
+  // stage the particles in id order
+  const int64_t n = q->n;
+  std::vector<D4> hp((size_t)n), hv((size_t)n), hw((size_t)n);
+  std::vector<uint8_t> ht((size_t)n);
+  std::vector<int> hg((size_t)n), hrg((size_t)z.nr, 0), hsort((size_t)z.nr, 0);
+  for (int64_t k = 0; k < n; ++k) {
+    int64_t g = q->id[k];
+    uint8_t t = q->type[k];
+    bool rig = t == SDPDEM_RIGID;
+    hp[(size_t)g] = D4{q->pos[3 * k], q->pos[3 * k + 1], q->pos[3 * k + 2],
+                       rig ? q->radius[k] : 0.5 * params->dx};
+    hv[(size_t)g] = D4{q->vel[3 * k], q->vel[3 * k + 1], q->vel[3 * k + 2],
+                       rig ? q->mass[k] : params->mass_fluid};
+    hw[(size_t)g] = D4{q->angvel[3 * k], q->angvel[3 * k + 1], q->angvel[3 * k + 2],
+                       rig ? q->inertia[k] : params->inertia_fluid};
+    ht[(size_t)g] = t;
+    hg[(size_t)g] = (int)g;
+    if (rig) {
+      int sl = slot_of[(size_t)g];
+      hrg[(size_t)sl] = (int)g;
+      hsort[(size_t)sl] = (int)g;
+    }
+  }
+  Dev& d = s->d;
+  bool ok = true;
+  ok &= hipMemcpyAsync(s->pos[0], hp.data(), sizeof(D4) * n, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipMemcpyAsync(s->vel[0], hv.data(), sizeof(D4) * n, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipMemcpyAsync(s->om[0], hw.data(), sizeof(D4) * n, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipMemcpyAsync(s->type[0], ht.data(), n, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipMemcpyAsync(s->gid[0], hg.data(), sizeof(int) * n, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipMemcpyAsync(d.gid2slot, slot_of.data(), sizeof(int) * n, hipMemcpyHostToDevice, st) == hipSuccess;
+  if (z.nr) {
+    ok &= hipMemcpyAsync(d.rig_gid, hrg.data(), sizeof(int) * z.nr, hipMemcpyHostToDevice, st) == hipSuccess;
+    ok &= hipMemcpyAsync(d.rig_sorted, hsort.data(), sizeof(int) * z.nr, hipMemcpyHostToDevice, st) == hipSuccess;
+  }
+  launch_fill_i32(s->ct_cnt[0], 0, (size_t)z.nr, st);
+  launch_fill_i32(s->ct_cnt[1], 0, (size_t)z.nr, st);
+  launch_fill_i32(d.status, 0, 64, st);
+  launch_fill_i32(reinterpret_cast<int*>(d.fout), 0, 12 * (size_t)z.npad, st);
+  launch_fill_i32(d.nbr_cnt, 0, (size_t)z.npad, st);
+  launch_fill_f64(d.f_dg, 0.0, 3 * (size_t)z.nr, st);
+  launch_fill_f64(d.f_pg, 0.0, 3 * (size_t)z.nr, st);
+  launch_fill_f64(d.f_dem, 0.0, 3 * (size_t)z.nr, st);
+  launch_fill_f64(d.f_lub, 0.0, 3 * (size_t)z.nr, st);
+  launch_fill_f64(d.n_dem, 0.0, 3 * (size_t)z.nr, st);
+  launch_fill_f64(d.eps, 0.0, (size_t)z.nr, st);
+  launch_fill_f64(d.omega, 0.0, (size_t)z.nr, st);
+  launch_fill_f64(d.rho, params->rho0, (size_t)z.npad, st);
+  launch_fill_f64(d.p, 0.0, (size_t)z.npad, st);
+  ok &= hipStreamSynchronize(st) == hipSuccess;
+  ok &= hipGetLastError() == hipSuccess;
+  if (!ok) {
+    delete s;
+    return SDPDEM_E_HIP;
+  }
+  *out = s;
+  return SDPDEM_OK;
+}
+
+int sdpdem_step(sdpdem_system* s, int64_t nsteps, void* hip_stream) {
+  if (!s || nsteps < 0) return SDPDEM_E_INVALID_ARG;
+  hipStream_t st = (hipStream_t)hip_stream;
+  for (int64_t it = 0; it < nsteps; ++it) {
+    if (!s->cache_valid) run_build(s, st);
+    run_pass(s, 1, 0, true, st);
+    // positions moved: sort, neighbours, density and smoothing at x(n+1);
+    // they stay valid for the first pass of the next step
+    run_build(s, st);
+    run_pass(s, 2, 1, true, st);
+    s->cache_valid = true;
+    s->step += 1;
+  }
+  return sync_status(s, st);
+}
+
+int sdpdem_compute_forces(sdpdem_system* s, void* hip_stream) {
+  if (!s) return SDPDEM_E_INVALID_ARG;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (!s->cache_valid) {
+    run_build(s, st);
+    s->cache_valid = true;
+  }
+  run_pass(s, 1, 0, false, st);
+  return sync_status(s, st);
+}
+
+int sdpdem_read_field(sdpdem_system* s, int field, double* dst, size_t bytes, void* hip_stream) {
+  if (!s || !dst) return SDPDEM_E_INVALID_ARG;
+  int comps = sdpdem_field_comps(field);
+  if (comps == 0) return SDPDEM_E_INVALID_ARG;
+  size_t need = (size_t)s->d.n * comps * sizeof(double);
+  if (bytes < need) return SDPDEM_E_INVALID_ARG;
+  hipStream_t st = (hipStream_t)hip_stream;
+  launch_read_field(s->d, field, rigid_active(s) ? 1 : 0, s->field_buf, st);
+  if (hipMemcpyAsync(dst, s->field_buf, need, hipMemcpyDeviceToHost, st) != hipSuccess)
+    return SDPDEM_E_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return SDPDEM_E_HIP;
+  return hipGetLastError() == hipSuccess ? SDPDEM_OK : SDPDEM_E_HIP;
+}
+
+int sdpdem_read_neighbors(sdpdem_system* s, int64_t* row_ptr, int32_t* cols, int64_t cap,
+                          int64_t* nnz, void* hip_stream) {
+  if (!s || !row_ptr || !nnz) return SDPDEM_E_INVALID_ARG;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int n = s->d.n;
+  const size_t np = (size_t)s->d.npad;
+  std::vector<int> cnt((size_t)n), gid((size_t)n);
+  if (hipMemcpyAsync(cnt.data(), s->d.nbr_cnt, sizeof(int) * n, hipMemcpyDeviceToHost, st) !=
+          hipSuccess ||
+      hipMemcpyAsync(gid.data(), s->d.gid, sizeof(int) * n, hipMemcpyDeviceToHost, st) !=
+          hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return SDPDEM_E_HIP;
+  std::vector<int64_t> rowlen((size_t)n + 1, 0);
+  int kmax = 0;
+  for (int i = 0; i < n; ++i) {
+    rowlen[(size_t)gid[(size_t)i]] = cnt[(size_t)i];
+    kmax = std::max(kmax, cnt[(size_t)i]);
+  }
+  row_ptr[0] = 0;
+  for (int g = 0; g < n; ++g) row_ptr[g + 1] = row_ptr[g] + rowlen[(size_t)g];
+  *nnz = row_ptr[n];
+  if (!cols) return SDPDEM_OK;
+  if (cap < *nnz) return SDPDEM_E_INVALID_ARG;
+  // columns in chunks that fit the field buffer (3n doubles = 6n ints)
+  int* dbuf = reinterpret_cast<int*>(s->field_buf);
+  const int per = std::max(1, (int)std::min<size_t>(6, (6 * (size_t)n) / np));
+  std::vector<int> hb(per * np);
+  for (int k0 = 0; k0 < kmax; k0 += per) {
+    int kn = std::min(per, kmax - k0);
+    launch_nbr_cols(s->d, k0, kn, dbuf, st);
+    if (hipMemcpyAsync(hb.data(), dbuf, sizeof(int) * kn * np, hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return SDPDEM_E_HIP;
+    for (int i = 0; i < n; ++i) {
+      int g = gid[(size_t)i];
+      for (int k = 0; k < kn; ++k) {
+        int v = hb[(size_t)k * np + i];
+        if (v >= 0) cols[row_ptr[g] + k0 + k] = v;
+      }
+    }
+  }
+  for (int g = 0; g < n; ++g) std::sort(cols + row_ptr[g], cols + row_ptr[g + 1]);
+  return SDPDEM_OK;
+}
+
+int sdpdem_read_contacts(sdpdem_system* s, int32_t* pairs, double* delta_t, int64_t cap,
+                         int64_t* n_contacts, void* hip_stream) {
+  if (!s || !n_contacts) return SDPDEM_E_INVALID_ARG;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int nr = s->d.nr, mc = s->d.maxc;
+  std::vector<int> cnt((size_t)nr), part((size_t)nr * mc), rg((size_t)nr);
+  std::vector<double> dt((size_t)nr * mc * 3);
+  if (nr) {
+    if (hipMemcpyAsync(cnt.data(), s->d.ct_cnt, sizeof(int) * nr, hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(part.data(), s->d.ct_partner, sizeof(int) * nr * mc, hipMemcpyDeviceToHost,
+                       st) != hipSuccess ||
+        hipMemcpyAsync(dt.data(), s->d.ct_dt, sizeof(double) * nr * mc * 3, hipMemcpyDeviceToHost,
+                       st) != hipSuccess ||
+        hipMemcpyAsync(rg.data(), s->d.rig_gid, sizeof(int) * nr, hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return SDPDEM_E_HIP;
+  }
+  struct Row {
+    int i, j;
+    double d[3];
+  };
+  std::vector<Row> rows;
+  for (int sl = 0; sl < nr; ++sl) {
+    int gi = rg[(size_t)sl];
+    for (int c = 0; c < cnt[(size_t)sl] && c < mc; ++c) {
+      int gj = part[(size_t)sl * mc + c];
+      if (gj <= gi) continue;
+      Row r{gi, gj, {dt[((size_t)sl * mc + c) * 3], dt[((size_t)sl * mc + c) * 3 + 1],
+                     dt[((size_t)sl * mc + c) * 3 + 2]}};
+      rows.push_back(r);
+    }
+  }
+  std::sort(rows.begin(), rows.end(),
+            [](const Row& a, const Row& b) { return a.i != b.i ? a.i < b.i : a.j < b.j; });
+  *n_contacts = (int64_t)rows.size();
+  if (!pairs || !delta_t) return SDPDEM_OK;
+  if (cap < (int64_t)rows.size()) return SDPDEM_E_INVALID_ARG;
+  for (size_t m = 0; m < rows.size(); ++m) {
+    pairs[2 * m] = rows[m].i;
+    pairs[2 * m + 1] = rows[m].j;
+    for (int a = 0; a < 3; ++a) delta_t[3 * m + a] = rows[m].d[a];
+  }
+  return SDPDEM_OK;
+}
+
+int sdpdem_load_contacts(sdpdem_system* s, const int32_t* pairs, const double* delta_t,
+                         int64_t n_contacts, void* hip_stream) {
+  if (!s || n_contacts < 0 || (n_contacts > 0 && (!pairs || !delta_t)))
+    return SDPDEM_E_INVALID_ARG;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int nr = s->d.nr, mc = s->d.maxc, n = s->d.n;
+  std::vector<std::vector<std::pair<int, std::array<double, 3>>>> rows((size_t)nr);
+  for (int64_t m = 0; m < n_contacts; ++m) {
+    int i = pairs[2 * m], j = pairs[2 * m + 1];
+    if (i < 0 || j < 0 || i >= n || j >= n || i == j) return SDPDEM_E_INVALID_ARG;
+    int si = s->h_gid2slot[(size_t)i], sj = s->h_gid2slot[(size_t)j];
+    if (si < 0 || sj < 0) return SDPDEM_E_INVALID_ARG;
+    std::array<double, 3> a{delta_t[3 * m], delta_t[3 * m + 1], delta_t[3 * m + 2]};
+    std::array<double, 3> b{-a[0], -a[1], -a[2]};
+    rows[(size_t)si].push_back({j, a});
+    rows[(size_t)sj].push_back({i, b});
+  }
+  std::vector<int> cnt((size_t)nr, 0), part((size_t)nr * mc, 0);
+  std::vector<double> dt((size_t)nr * mc * 3, 0.0);
+  for (int sl = 0; sl < nr; ++sl) {
+    auto& r = rows[(size_t)sl];
+    if ((int)r.size() > mc) return SDPDEM_E_CONTACT_OVERFLOW;
+    std::sort(r.begin(), r.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+    cnt[(size_t)sl] = (int)r.size();
+    for (size_t c = 0; c < r.size(); ++c) {
+      part[(size_t)sl * mc + c] = r[c].first;
+      for (int a = 0; a < 3; ++a) dt[((size_t)sl * mc + c) * 3 + a] = r[c].second[a];
+    }
+  }
+  if (nr) {
+    if (hipMemcpyAsync(s->d.ct_cnt, cnt.data(), sizeof(int) * nr, hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(s->d.ct_partner, part.data(), sizeof(int) * nr * mc, hipMemcpyHostToDevice,
+                       st) != hipSuccess ||
+        hipMemcpyAsync(s->d.ct_dt, dt.data(), sizeof(double) * nr * mc * 3, hipMemcpyHostToDevice,
+                       st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return SDPDEM_E_HIP;
+  }
+  return SDPDEM_OK;
+}
+
+int sdpdem_totals(sdpdem_system* s, double out[16], void* hip_stream) {
+  if (!s || !out) return SDPDEM_E_INVALID_ARG;
+  hipStream_t st = (hipStream_t)hip_stream;
+  launch_totals(s->d, s->tot_part, s->tot_out, st);
+  double t[16] = {0};
+  if (hipMemcpyAsync(t, s->tot_out, sizeof(double) * 13, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return SDPDEM_E_HIP;
+  for (int k = 0; k < 12; ++k) out[k] = t[k];
+  out[12] = (double)s->step;
+  out[13] = out[14] = out[15] = 0.0;
+  return SDPDEM_OK;
+}
+
+int64_t sdpdem_get_step(const sdpdem_system* s) { return s ? s->step : -1; }
+
+int sdpdem_info(sdpdem_system* s, int64_t out[16], void* hip_stream) {
+  if (!s || !out) return SDPDEM_E_INVALID_ARG;
+  for (int k = 0; k < 16; ++k) out[k] = 0;
+  out[0] = s->d.n;
+  out[1] = s->d.nr;
+  for (int a = 0; a < 3; ++a) {
+    out[2 + a] = s->d.g.nc[a];
+    out[5 + a] = s->d.rg.nc[a];
+  }
+  std::vector<int> cnt((size_t)s->d.n);
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (hipMemcpyAsync(cnt.data(), s->d.nbr_cnt, sizeof(int) * s->d.n, hipMemcpyDeviceToHost, st) !=
+          hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return SDPDEM_E_HIP;
+  int64_t mx = 0, tot = 0;
+  for (int v : cnt) {
+    mx = std::max<int64_t>(mx, v);
+    tot += v;
+  }
+  out[8] = mx;
+  out[9] = tot;
+  return SDPDEM_OK;
+}
+
+int sdpdem_set_profiling(sdpdem_system* s, int kernel) {
+  if (!s || kernel < 0 || kernel >= SDPDEM_NUM_KERNELS) return SDPDEM_E_INVALID_ARG;
+  prof_flush(s);
+  s->prof_kernel = kernel;
+  s->prof_ms = 0.0;
+  s->prof_n = 0;
+  return SDPDEM_OK;
+}
+
+int sdpdem_kernel_time(sdpdem_system* s, double* total_ms, int64_t* launches) {
+  if (!s || !total_ms || !launches) return SDPDEM_E_INVALID_ARG;
+  prof_flush(s);
+  *total_ms = s->prof_ms;
+  *launches = s->prof_n;
+  s->prof_ms = 0.0;
+  s->prof_n = 0;
+  return SDPDEM_OK;
+}
+
+void sdpdem_destroy(sdpdem_system* s) {
+  if (!s) return;
+  prof_flush(s);
+  for (auto& e : s->ev) {
+    hipEventDestroy(e.first);
+    hipEventDestroy(e.second);
+  }
+  delete s;
+}
+
+const char* sdpdem_status_string(int status) {
+  switch (status) {
+    case SDPDEM_OK:
+      return "ok";
+    case SDPDEM_E_INVALID_ARG:
+      return "invalid argument";
+    case SDPDEM_E_WORKSPACE_TOO_SMALL:
+      return "workspace too small";
+    case SDPDEM_E_NBR_OVERFLOW:
+      return "a neighbour row exceeded max_neighbors";
+    case SDPDEM_E_CONTACT_OVERFLOW:
+      return "a rigid contact row exceeded max_contacts";
+    case SDPDEM_E_NONFINITE:
+      return "non-finite position, velocity or spin";
+    case SDPDEM_E_OUT_OF_DOMAIN:
+      return "a particle left the domain";
+    case SDPDEM_E_HIP:
+      return "HIP runtime error";
+    default:
+      return "unknown status";
+  }
+}
+
+}  // extern "C"

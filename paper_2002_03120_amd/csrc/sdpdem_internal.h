@@ -1,0 +1,138 @@
+// sdpdem_internal.h -- device data layout and kernel launchers of the
+// SDPD-DEM library (shared by the kernel and host translation units).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "sdpdem.h"
+
+namespace sdpdem {
+
+enum : uint8_t { T_FLUID = 0, T_RIGID = 1, T_INNER = 2, T_OUTER = 3 };
+
+// status bits raised by kernels (sticky until the system is destroyed)
+enum : int {
+  ST_NBR_OVERFLOW = 1,
+  ST_CONTACT_OVERFLOW = 2,
+  ST_NONFINITE = 4,
+  ST_OUT_OF_DOMAIN = 8
+};
+
+struct __align__(32) D4 {
+  double x, y, z, w;
+};
+struct __align__(16) F4 {
+  float x, y, z, w;
+};
+
+// A uniform cell grid.  Periodic axes span [org, org+L) with nc >= 3 cells;
+// wall axes span the particle bounding box plus one cell of slack.
+struct Grid {
+  double lo[3];
+  double cs[3];
+  double inv_cs[3];
+  int nc[3];
+  int per[3];
+  int ncells;
+};
+
+// Everything a kernel reads, passed by value.  Particle arrays are in the
+// current cell-sorted order; rigid arrays are indexed by rigid slot (the
+// rank of the rigid particle's id among all rigid ids).
+struct Dev {
+  int n, nr, npad, maxn, maxc;
+  int have_rxn;  // the drag reaction of the last evaluation is valid
+  // constants
+  double org[3], L[3], halfL[3];
+  int per[3];
+  int noslip;
+  double h, h2, dx, lever;
+  double rho0, p0, alpha, beta, p_ref, m_f, I_f;
+  double cw_m;    // C_W * m_f, density per unit kernel sum
+  double w_norm;  // 105 / (16 pi h^3)
+  double W0;      // W(0)
+  double eta, dt, body[3];
+  int gtype, gaxis;
+  double E, nu, mu, damp, eps_min, lub_gap_min;
+  int lub;
+  int clamp;   // negative pressure -> 0
+  int smooth;  // Shepard filter of the pressure
+  // single-precision pair constants
+  float hf, inv_hf, cFf, CAf, CBf, kTf, inv_sqrt_dtf, cC, cD, cR, cT, leverf;
+  uint32_t key0, key1;
+  Grid g, rg;
+  // particles (current buffer)
+  D4* pos;  // x, y, z, radius (lever for fluid and walls)
+  D4* vel;  // vx, vy, vz, mass
+  D4* om;   // wx, wy, wz, inertia
+  uint8_t* type;
+  int* gid;
+  // sort scratch
+  uint32_t* key;
+  int* count;
+  int* cstart;  // ncells + 1
+  int* cursor;
+  int* perm;
+  // neighbours and fields
+  int* nbr;  // [maxn * npad], column k of row i at k*npad + i
+  int* nbr_cnt;
+  double* rho;
+  double* p;
+  float* ps;
+  F4* vrec;  // FP32 vx, vy, vz, p~/d^2
+  F4* wrec;  // FP32 wx, wy, wz, d = rho/m_f
+  float* fout;  // 12 planes of npad: F_sdpd(3) N_sdpd(3) F_cd(3) F_rxn(3)
+  // rigid
+  int* gid2slot;
+  int* rig_sorted;
+  int* rig_gid;
+  double* f_dg;
+  double* f_pg;
+  double* f_dem;
+  double* f_lub;
+  double* n_dem;
+  double* eps;
+  double* omega;
+  uint32_t* rkey;
+  int* rcount;
+  int* rstart;
+  int* rcursor;
+  int* ritems;
+  int* ct_cnt;      // current contact table
+  int* ct_partner;  // partner id
+  double* ct_dt;
+  int* status;
+};
+
+// host-side launchers (sdpdem_kernels.hip)
+void launch_fill_i32(int* a, int v, size_t count, hipStream_t st);
+void launch_fill_f64(double* a, double v, size_t count, hipStream_t st);
+void launch_bin(const Dev& d, hipStream_t st);
+void launch_bin_rigid(const Dev& d, hipStream_t st);
+// exclusive scan of count[0..m) into start[0..m] and cursor[0..m)
+void launch_scan(const int* count, int m, int* start, int* cursor, int* block_sums,
+                 hipStream_t st);
+int scan_block_sums_size(int m);
+void launch_scatter(const uint32_t* key, int n, int* cursor, int* perm, hipStream_t st);
+// sort each cell's slice of perm by sortkey[perm[k]] (sortkey == null: by value)
+void launch_cell_sort(const int* start, int ncells, int* perm, const int* sortkey,
+                      hipStream_t st);
+void launch_permute(const Dev& d, const D4* spos, const D4* svel, const D4* som,
+                    const uint8_t* stype, const int* sgid, hipStream_t st);
+void launch_build_density(const Dev& d, hipStream_t st);
+void launch_smooth(const Dev& d, hipStream_t st);
+void launch_fluid_forces(const Dev& d, uint32_t step, bool noise, hipStream_t st);
+void launch_fpi_action(const Dev& d, hipStream_t st);
+void launch_fpi_reaction(const Dev& d, hipStream_t st);
+void launch_dem(const Dev& d, int commit, int* nxt_cnt, int* nxt_partner, double* nxt_dt,
+                hipStream_t st);
+void launch_integrate(const Dev& d, int velver, int rigid_active, hipStream_t st);
+void launch_read_field(const Dev& d, int field, int rigid_active, double* out, hipStream_t st);
+int totals_partial_blocks(int n);
+void launch_totals(const Dev& d, double* partial, double* out, hipStream_t st);
+// neighbour columns k0..k0+kn-1 as ids (-1 past a row's end)
+void launch_nbr_cols(const Dev& d, int k0, int kn, int* out, hipStream_t st);
+
+}  // namespace sdpdem

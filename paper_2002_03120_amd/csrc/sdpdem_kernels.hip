@@ -1,0 +1,1220 @@
+// sdpdem_kernels.hip -- gfx950 kernels of the SDPD-DEM per-step path.
+//
+// Layout: particles live in cell-sorted order (counting sort of linear cell
+// keys, ties broken by id), so every neighbour gather touches a compact
+// region that the XCD's L2 holds.  Per-particle kernels map blocks to XCDs
+// in contiguous chunks (a dispatch sends block b to XCD b % 8).  Sums are
+// gathers, never atomics on floating point, so every run is bit-for-bit
+// repeatable.
+//
+// Precision: positions, velocities, spins, density, pressure, the
+// fluid-particle coupling, DEM and the integrator in FP64; the SDPD pair
+// forces (Sec. 2.1) in FP32 with FP32 per-particle accumulation, their
+// separation vectors taken as FP64 differences rounded once.
+#include <cmath>
+
+#include "sdpdem_internal.h"
+
+namespace sdpdem {
+
+static constexpr int BS = 256;
+static constexpr double PI = 3.14159265358979323846;
+
+static inline int nblocks(size_t n, int bs = BS) {
+  size_t b = (n + bs - 1) / bs;
+  b = (b + 7) / 8 * 8;  // a multiple of the 8 XCDs
+  return (int)(b > 0 ? b : 8);
+}
+
+// Block index -> particle chunk, contiguous per XCD.
+__device__ __forceinline__ int xcd_tid() {
+  unsigned nb = gridDim.x, b = blockIdx.x;
+  unsigned lb = (nb % 8u == 0u) ? (b % 8u) * (nb / 8u) + (b / 8u) : b;
+  return (int)(lb * blockDim.x + threadIdx.x);
+}
+
+__device__ __forceinline__ double min_img(double d, int per, double L, double halfL) {
+  if (per) {
+    if (d > halfL)
+      d = d - L;
+    else if (d < -halfL)
+      d = d + L;
+  }
+  return d;
+}
+
+// r^2 = (dx*dx + dy*dy) + dz*dz with every product and sum rounded (no
+// contraction), so that neighbour membership is the same bit for bit as a
+// plain double-precision evaluation of the definition.
+__device__ __forceinline__ double r2_exact(double a, double b, double c) {
+#pragma clang fp contract(off)
+  double t = a * a;
+  double u = b * b;
+  double v = c * c;
+  return (t + u) + v;
+}
+
+__device__ __forceinline__ int cell_coord(double x, const Grid& g, int a, int* oob) {
+  double f = floor((x - g.lo[a]) * g.inv_cs[a]);
+  int n = g.nc[a];
+  if (g.per[a]) {
+    f = f - (double)n * floor(f / (double)n);
+    if (!(f >= 0.0 && f < (double)n)) {
+      *oob = 1;
+      return 0;
+    }
+    return (int)f;
+  }
+  if (!(f >= 0.0)) {
+    *oob = 1;
+    return 0;
+  }
+  if (f >= (double)n) {
+    *oob = 1;
+    return n - 1;
+  }
+  return (int)f;
+}
+
+__device__ __forceinline__ int cell_index(const Grid& g, int cx, int cy, int cz) {
+  return (cz * g.nc[1] + cy) * g.nc[0] + cx;
+}
+
+// wrap (periodic) or reject (wall) a neighbour cell coordinate
+__device__ __forceinline__ bool wrap_axis(int& c, int n, int per) {
+  if (c < 0) {
+    if (!per) return false;
+    c += n;
+  } else if (c >= n) {
+    if (!per) return false;
+    c -= n;
+  }
+  return true;
+}
+
+// Lucy kernel with support H (Eq. kernel), double precision
+__device__ __forceinline__ double lucy_w(double r, double H) {
+  if (r >= H) return 0.0;
+  double q = r / H;
+  double om = 1.0 - q;
+  return 105.0 / (16.0 * PI * H * H * H) * (1.0 + 3.0 * q) * om * om * om;
+}
+
+// ---------------------------------------------------------------------------
+// generic helpers
+
+__global__ void k_fill_i32(int* a, int v, size_t count) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) a[i] = v;
+}
+__global__ void k_fill_f64(double* a, double v, size_t count) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) a[i] = v;
+}
+
+void launch_fill_i32(int* a, int v, size_t count, hipStream_t st) {
+  if (!count) return;
+  k_fill_i32<<<(unsigned)((count + BS - 1) / BS), BS, 0, st>>>(a, v, count);
+}
+void launch_fill_f64(double* a, double v, size_t count, hipStream_t st) {
+  if (!count) return;
+  k_fill_f64<<<(unsigned)((count + BS - 1) / BS), BS, 0, st>>>(a, v, count);
+}
+
+// ---------------------------------------------------------------------------
+// (a1) binning and counting sort
+
+__global__ __launch_bounds__(BS) void k_bin(Dev d) {
+  int i = xcd_tid();
+  if (i >= d.n) return;
+  D4 p = d.pos[i];
+  int oob = 0;
+  int cx = cell_coord(p.x, d.g, 0, &oob);
+  int cy = cell_coord(p.y, d.g, 1, &oob);
+  int cz = cell_coord(p.z, d.g, 2, &oob);
+  if (oob) atomicOr(d.status, ST_OUT_OF_DOMAIN);
+  int c = cell_index(d.g, cx, cy, cz);
+  d.key[i] = (uint32_t)c;
+  atomicAdd(&d.count[c], 1);
+}
+
+void launch_bin(const Dev& d, hipStream_t st) {
+  k_bin<<<nblocks(d.n), BS, 0, st>>>(d);
+}
+
+__global__ __launch_bounds__(BS) void k_bin_rigid(Dev d) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= d.nr) return;
+  D4 p = d.pos[d.rig_sorted[s]];
+  int oob = 0;
+  int cx = cell_coord(p.x, d.rg, 0, &oob);
+  int cy = cell_coord(p.y, d.rg, 1, &oob);
+  int cz = cell_coord(p.z, d.rg, 2, &oob);
+  if (oob) atomicOr(d.status, ST_OUT_OF_DOMAIN);
+  int c = cell_index(d.rg, cx, cy, cz);
+  d.rkey[s] = (uint32_t)c;
+  atomicAdd(&d.rcount[c], 1);
+}
+
+void launch_bin_rigid(const Dev& d, hipStream_t st) {
+  if (d.nr == 0) return;
+  k_bin_rigid<<<(d.nr + BS - 1) / BS, BS, 0, st>>>(d);
+}
+
+// Block-wide exclusive scan of one int per thread (wave64 shuffles + LDS).
+__device__ int block_exclusive_scan(int v, int* lds, int* total) {
+  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) lds[wid] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int w = 0; w < BS / 64; ++w) {
+      int t = lds[w];
+      lds[w] = acc;
+      acc += t;
+    }
+    lds[BS / 64] = acc;
+  }
+  __syncthreads();
+  int res = x - v + lds[wid];
+  *total = lds[BS / 64];
+  __syncthreads();
+  return res;
+}
+
+static constexpr int SCAN_ITEMS = 8;
+static constexpr int SCAN_TILE = BS * SCAN_ITEMS;
+
+__global__ __launch_bounds__(BS) void k_scan_reduce(const int* in, int m, int* block_sums) {
+  __shared__ int lds[BS / 64 + 1];
+  int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    int idx = base + k;
+    if (idx < m) s += in[idx];
+  }
+  int tot;
+  block_exclusive_scan(s, lds, &tot);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+// exclusive scan of the block sums in one block, chunk by chunk
+__global__ __launch_bounds__(BS) void k_scan_blocksums(int* block_sums, int nb) {
+  __shared__ int lds[BS / 64 + 1];
+  int carry = 0;
+  for (int base = 0; base < nb; base += BS) {
+    int idx = base + (int)threadIdx.x;
+    int v = idx < nb ? block_sums[idx] : 0;
+    int tot;
+    int ex = block_exclusive_scan(v, lds, &tot);
+    if (idx < nb) block_sums[idx] = ex + carry;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) block_sums[nb] = carry;
+}
+
+__global__ __launch_bounds__(BS) void k_scan_apply(const int* in, int m, const int* block_sums,
+                                                  int nb, int* start, int* cursor) {
+  __shared__ int lds[BS / 64 + 1];
+  int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+  int v[SCAN_ITEMS];
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    int idx = base + k;
+    v[k] = idx < m ? in[idx] : 0;
+    s += v[k];
+  }
+  int tot;
+  int ex = block_exclusive_scan(s, lds, &tot) + block_sums[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    int idx = base + k;
+    if (idx < m) {
+      start[idx] = ex;
+      cursor[idx] = ex;
+    }
+    ex += v[k];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) start[m] = block_sums[nb];
+}
+
+int scan_block_sums_size(int m) { return (m + SCAN_TILE - 1) / SCAN_TILE + 1; }
+
+void launch_scan(const int* count, int m, int* start, int* cursor, int* block_sums,
+                 hipStream_t st) {
+  int nb = (m + SCAN_TILE - 1) / SCAN_TILE;
+  if (nb < 1) nb = 1;
+  k_scan_reduce<<<nb, BS, 0, st>>>(count, m, block_sums);
+  k_scan_blocksums<<<1, BS, 0, st>>>(block_sums, nb);
+  k_scan_apply<<<nb, BS, 0, st>>>(count, m, block_sums, nb, start, cursor);
+}
+
+__global__ __launch_bounds__(BS) void k_scatter(const uint32_t* key, int n, int* cursor,
+                                               int* perm) {
+  int i = xcd_tid();
+  if (i >= n) return;
+  int slot = atomicAdd(&cursor[key[i]], 1);
+  perm[slot] = i;
+}
+
+void launch_scatter(const uint32_t* key, int n, int* cursor, int* perm, hipStream_t st) {
+  if (n == 0) return;
+  k_scatter<<<nblocks(n), BS, 0, st>>>(key, n, cursor, perm);
+}
+
+// Insertion sort of each cell's slice: ties of the counting sort are
+// broken by a fixed key (the particle id), making the order deterministic.
+__global__ __launch_bounds__(BS) void k_cell_sort(const int* start, int ncells, int* perm,
+                                                 const int* sortkey) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  int lo = start[c], hi = start[c + 1];
+  for (int a = lo + 1; a < hi; ++a) {
+    int v = perm[a];
+    int kv = sortkey ? sortkey[v] : v;
+    int b = a - 1;
+    while (b >= lo) {
+      int w = perm[b];
+      int kw = sortkey ? sortkey[w] : w;
+      if (kw <= kv) break;
+      perm[b + 1] = w;
+      --b;
+    }
+    perm[b + 1] = v;
+  }
+}
+
+void launch_cell_sort(const int* start, int ncells, int* perm, const int* sortkey,
+                      hipStream_t st) {
+  if (ncells == 0) return;
+  k_cell_sort<<<(ncells + BS - 1) / BS, BS, 0, st>>>(start, ncells, perm, sortkey);
+}
+
+__global__ __launch_bounds__(BS) void k_permute(Dev d, const D4* spos, const D4* svel,
+                                               const D4* som, const uint8_t* stype,
+                                               const int* sgid) {
+  int i = xcd_tid();
+  if (i >= d.n) return;
+  int o = d.perm[i];
+  d.pos[i] = spos[o];
+  d.vel[i] = svel[o];
+  d.om[i] = som[o];
+  uint8_t t = stype[o];
+  int g = sgid[o];
+  d.type[i] = t;
+  d.gid[i] = g;
+  if (t == T_RIGID) d.rig_sorted[d.gid2slot[g]] = i;
+}
+
+void launch_permute(const Dev& d, const D4* spos, const D4* svel, const D4* som,
+                    const uint8_t* stype, const int* sgid, hipStream_t st) {
+  k_permute<<<nblocks(d.n), BS, 0, st>>>(d, spos, svel, som, stype, sgid);
+}
+
+// ---------------------------------------------------------------------------
+// (a2)+(a3) neighbour list fused with the density summation (Eq. compdens)
+// and the equation of state (Eq. prtcpres).  One thread per particle; the
+// 27-cell stencil is walked row by row, a row of three cells being one
+// contiguous slice of the sorted arrays unless it wraps.
+
+__global__ __launch_bounds__(BS) void k_build_density(Dev d) {
+  int i = xcd_tid();
+  if (i >= d.n) return;
+  uint8_t ti = d.type[i];
+  if (ti == T_OUTER) {
+    d.nbr_cnt[i] = 0;
+    d.rho[i] = d.rho0;
+    d.p[i] = d.p_ref;
+    return;
+  }
+  D4 pi = d.pos[i];
+  int oob = 0;
+  int cx = cell_coord(pi.x, d.g, 0, &oob);
+  int cy = cell_coord(pi.y, d.g, 1, &oob);
+  int cz = cell_coord(pi.z, d.g, 2, &oob);
+  const double h = d.h, h2 = d.h2;
+  double acc = d.W0;
+  int cnt = 0;
+  const size_t npad = (size_t)d.npad;
+  for (int dz = -1; dz <= 1; ++dz) {
+    int z = cz + dz;
+    if (!wrap_axis(z, d.g.nc[2], d.g.per[2])) continue;
+    for (int dy = -1; dy <= 1; ++dy) {
+      int y = cy + dy;
+      if (!wrap_axis(y, d.g.nc[1], d.g.per[1])) continue;
+      // up to three x cells; a slice [c0, c1] of consecutive cells
+      int xs[3];
+      int nx = 0;
+      for (int dxx = -1; dxx <= 1; ++dxx) {
+        int x = cx + dxx;
+        if (wrap_axis(x, d.g.nc[0], d.g.per[0])) xs[nx++] = x;
+      }
+      int k = 0;
+      while (k < nx) {
+        int x0 = xs[k], x1 = xs[k];
+        while (k + 1 < nx && xs[k + 1] == x1 + 1) {
+          ++k;
+          x1 = xs[k];
+        }
+        ++k;
+        int jb = d.cstart[cell_index(d.g, x0, y, z)];
+        int je = d.cstart[cell_index(d.g, x1, y, z) + 1];
+        for (int j = jb; j < je; ++j) {
+          if (j == i) continue;
+          D4 pj = d.pos[j];
+          double ex = min_img(pi.x - pj.x, d.per[0], d.L[0], d.halfL[0]);
+          double ey = min_img(pi.y - pj.y, d.per[1], d.L[1], d.halfL[1]);
+          double ez = min_img(pi.z - pj.z, d.per[2], d.L[2], d.halfL[2]);
+          double r2 = r2_exact(ex, ey, ez);
+          if (r2 < h2) {
+            if (cnt < d.maxn) d.nbr[(size_t)cnt * npad + i] = j;
+            ++cnt;
+            double q = sqrt(r2) / h;
+            double om = 1.0 - q;
+            acc += d.w_norm * (1.0 + 3.0 * q) * om * om * om;
+          }
+        }
+      }
+    }
+  }
+  if (cnt > d.maxn) {
+    atomicOr(d.status, ST_NBR_OVERFLOW);
+    cnt = d.maxn;
+  }
+  d.nbr_cnt[i] = cnt;
+  double rho = d.cw_m * acc;
+  double p = d.p0 * pow(rho / d.rho0, d.alpha) - d.beta;
+  if (d.clamp && p < 0.0) p = 0.0;  // free-surface correction (Sec. 2.5)
+  d.rho[i] = rho;
+  d.p[i] = p;
+}
+
+void launch_build_density(const Dev& d, hipStream_t st) {
+  k_build_density<<<nblocks(d.n), BS, 0, st>>>(d);
+}
+
+// (a4) Shepard filter of the pressure and the FP32 pair records:
+// v, p~/d^2 and spin, d = rho/m_f.
+__global__ __launch_bounds__(BS) void k_smooth(Dev d) {
+  int i = xcd_tid();
+  if (i >= d.n) return;
+  uint8_t ti = d.type[i];
+  double pi = d.p[i];
+  double ps = pi;
+  if (d.smooth && ti != T_OUTER) {
+    D4 xi = d.pos[i];
+    double num = pi * d.W0, den = d.W0;
+    int cnt = d.nbr_cnt[i];
+    const size_t npad = (size_t)d.npad;
+    for (int k = 0; k < cnt; ++k) {
+      int j = d.nbr[(size_t)k * npad + i];
+      D4 xj = d.pos[j];
+      double ex = min_img(xi.x - xj.x, d.per[0], d.L[0], d.halfL[0]);
+      double ey = min_img(xi.y - xj.y, d.per[1], d.L[1], d.halfL[1]);
+      double ez = min_img(xi.z - xj.z, d.per[2], d.L[2], d.halfL[2]);
+      double q = sqrt(ex * ex + ey * ey + ez * ez) / d.h;
+      double om = fmax(1.0 - q, 0.0);
+      double w = d.w_norm * (1.0 + 3.0 * q) * om * om * om;
+      num += d.p[j] * w;
+      den += w;
+    }
+    ps = num / den;
+  }
+  d.ps[i] = (float)ps;
+  double di = d.rho[i] / d.m_f;
+  D4 v = d.vel[i], w = d.om[i];
+  F4 vr, wr;
+  vr.x = (float)v.x;
+  vr.y = (float)v.y;
+  vr.z = (float)v.z;
+  vr.w = (float)(ps / (di * di));
+  wr.x = (float)w.x;
+  wr.y = (float)w.y;
+  wr.z = (float)w.z;
+  wr.w = (float)di;
+  d.vrec[i] = vr;
+  d.wrec[i] = wr;
+}
+
+void launch_smooth(const Dev& d, hipStream_t st) {
+  k_smooth<<<nblocks(d.n), BS, 0, st>>>(d);
+}
+
+// ---------------------------------------------------------------------------
+// (a5) SDPD+a pair forces, Eqs. FijC, FijD, FijR, FijT.
+
+// Philox4x32-10 (Salmon et al., SC'11): two 32x32 -> 64-bit products per
+// round with the published multipliers, Weyl key increments between rounds.
+__device__ __forceinline__ void philox10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
+                                         uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+__device__ __forceinline__ float u01(uint32_t x) {
+  return (float)((x >> 8) + 1u) * 5.9604644775390625e-8f;  // (0, 1], exact
+}
+
+// nine standard normals of the unordered pair {a, b} at a step; the tenth
+// Box-Muller output is not used
+__device__ __forceinline__ void pair_normals(uint32_t a, uint32_t b, uint32_t step, uint32_t k0,
+                                             uint32_t k1, float z[9]) {
+  uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+  float u[12];
+#pragma unroll
+  for (uint32_t blk = 0; blk < 3; ++blk) {
+    uint32_t c0 = lo, c1 = hi, c2 = step, c3 = blk;
+    philox10(c0, c1, c2, c3, k0, k1);
+    u[4 * blk + 0] = u01(c0);
+    u[4 * blk + 1] = u01(c1);
+    u[4 * blk + 2] = u01(c2);
+    u[4 * blk + 3] = u01(c3);
+  }
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    float rad = sqrtf(-2.0f * logf(u[2 * m]));
+    float sn, cs;
+    sincospif(2.0f * u[2 * m + 1], &sn, &cs);
+    if (2 * m < 9) z[2 * m] = rad * cs;
+    if (2 * m + 1 < 9) z[2 * m + 1] = rad * sn;
+  }
+}
+
+template <bool NOISE>
+__global__ __launch_bounds__(BS) void k_fluid_forces(Dev d, uint32_t step) {
+  int i = xcd_tid();
+  if (i >= d.n) return;
+  uint8_t ti = d.type[i];
+  float F0 = 0.f, F1 = 0.f, F2 = 0.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, N0 = 0.f, N1 = 0.f, N2 = 0.f;
+  if (ti == T_FLUID || ti == T_INNER) {
+    const D4 pi = d.pos[i];
+    const F4 vi = d.vrec[i];
+    const F4 wi = d.wrec[i];
+    const uint32_t gi = NOISE ? (uint32_t)d.gid[i] : 0u;
+    const int cnt = d.nbr_cnt[i];
+    const size_t npad = (size_t)d.npad;
+    for (int k = 0; k < cnt; ++k) {
+      const int j = d.nbr[(size_t)k * npad + i];
+      const D4 pj = d.pos[j];
+      const F4 vj = d.vrec[j];
+      const F4 wj = d.wrec[j];
+      const double dx_ = min_img(pi.x - pj.x, d.per[0], d.L[0], d.halfL[0]);
+      const double dy_ = min_img(pi.y - pj.y, d.per[1], d.L[1], d.halfL[1]);
+      const double dz_ = min_img(pi.z - pj.z, d.per[2], d.L[2], d.halfL[2]);
+      const double r2d = dx_ * dx_ + dy_ * dy_ + dz_ * dz_;
+      const float rx = (float)dx_, ry = (float)dy_, rz = (float)dz_;
+      const float r = sqrtf((float)r2d);
+      const float inv_r = 1.0f / r;
+      const float ex = rx * inv_r, ey = ry * inv_r, ez = rz * inv_r;
+      // 1 - r/h = (h^2 - r^2) / (h (h + r)), the difference taken in FP64 so
+      // that pairs close to the cut-off keep full FP32 relative precision
+      const float omq = fmaxf((float)(d.h2 - r2d) * d.inv_hf / (d.hf + r), 0.0f);
+      const float Fk = d.cFf * omq * omq;  // F(r) = -W'(r)/r, Eq. F
+      // Pair force = along-e part + transverse part.  The torque takes the
+      // transverse part only: e x e = 0, and dropping the (often dominant)
+      // pressure term keeps the FP32 cross product free of cancellation.
+      // conservative force, Eq. FijC: (p_i/d_i^2 + p_j/d_j^2) F r_ij
+      const float pc = d.cC * ((vi.w + vj.w) * Fk);
+      // dissipative force, Eq. FijD: -ga v_ij - (ga + 2 gb)/3 (e.v_ij) e
+      const float fdd = Fk / (wi.w * wj.w);
+      const float ga = d.CAf * fdd, gb = d.CBf * fdd;
+      const float vx = vi.x - vj.x, vy = vi.y - vj.y, vz = vi.z - vj.z;
+      const float ev = ex * vx + ey * vy + ez * vz;
+      const float cde = -d.cD * (ga + 2.0f * gb) * ev * (1.0f / 3.0f);
+      const float cdv = -d.cD * ga;
+      float tx = cdv * vx, ty = cdv * vy, tz = cdv * vz;  // transverse-capable part
+      const float cx_ = pc * rx + cde * ex + tx;
+      const float cy_ = pc * ry + cde * ey + ty;
+      const float cz_ = pc * rz + cde * ez + tz;
+      C0 += cx_;
+      C1 += cy_;
+      C2 += cz_;
+      float fx = cx_, fy = cy_, fz = cz_;
+      // rotational force, Eq. FijR: -gamma^a (r_ij / 2) x (w_i + w_j)
+      const float sx = wi.x + wj.x, sy = wi.y + wj.y, sz = wi.z + wj.z;
+      const float gr = -d.cR * ga * 0.5f;
+      const float rrx = gr * (ry * sz - rz * sy);
+      const float rry = gr * (rz * sx - rx * sz);
+      const float rrz = gr * (rx * sy - ry * sx);
+      fx += rrx;
+      fy += rry;
+      fz += rrz;
+      tx += rrx;
+      ty += rry;
+      tz += rrz;
+      if (NOISE) {
+        // thermal force, Eq. FijT with dW^S = sym(dW) - tr(dW)/3
+        float z[9];
+        pair_normals(gi, (uint32_t)d.gid[j], step, d.key0, d.key1, z);
+        const float sa = 2.0f * sqrtf(d.kTf * ga);
+        const float sb = 2.0f * sqrtf(d.kTf * gb);
+        const float tr3 = (z[0] + z[4] + z[8]) * (1.0f / 3.0f);
+        const float s01 = 0.5f * (z[1] + z[3]), s02 = 0.5f * (z[2] + z[6]),
+                    s12 = 0.5f * (z[5] + z[7]);
+        const float se0 = (z[0] - tr3) * ex + s01 * ey + s02 * ez;
+        const float se1 = s01 * ex + (z[4] - tr3) * ey + s12 * ez;
+        const float se2 = s02 * ex + s12 * ey + (z[8] - tr3) * ez;
+        const float ca = d.cT * d.inv_sqrt_dtf * sa;
+        const float cb = d.cT * d.inv_sqrt_dtf * sb * tr3;
+        fx += ca * se0 + cb * ex;
+        fy += ca * se1 + cb * ey;
+        fz += ca * se2 + cb * ez;
+        tx += ca * se0;
+        ty += ca * se1;
+        tz += ca * se2;
+      }
+      F0 += fx;
+      F1 += fy;
+      F2 += fz;
+      // torque with the lever dx/2 along -e_ij (Sec. 2.6)
+      N0 -= d.leverf * (ey * tz - ez * ty);
+      N1 -= d.leverf * (ez * tx - ex * tz);
+      N2 -= d.leverf * (ex * ty - ey * tx);
+    }
+  }
+  const size_t np = (size_t)d.npad;
+  float* o = d.fout;
+  o[0 * np + i] = F0;
+  o[1 * np + i] = F1;
+  o[2 * np + i] = F2;
+  o[3 * np + i] = N0;
+  o[4 * np + i] = N1;
+  o[5 * np + i] = N2;
+  o[6 * np + i] = C0;
+  o[7 * np + i] = C1;
+  o[8 * np + i] = C2;
+}
+
+void launch_fluid_forces(const Dev& d, uint32_t step, bool noise, hipStream_t st) {
+  if (noise)
+    k_fluid_forces<true><<<nblocks(d.n), BS, 0, st>>>(d, step);
+  else
+    k_fluid_forces<false><<<nblocks(d.n), BS, 0, st>>>(d, step);
+}
+
+// ---------------------------------------------------------------------------
+// (a6) fluid-particle action: one wavefront per rigid particle gathers the
+// fluid inside H_s = R_s + h (Sec. 2.4): Omega_s, the W-weighted fluid
+// velocity, the W-weighted F^C + F^D of the neighbours and the number of
+// other rigid centres inside H_s, then forms eps, F^DG and F^PG.
+
+__device__ double drag_b(double eps, double dv, double dd, double rho, double mu) {
+  // beta / (1 - eps) of the Ergun (eps <= 0.8) and Wen-Yu branches
+  if (eps <= 0.8) return 150.0 * mu * (1.0 - eps) / (eps * dd * dd) + 1.75 * rho * dv / dd;
+  double re = rho * dd * eps * dv / mu;
+  double cd_dv = re <= 1000.0 ? 24.0 * mu * (1.0 + 0.15 * pow(re, 0.687)) / (rho * dd * eps)
+                              : 0.44 * dv;
+  return 0.75 * cd_dv * eps * rho * pow(eps, -2.65) / dd;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// cells within reach of a sphere of radius H around a cell coordinate
+__device__ __forceinline__ void reach(const Grid& g, int a, int c, double H, int& lo, int& cnt) {
+  int k = (int)ceil(H * g.inv_cs[a] * (1.0 + 1e-9));
+  if (g.per[a] && 2 * k + 1 >= g.nc[a]) {
+    lo = 0;
+    cnt = g.nc[a];
+    return;
+  }
+  lo = c - k;
+  cnt = 2 * k + 1;
+}
+
+__global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (wave >= d.nr) return;
+  const int si = d.rig_sorted[wave];
+  const D4 ps = d.pos[si];
+  const double R = ps.w, H = R + d.h, H2 = H * H;
+  int oob = 0;
+  int c[3] = {cell_coord(ps.x, d.g, 0, &oob), cell_coord(ps.y, d.g, 1, &oob),
+              cell_coord(ps.z, d.g, 2, &oob)};
+  int lo[3], cnt[3];
+  for (int a = 0; a < 3; ++a) reach(d.g, a, c[a], H, lo[a], cnt[a]);
+  const int nrows = cnt[1] * cnt[2];
+  const size_t np = (size_t)d.npad;
+  double om = 0, v0 = 0, v1 = 0, v2 = 0, f0 = 0, f1 = 0, f2 = 0;
+  int nrig = 0;
+  for (int row = lane; row < nrows; row += 64) {
+    int z = lo[2] + row / cnt[1];
+    int y = lo[1] + row % cnt[1];
+    if (!wrap_axis(z, d.g.nc[2], d.g.per[2]) || !wrap_axis(y, d.g.nc[1], d.g.per[1])) continue;
+    for (int kx = 0; kx < cnt[0]; ++kx) {
+      int x = lo[0] + kx;
+      if (!wrap_axis(x, d.g.nc[0], d.g.per[0])) continue;
+      int cc = cell_index(d.g, x, y, z);
+      int jb = d.cstart[cc], je = d.cstart[cc + 1];
+      for (int j = jb; j < je; ++j) {
+        if (j == si) continue;
+        uint8_t tj = d.type[j];
+        if (tj != T_FLUID && tj != T_RIGID) continue;
+        D4 pj = d.pos[j];
+        double ex = min_img(ps.x - pj.x, d.per[0], d.L[0], d.halfL[0]);
+        double ey = min_img(ps.y - pj.y, d.per[1], d.L[1], d.halfL[1]);
+        double ez = min_img(ps.z - pj.z, d.per[2], d.L[2], d.halfL[2]);
+        double r2 = r2_exact(ex, ey, ez);
+        if (!(r2 < H2)) continue;
+        if (tj == T_RIGID) {
+          ++nrig;
+          continue;
+        }
+        double w = lucy_w(sqrt(r2), H);
+        D4 vj = d.vel[j];
+        om += w;
+        v0 += w * vj.x;
+        v1 += w * vj.y;
+        v2 += w * vj.z;
+        f0 += w * (double)d.fout[6 * np + j];
+        f1 += w * (double)d.fout[7 * np + j];
+        f2 += w * (double)d.fout[8 * np + j];
+      }
+    }
+  }
+  om = wave_sum(om);
+  v0 = wave_sum(v0);
+  v1 = wave_sum(v1);
+  v2 = wave_sum(v2);
+  f0 = wave_sum(f0);
+  f1 = wave_sum(f1);
+  f2 = wave_sum(f2);
+  nrig = wave_sum_i(nrig);
+  if (lane != 0) return;
+  const int s = wave;
+  const double Vs = 4.0 / 3.0 * PI * R * R * R;
+  const double VH = 4.0 / 3.0 * PI * H * H * H;
+  double eps = 1.0 - Vs * (double)nrig / VH;
+  eps = fmin(fmax(eps, d.eps_min), 1.0);
+  d.eps[s] = eps;
+  d.omega[s] = om;
+  double dg[3] = {0, 0, 0}, pg[3] = {0, 0, 0};
+  if (om > 0.0) {
+    const D4 vs = d.vel[si];
+    double dv[3] = {vs.x - v0 / om, vs.y - v1 / om, vs.z - v2 / om};
+    double dva = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+    double B = drag_b(eps, dva, 2.0 * R, d.rho0, d.eta);
+    double kp = d.rho0 * Vs / d.m_f;
+    for (int a = 0; a < 3; ++a) dg[a] = -B * Vs * dv[a];
+    pg[0] = kp * (f0 / om);
+    pg[1] = kp * (f1 / om);
+    pg[2] = kp * (f2 / om);
+  }
+  for (int a = 0; a < 3; ++a) {
+    d.f_dg[3 * s + a] = dg[a];
+    d.f_pg[3 * s + a] = pg[a];
+  }
+}
+
+void launch_fpi_action(const Dev& d, hipStream_t st) {
+  if (d.nr == 0) return;
+  int waves_per_block = BS / 64;
+  k_fpi_action<<<(d.nr + waves_per_block - 1) / waves_per_block, BS, 0, st>>>(d);
+}
+
+// 27 cells of the rigid grid around a coordinate (all cells of a periodic
+// axis shorter than three cells, each once)
+template <class Fn>
+__device__ __forceinline__ void for_rigid_stencil(const Grid& G, int cx, int cy, int cz, Fn&& fn) {
+  int lo[3], cnt[3], cc[3] = {cx, cy, cz};
+  for (int a = 0; a < 3; ++a) {
+    if (G.per[a] && G.nc[a] < 3) {
+      lo[a] = 0;
+      cnt[a] = G.nc[a];
+    } else {
+      lo[a] = cc[a] - 1;
+      cnt[a] = 3;
+    }
+  }
+  for (int kz = 0; kz < cnt[2]; ++kz) {
+    int z = lo[2] + kz;
+    if (!wrap_axis(z, G.nc[2], G.per[2])) continue;
+    for (int ky = 0; ky < cnt[1]; ++ky) {
+      int y = lo[1] + ky;
+      if (!wrap_axis(y, G.nc[1], G.per[1])) continue;
+      for (int kx = 0; kx < cnt[0]; ++kx) {
+        int x = lo[0] + kx;
+        if (!wrap_axis(x, G.nc[0], G.per[0])) continue;
+        fn(cell_index(G, x, y, z));
+      }
+    }
+  }
+}
+
+// (a7) reaction on each fluid particle, Eq. F_fpi_DG_reac normalised per
+// rigid particle: -sum_s F^DG_s w_sj / Omega_s over rigid s with j in C_s.
+__global__ __launch_bounds__(BS) void k_fpi_reaction(Dev d) {
+  int i = xcd_tid();
+  if (i >= d.n) return;
+  double a0 = 0, a1 = 0, a2 = 0;
+  if (d.type[i] == T_FLUID) {
+    D4 pi = d.pos[i];
+    int oob = 0;
+    int cx = cell_coord(pi.x, d.rg, 0, &oob);
+    int cy = cell_coord(pi.y, d.rg, 1, &oob);
+    int cz = cell_coord(pi.z, d.rg, 2, &oob);
+    for_rigid_stencil(d.rg, cx, cy, cz, [&](int cell) {
+      int tb = d.rstart[cell], te = d.rstart[cell + 1];
+      for (int t = tb; t < te; ++t) {
+        int s = d.ritems[t];
+        double oms = d.omega[s];
+        if (!(oms > 0.0)) continue;
+        D4 ps = d.pos[d.rig_sorted[s]];
+        double H = ps.w + d.h;
+        double ex = min_img(ps.x - pi.x, d.per[0], d.L[0], d.halfL[0]);
+        double ey = min_img(ps.y - pi.y, d.per[1], d.L[1], d.halfL[1]);
+        double ez = min_img(ps.z - pi.z, d.per[2], d.L[2], d.halfL[2]);
+        double r2 = r2_exact(ex, ey, ez);
+        if (!(r2 < H * H)) continue;
+        double c = lucy_w(sqrt(r2), H) / oms;
+        a0 -= d.f_dg[3 * s + 0] * c;
+        a1 -= d.f_dg[3 * s + 1] * c;
+        a2 -= d.f_dg[3 * s + 2] * c;
+      }
+    });
+  }
+  const size_t np = (size_t)d.npad;
+  d.fout[9 * np + i] = (float)a0;
+  d.fout[10 * np + i] = (float)a1;
+  d.fout[11 * np + i] = (float)a2;
+}
+
+void launch_fpi_reaction(const Dev& d, hipStream_t st) {
+  k_fpi_reaction<<<nblocks(d.n), BS, 0, st>>>(d);
+}
+
+// ---------------------------------------------------------------------------
+// (a8) DEM contacts (Sec. 2.2) and lubrication (Sec. 2.3), one thread per
+// rigid particle, FP64.  The contact table row of a particle holds partner
+// ids and tangential displacements; commit (second pass) writes the next
+// table: the updated history of every pair still in contact.
+
+__global__ __launch_bounds__(BS) void k_dem(Dev d, int commit, int* nxt_cnt, int* nxt_partner,
+                                           double* nxt_dt) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= d.nr) return;
+  const int si = d.rig_sorted[s];
+  const D4 ps = d.pos[si], vs = d.vel[si], ws = d.om[si];
+  const double Rs = ps.w, ms = vs.w;
+  const double Di = (1.0 - d.nu * d.nu) / (d.E * PI);
+  int oob = 0;
+  int cx = cell_coord(ps.x, d.rg, 0, &oob);
+  int cy = cell_coord(ps.y, d.rg, 1, &oob);
+  int cz = cell_coord(ps.z, d.rg, 2, &oob);
+  const int mc = d.maxc;
+  const int ocnt = d.ct_cnt[s];
+  double F[3] = {0, 0, 0}, FL[3] = {0, 0, 0}, N[3] = {0, 0, 0};
+  int ncnt = 0;
+  int overflow = 0;
+  for_rigid_stencil(d.rg, cx, cy, cz, [&](int cell) {
+    int tb = d.rstart[cell], te = d.rstart[cell + 1];
+    for (int t = tb; t < te; ++t) {
+      int k = d.ritems[t];
+      if (k == s) continue;
+      int sk = d.rig_sorted[k];
+      D4 pk = d.pos[sk];
+      double Rk = pk.w;
+      double e0 = min_img(ps.x - pk.x, d.per[0], d.L[0], d.halfL[0]);
+      double e1 = min_img(ps.y - pk.y, d.per[1], d.L[1], d.halfL[1]);
+      double e2 = min_img(ps.z - pk.z, d.per[2], d.L[2], d.halfL[2]);
+      double L2 = r2_exact(e0, e1, e2);
+      double reachk = Rs + Rk + d.h;
+      if (!(L2 < reachk * reachk)) continue;
+      double L = sqrt(L2);
+      D4 vk = d.vel[sk];
+      if (L < Rs + Rk) {
+        D4 wk = d.om[sk];
+        int gk = d.rig_gid[k];
+        double dt0 = 0, dt1 = 0, dt2 = 0;
+        for (int q = 0; q < ocnt; ++q) {
+          if (d.ct_partner[s * mc + q] == gk) {
+            dt0 = d.ct_dt[(size_t)(s * mc + q) * 3 + 0];
+            dt1 = d.ct_dt[(size_t)(s * mc + q) * 3 + 1];
+            dt2 = d.ct_dt[(size_t)(s * mc + q) * 3 + 2];
+            break;
+          }
+        }
+        double n0 = e0 / L, n1 = e1 / L, n2 = e2 / L;
+        double ov = L - (Rs + Rk);  // delta_n = ov * n
+        double u0 = vs.x - vk.x, u1 = vs.y - vk.y, u2 = vs.z - vk.z;
+        double un = u0 * n0 + u1 * n1 + u2 * n2;
+        double rw0 = Rs * ws.x + Rk * wk.x, rw1 = Rs * ws.y + Rk * wk.y,
+               rw2 = Rs * ws.z + Rk * wk.z;
+        double t0 = u0 - un * n0 + (rw1 * n2 - rw2 * n1);
+        double t1 = u1 - un * n1 + (rw2 * n0 - rw0 * n2);
+        double t2 = u2 - un * n2 + (rw0 * n1 - rw1 * n0);
+        double kn = 4.0 / (3.0 * PI) * (1.0 / (Di + Di)) * sqrt(Rs * Rk / (Rs + Rk));
+        double kt = kn / (2.0 * (1.0 + d.nu));
+        double mk = vk.w;
+        double mm = 2.0 * ms * mk / (ms + mk);
+        double cn = d.damp * 2.0 * sqrt(mm * kn), ct = d.damp * 2.0 * sqrt(mm * kt);
+        double fn0 = -kn * ov * n0 - cn * un * n0;
+        double fn1 = -kn * ov * n1 - cn * un * n1;
+        double fn2 = -kn * ov * n2 - cn * un * n2;
+        double ft0 = -kt * dt0 - ct * t0, ft1 = -kt * dt1 - ct * t1, ft2 = -kt * dt2 - ct * t2;
+        double vta = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+        double dta = sqrt(dt0 * dt0 + dt1 * dt1 + dt2 * dt2);
+        double d0 = 0, d1 = 0, d2 = 0;
+        if (vta > 0.0) {
+          d0 = t0 / vta;
+          d1 = t1 / vta;
+          d2 = t2 / vta;
+        } else if (dta > 0.0) {
+          d0 = dt0 / dta;
+          d1 = dt1 / dta;
+          d2 = dt2 / dta;
+        }
+        double fna = sqrt(fn0 * fn0 + fn1 * fn1 + fn2 * fn2);
+        double fta = sqrt(ft0 * ft0 + ft1 * ft1 + ft2 * ft2);
+        double lim = d.mu * fna;
+        double nd0, nd1, nd2;
+        if (fta >= lim) {  // Coulomb slider, Eq. slideref
+          ft0 = -lim * d0;
+          ft1 = -lim * d1;
+          ft2 = -lim * d2;
+          double m = lim / kt;
+          nd0 = m * d0;
+          nd1 = m * d1;
+          nd2 = m * d2;
+        } else {  // Eq. tandispn
+          nd0 = dta * d0 + t0 * d.dt;
+          nd1 = dta * d1 + t1 * d.dt;
+          nd2 = dta * d2 + t2 * d.dt;
+        }
+        F[0] += fn0 + ft0;
+        F[1] += fn1 + ft1;
+        F[2] += fn2 + ft2;
+        // torque R_s (-n) x F_t
+        N[0] += -Rs * (n1 * ft2 - n2 * ft1);
+        N[1] += -Rs * (n2 * ft0 - n0 * ft2);
+        N[2] += -Rs * (n0 * ft1 - n1 * ft0);
+        if (commit) {
+          if (ncnt < mc) {
+            nxt_partner[s * mc + ncnt] = gk;
+            nxt_dt[(size_t)(s * mc + ncnt) * 3 + 0] = nd0;
+            nxt_dt[(size_t)(s * mc + ncnt) * 3 + 1] = nd1;
+            nxt_dt[(size_t)(s * mc + ncnt) * 3 + 2] = nd2;
+            ++ncnt;
+          } else {
+            overflow = 1;
+          }
+        }
+      } else if (d.lub) {
+        double gap = L - (Rs + Rk);
+        if (gap > 0.0 && gap < d.h) {
+          double db = Rs + Rk;
+          double gg = gap > d.lub_gap_min ? gap : d.lub_gap_min;
+          double c = 3.0 * PI * d.eta * db * db / (8.0 * gg);
+          FL[0] += c * (vk.x - vs.x);
+          FL[1] += c * (vk.y - vs.y);
+          FL[2] += c * (vk.z - vs.z);
+        }
+      }
+    }
+  });
+  for (int a = 0; a < 3; ++a) {
+    d.f_dem[3 * s + a] = F[a];
+    d.f_lub[3 * s + a] = FL[a];
+    d.n_dem[3 * s + a] = N[a];
+  }
+  if (commit) {
+    nxt_cnt[s] = ncnt;
+    if (overflow) atomicOr(d.status, ST_CONTACT_OVERFLOW);
+  }
+}
+
+void launch_dem(const Dev& d, int commit, int* nxt_cnt, int* nxt_partner, double* nxt_dt,
+                hipStream_t st) {
+  if (d.nr == 0) return;
+  k_dem<<<(d.nr + BS - 1) / BS, BS, 0, st>>>(d, commit, nxt_cnt, nxt_partner, nxt_dt);
+}
+
+// ---------------------------------------------------------------------------
+// (a9) velocity Verlet (Alg. 1, update) with the boundary treatment.
+
+__device__ __forceinline__ void total_force(const Dev& d, int i, uint8_t t, const D4& p,
+                                            int rigid_active, double F[3], double N[3]) {
+  double sg = 1.0;
+  if (d.gtype == 1) {
+    double x = d.gaxis == 0 ? p.x : (d.gaxis == 1 ? p.y : p.z);
+    sg = (x - d.org[d.gaxis] >= 0.5 * d.L[d.gaxis]) ? 1.0 : -1.0;
+  }
+  const size_t np = (size_t)d.npad;
+  double m = d.vel[i].w;
+  for (int a = 0; a < 3; ++a) {
+    double body = m * d.body[a] * sg;
+    if (t == T_FLUID) {
+      double rx = d.have_rxn ? (double)d.fout[(9 + a) * np + i] : 0.0;
+      F[a] = (double)d.fout[a * np + i] + rx + body;
+      N[a] = (double)d.fout[(3 + a) * np + i];
+    } else if (t == T_INNER) {
+      F[a] = (double)d.fout[a * np + i] + body;
+      N[a] = (double)d.fout[(3 + a) * np + i];
+    } else if (t == T_RIGID && rigid_active) {
+      int s = d.gid2slot[d.gid[i]];
+      F[a] = d.f_pg[3 * s + a] + d.f_dg[3 * s + a] + d.f_dem[3 * s + a] + d.f_lub[3 * s + a] +
+             body;
+      N[a] = d.n_dem[3 * s + a];
+    } else {
+      F[a] = 0.0;
+      N[a] = 0.0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(BS) void k_integrate(Dev d, int velver, int rigid_active) {
+  int i = xcd_tid();
+  if (i >= d.n) return;
+  uint8_t t = d.type[i];
+  if (t == T_OUTER) return;
+  if (t == T_RIGID && !rigid_active) return;
+  D4 p = d.pos[i], v = d.vel[i], w = d.om[i];
+  double F[3], N[3];
+  total_force(d, i, t, p, rigid_active, F, N);
+  const double hdt = 0.5 * d.dt;
+  v.x += hdt * F[0] / v.w;
+  v.y += hdt * F[1] / v.w;
+  v.z += hdt * F[2] / v.w;
+  w.x += hdt * N[0] / w.w;
+  w.y += hdt * N[1] / w.w;
+  w.z += hdt * N[2] / w.w;
+  int bad = 0;
+  if (velver == 1 && (t == T_FLUID || t == T_RIGID)) {
+    double x[3] = {p.x + d.dt * v.x, p.y + d.dt * v.y, p.z + d.dt * v.z};
+    double vv[3] = {v.x, v.y, v.z};
+    for (int a = 0; a < 3; ++a) {
+      double lo = d.org[a], hi = d.org[a] + d.L[a];
+      if (d.per[a]) {
+        if (x[a] < lo)
+          x[a] += d.L[a];
+        else if (x[a] >= hi)
+          x[a] -= d.L[a];
+      } else if (x[a] < lo || x[a] > hi) {
+        x[a] = x[a] < lo ? 2.0 * lo - x[a] : 2.0 * hi - x[a];
+        if (d.noslip) {
+          vv[0] = -vv[0];
+          vv[1] = -vv[1];
+          vv[2] = -vv[2];
+        } else {
+          vv[a] = -vv[a];
+        }
+        if (x[a] < lo || x[a] > hi) bad |= ST_OUT_OF_DOMAIN;
+      }
+    }
+    p.x = x[0];
+    p.y = x[1];
+    p.z = x[2];
+    v.x = vv[0];
+    v.y = vv[1];
+    v.z = vv[2];
+    d.pos[i] = p;
+  }
+  if (!isfinite(v.x) || !isfinite(v.y) || !isfinite(v.z) || !isfinite(w.x) || !isfinite(w.y) ||
+      !isfinite(w.z) || !isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z))
+    bad |= ST_NONFINITE;
+  if (bad) atomicOr(d.status, bad);
+  d.vel[i] = v;
+  d.om[i] = w;
+  if (velver == 2) {
+    // positions did not move: refresh the FP32 records for the next pass
+    F4 vr = d.vrec[i], wr = d.wrec[i];
+    vr.x = (float)v.x;
+    vr.y = (float)v.y;
+    vr.z = (float)v.z;
+    wr.x = (float)w.x;
+    wr.y = (float)w.y;
+    wr.z = (float)w.z;
+    d.vrec[i] = vr;
+    d.wrec[i] = wr;
+  }
+}
+
+void launch_integrate(const Dev& d, int velver, int rigid_active, hipStream_t st) {
+  k_integrate<<<nblocks(d.n), BS, 0, st>>>(d, velver, rigid_active);
+}
+
+// ---------------------------------------------------------------------------
+// read-out in id order
+
+__global__ __launch_bounds__(BS) void k_read_field(Dev d, int field, int rigid_active,
+                                                  double* out) {
+  int i = xcd_tid();
+  if (i >= d.n) return;
+  const int g = d.gid[i];
+  const uint8_t t = d.type[i];
+  const size_t np = (size_t)d.npad;
+  double v[3] = {0, 0, 0};
+  int comps = (field == SDPDEM_DENS || field == SDPDEM_PRES || field == SDPDEM_PRES_SMOOTH ||
+               field == SDPDEM_EPS) ? 1 : 3;
+  int s = (t == T_RIGID) ? d.gid2slot[g] : -1;
+  switch (field) {
+    case SDPDEM_POS: {
+      D4 p = d.pos[i];
+      v[0] = p.x;
+      v[1] = p.y;
+      v[2] = p.z;
+    } break;
+    case SDPDEM_VEL: {
+      D4 p = d.vel[i];
+      v[0] = p.x;
+      v[1] = p.y;
+      v[2] = p.z;
+    } break;
+    case SDPDEM_ANGVEL: {
+      D4 p = d.om[i];
+      v[0] = p.x;
+      v[1] = p.y;
+      v[2] = p.z;
+    } break;
+    case SDPDEM_DENS:
+      v[0] = d.rho[i];
+      break;
+    case SDPDEM_PRES:
+      v[0] = d.p[i];
+      break;
+    case SDPDEM_PRES_SMOOTH:
+      v[0] = (double)d.ps[i];
+      break;
+    case SDPDEM_F_SDPD:
+    case SDPDEM_N_SDPD:
+    case SDPDEM_F_CD:
+    case SDPDEM_F_RXN: {
+      int base = field == SDPDEM_F_SDPD ? 0 : field == SDPDEM_N_SDPD ? 3 : field == SDPDEM_F_CD ? 6 : 9;
+      if (field != SDPDEM_F_RXN || d.have_rxn)
+        for (int a = 0; a < 3; ++a) v[a] = (double)d.fout[(base + a) * np + i];
+    } break;
+    case SDPDEM_F_DG:
+    case SDPDEM_F_PG:
+    case SDPDEM_F_DEM:
+    case SDPDEM_F_LUB:
+    case SDPDEM_N_DEM:
+      if (s >= 0 && rigid_active) {
+        const double* src = field == SDPDEM_F_DG ? d.f_dg : field == SDPDEM_F_PG ? d.f_pg
+                          : field == SDPDEM_F_DEM ? d.f_dem : field == SDPDEM_F_LUB ? d.f_lub
+                          : d.n_dem;
+        for (int a = 0; a < 3; ++a) v[a] = src[3 * s + a];
+      }
+      break;
+    case SDPDEM_EPS:
+      if (s >= 0 && rigid_active) v[0] = d.eps[s];
+      break;
+    case SDPDEM_F_TOTAL:
+    case SDPDEM_N_TOTAL: {
+      double F[3], N[3];
+      total_force(d, i, t, d.pos[i], rigid_active, F, N);
+      for (int a = 0; a < 3; ++a) v[a] = field == SDPDEM_F_TOTAL ? F[a] : N[a];
+    } break;
+    default:
+      break;
+  }
+  for (int a = 0; a < comps; ++a) out[(size_t)g * comps + a] = v[a];
+}
+
+void launch_read_field(const Dev& d, int field, int rigid_active, double* out, hipStream_t st) {
+  k_read_field<<<nblocks(d.n), BS, 0, st>>>(d, field, rigid_active, out);
+}
+
+// FP64 totals: per-block partial sums in a fixed tree, then one block.
+static constexpr int NTOT = 13;
+
+__global__ __launch_bounds__(BS) void k_totals_partial(Dev d, double* part) {
+  __shared__ double sh[NTOT][BS];
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double q[NTOT];
+  for (int k = 0; k < NTOT; ++k) q[k] = 0.0;
+  q[9] = INFINITY;
+  q[10] = -INFINITY;
+  if (i < d.n && d.type[i] != T_OUTER) {
+    D4 x = d.pos[i], v = d.vel[i], w = d.om[i];
+    double m = v.w, I = w.w;
+    q[0] = m * v.x;
+    q[1] = m * v.y;
+    q[2] = m * v.z;
+    q[3] = m * (x.y * v.z - x.z * v.y) + I * w.x;
+    q[4] = m * (x.z * v.x - x.x * v.z) + I * w.y;
+    q[5] = m * (x.x * v.y - x.y * v.x) + I * w.z;
+    double v2 = v.x * v.x + v.y * v.y + v.z * v.z;
+    q[6] = 0.5 * m * v2;
+    q[7] = 0.5 * I * (w.x * w.x + w.y * w.y + w.z * w.z);
+    q[8] = sqrt(v2);
+    q[9] = d.rho[i];
+    q[10] = d.rho[i];
+    q[11] = m;
+  }
+  for (int k = 0; k < NTOT; ++k) sh[k][threadIdx.x] = q[k];
+  __syncthreads();
+  for (int o = BS / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      for (int k = 0; k < NTOT; ++k) {
+        double a = sh[k][threadIdx.x], b = sh[k][threadIdx.x + o];
+        sh[k][threadIdx.x] = k == 8 || k == 10 ? fmax(a, b) : k == 9 ? fmin(a, b) : a + b;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < NTOT; ++k) part[(size_t)blockIdx.x * NTOT + k] = sh[k][0];
+}
+
+__global__ __launch_bounds__(BS) void k_totals_final(const double* part, int nb, double* out) {
+  __shared__ double sh[NTOT][BS];
+  double q[NTOT];
+  for (int k = 0; k < NTOT; ++k) q[k] = k == 9 ? INFINITY : (k == 10 || k == 8) ? -INFINITY : 0.0;
+  q[8] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += BS)
+    for (int k = 0; k < NTOT; ++k) {
+      double x = part[(size_t)b * NTOT + k];
+      q[k] = k == 8 || k == 10 ? fmax(q[k], x) : k == 9 ? fmin(q[k], x) : q[k] + x;
+    }
+  for (int k = 0; k < NTOT; ++k) sh[k][threadIdx.x] = q[k];
+  __syncthreads();
+  for (int o = BS / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      for (int k = 0; k < NTOT; ++k) {
+        double a = sh[k][threadIdx.x], b = sh[k][threadIdx.x + o];
+        sh[k][threadIdx.x] = k == 8 || k == 10 ? fmax(a, b) : k == 9 ? fmin(a, b) : a + b;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < NTOT; ++k) out[k] = sh[k][0];
+}
+
+int totals_partial_blocks(int n) { return (n + BS - 1) / BS > 0 ? (n + BS - 1) / BS : 1; }
+
+void launch_totals(const Dev& d, double* partial, double* out, hipStream_t st) {
+  int nb = totals_partial_blocks(d.n);
+  k_totals_partial<<<nb, BS, 0, st>>>(d, partial);
+  k_totals_final<<<1, BS, 0, st>>>(partial, nb, out);
+}
+
+}  // namespace sdpdem

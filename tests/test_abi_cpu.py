@@ -1,0 +1,97 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads,
+exports every symbol of include/sdpdem.h, sizes workspaces and rejects bad
+arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2002_03120_amd import sdpdem as S
+from paper_2002_03120_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "sdpdem.h")).read()
+    return sorted(set(re.findall(r"\b(sdpdem_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(S.LIB_PATH):
+        from paper_2002_03120_amd import build as B
+        B.build()
+    return S.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    syms = _declared_symbols()
+    assert len(syms) >= 15
+    for name in syms:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
+        assert S.sdpdem_status_string(code) not in ("", "unknown status")
+    assert S.sdpdem_status_string(-99) == "unknown status"
+
+
+def test_field_comps(lib):
+    for name, f in S.FIELDS.items():
+        c = lib.sdpdem_field_comps(f)
+        assert c == (1 if name in ("DENS", "PRES", "PRES_SMOOTH", "EPS") else 3)
+    assert lib.sdpdem_field_comps(99) == 0
+
+
+def test_workspace_scales_with_problem(lib):
+    p, parts, _ = W.reverse_poiseuille(n_side=(10, 10, 10))
+    small = S.sdpdem_workspace_bytes(p, parts)
+    p2, parts2, _ = W.reverse_poiseuille(n_side=(20, 20, 20))
+    big = S.sdpdem_workspace_bytes(p2, parts2)
+    assert 6 * small < big < 10 * small
+    p3 = dict(p2, max_neighbors=128)
+    assert S.sdpdem_workspace_bytes(p3, parts2) > big
+
+
+@pytest.mark.parametrize("bad", [
+    dict(xi=0.0), dict(xi=1.0), dict(h=0.0), dict(dt=-1.0), dict(L=[4.0, 10.0, 10.0]),
+    dict(max_neighbors=0), dict(gravity_axis=3), dict(rho0=0.0),
+])
+def test_rejects_bad_params(lib, bad):
+    p, parts, _ = W.reverse_poiseuille(n_side=(10, 10, 10))
+    p.update(bad)
+    with pytest.raises(S.SdpdemError) as e:
+        S.sdpdem_workspace_bytes(p, parts)
+    assert e.value.code == S.E_INVALID_ARG
+
+
+def test_rejects_bad_particles(lib):
+    p, parts, _ = W.reverse_poiseuille(n_side=(6, 6, 6))
+    dup = {k: np.array(v, copy=True) for k, v in parts.items()}
+    dup["id"][0] = dup["id"][1]
+    badt = {k: np.array(v, copy=True) for k, v in parts.items()}
+    badt["type"][3] = 7
+    rig = {k: np.array(v, copy=True) for k, v in parts.items()}
+    rig["type"][3] = W.RIGID
+    rig["radius"][3] = 0.0
+    for q in (dup, badt, rig):
+        with pytest.raises(S.SdpdemError):
+            S.sdpdem_workspace_bytes(p, q)
+
+
+def test_create_rejects_small_workspace_without_device(lib):
+    p, parts, _ = W.reverse_poiseuille(n_side=(6, 6, 6))
+    pp = S.make_params(p)
+    q, keep = S.make_particles(parts)
+    h = ctypes.c_void_p()
+    # a fake non-null pointer with too few bytes is refused before any HIP call
+    rc = lib.sdpdem_create(ctypes.byref(pp), ctypes.byref(q), ctypes.c_void_p(256), 1024,
+                           None, ctypes.byref(h))
+    assert rc == S.E_WORKSPACE_TOO_SMALL
+    rc = lib.sdpdem_create(ctypes.byref(pp), ctypes.byref(q), None, 1 << 30, None,
+                           ctypes.byref(h))
+    assert rc == S.E_INVALID_ARG

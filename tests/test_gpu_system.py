@@ -1,0 +1,170 @@
+"""Multi-step behaviour of the GPU library: determinism, trajectories and
+conservation against the oracle, bit-exact restart, DEM contact tables,
+frozen rigid particles and the error paths forced from the host."""
+import math
+
+import numpy as np
+import pytest
+
+from _parity import assert_force_field, assert_same_neighbors, assert_scalar_fields
+from paper_2002_03120_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2002_03120_amd import sdpdem
+    sdpdem.lib()
+    return sdpdem
+
+
+def _c1(kT=1e-3, **over):
+    p, parts, _ = W.reverse_poiseuille(kBT=kT, **over)
+    parts = W.perturb(parts, p, jitter=0.1, kT=max(kT, 1e-4), seed=1, spin=True)
+    return p, parts
+
+
+def test_runs_are_bitwise_repeatable(S):
+    print("[case] determinism C1 x2", flush=True)
+    p, parts = _c1()
+    out = []
+    for _ in range(2):
+        g = S.System(p, parts)
+        g.step(20)
+        out.append([g.read_field(f) for f in ("POS", "VEL", "ANGVEL", "F_SDPD")])
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
+
+def test_reverse_poiseuille_trajectory_tracks_oracle(S, oracle_lib):
+    """200 steps of the reverse-Poiseuille box (kT = 1e-3): the FP32 pair
+    forces make the GPU trajectory drift from the FP64 one only slowly."""
+    print("[case] C1 trajectory 200 steps", flush=True)
+    p, parts = _c1()
+    g = S.System(p, parts)
+    o = oracle_lib.Oracle(p, parts)
+    errs = []
+    for blk in range(4):
+        g.step(50)
+        o.step(50)
+        errs.append(np.abs(g.read_field("POS") - o.read_field("POS")).max())
+    tg, to = g.totals(), o.totals()
+    print("  max |dx| per 50 steps", errs, "dP", tg[:3] - to[:3], "dKE", tg[6] - to[6], flush=True)
+    assert errs[-1] < 1e-6
+    assert abs(tg[6] - to[6]) < 1e-6 * to[6]
+
+
+def test_momentum_is_conserved_without_body_force(S):
+    print("[case] momentum C1 no body force", flush=True)
+    p, parts = _c1(g=0.0)
+    g = S.System(p, parts)
+    P0 = g.totals()[:3]
+    g.compute_forces()
+    scale = np.abs(g.read_field("F_SDPD")).sum()
+    g.step(100)
+    P1 = g.totals()[:3]
+    # FP32 per-particle sums of exactly antisymmetric pair terms
+    assert np.abs(P1 - P0).max() < 1e-6 * scale * 100 * p["dt"]
+
+
+def _colliding_spheres(lub=0, n_side=10, **over):
+    p, parts, _ = W.reverse_poiseuille(n_side=(n_side,) * 3, kBT=1e-3, g=0.0, dt=0.01,
+                                       enable_lub=lub, **over)
+    parts = W.perturb(parts, p, jitter=0.0, kT=1e-3, seed=11)
+    centres = [(3.0, 5.0, 5.0), (5.02, 5.3, 5.0), (3.0, 2.0, 8.0), (3.1, 4.02, 8.2)]
+    vels = [(0.1, 0.0, 0.05), (-0.1, 0.0, -0.05), (0.0, 0.1, 0.02), (0.03, -0.1, 0.0)]
+    R = 1.0
+    vs = 4.0 / 3.0 * math.pi * R ** 3
+    for c, v in zip(centres, vels):
+        k = int(np.argmin(((parts["pos"] - np.asarray(c)) ** 2).sum(axis=1)))
+        parts["type"][k] = W.RIGID
+        parts["pos"][k] = c
+        parts["vel"][k] = v
+        parts["mass"][k] = 2.5 * vs
+        parts["inertia"][k] = 0.4 * 2.5 * vs * R * R
+        parts["radius"][k] = R
+    return p, parts
+
+
+def test_contacts_and_forces_follow_oracle(S, oracle_lib):
+    print("[case] colliding spheres 30 steps", flush=True)
+    p, parts = _colliding_spheres()
+    g = S.System(p, parts)
+    o = oracle_lib.Oracle(p, parts)
+    g.step(30)
+    o.step(30)
+    pg, dg = g.read_contacts()
+    po, do = o.read_contacts()
+    assert pg.shape[0] == 2 and np.array_equal(pg, po)
+    assert np.allclose(dg, do, rtol=1e-4, atol=1e-10)
+    # single evaluation from the oracle's own state: tight parity again
+    state = {k: np.array(v, copy=True) for k, v in parts.items()}
+    state["pos"], state["vel"], state["angvel"] = (o.read_field(f) for f in ("POS", "VEL", "ANGVEL"))
+    p2 = dict(p, itr_start=o.current_step)
+    g2 = S.System(p2, state)
+    g2.load_contacts(po, do)
+    o2 = oracle_lib.Oracle(p2, state)
+    o2.load_contacts(po, do)
+    g2.compute_forces()
+    o2.compute_forces()
+    assert_same_neighbors(g2, o2)
+    for f in ("F_SDPD", "F_DG", "F_PG", "F_RXN", "F_DEM", "N_DEM"):
+        assert_force_field(g2, o2, f)
+
+
+def test_restart_is_bit_exact(S):
+    print("[case] restart", flush=True)
+    p, parts = _colliding_spheres(lub=1)
+    a = S.System(p, parts)
+    a.step(40)
+    b = S.System(p, parts)
+    b.step(20)
+    saved = {k: np.array(v, copy=True) for k, v in parts.items()}
+    saved["pos"], saved["vel"], saved["angvel"] = (b.read_field(f) for f in ("POS", "VEL", "ANGVEL"))
+    pairs, dts = b.read_contacts()
+    c = S.System(dict(p, itr_start=b.current_step), saved)
+    c.load_contacts(pairs, dts)
+    c.step(20)
+    for f in ("POS", "VEL", "ANGVEL"):
+        assert np.array_equal(a.read_field(f), c.read_field(f)), f
+    pa, da = a.read_contacts()
+    pc, dc = c.read_contacts()
+    assert np.array_equal(pa, pc) and np.array_equal(da, dc)
+
+
+def test_frozen_rigid_particles(S, oracle_lib):
+    print("[case] itr_actv_rigid", flush=True)
+    p, parts = _colliding_spheres(itr_actv_rigid=5)
+    g = S.System(p, parts)
+    o = oracle_lib.Oracle(p, parts)
+    g.step(3)
+    o.step(3)
+    rig = parts["type"] == W.RIGID
+    assert np.array_equal(g.read_field("POS")[rig], parts["pos"][rig])
+    g.compute_forces()
+    o.compute_forces()
+    for f in ("F_DG", "F_PG", "F_RXN", "F_DEM", "EPS"):
+        assert not np.any(g.read_field(f)) and not np.any(o.read_field(f))
+    g.step(5)
+    assert not np.array_equal(g.read_field("POS")[rig], parts["pos"][rig])
+
+
+def test_error_codes(S):
+    print("[case] error codes", flush=True)
+    p, parts, _ = W.reverse_poiseuille(n_side=(6, 6, 6), kBT=0.0)
+    g = S.System(dict(p, max_neighbors=10), parts)
+    assert g.compute_forces(check=False) == S.E_NBR_OVERFLOW
+    nan = {k: np.array(v, copy=True) for k, v in parts.items()}
+    nan["vel"][5, 1] = np.nan
+    assert S.System(p, nan).step(1, check=False) == S.E_NONFINITE
+    p2, one, _ = W.random_box(1, (10.0, 10.0, 10.0), (0, 0, 0), seed=0)
+    p2.update(kBT=0.0, dt=1.0)
+    one["vel"][0] = [100.0, 0.0, 0.0]
+    assert S.System(p2, one).step(1, check=False) == S.E_OUT_OF_DOMAIN
+    with pytest.raises(S.SdpdemError) as e:
+        S.System(dict(p, xi=-1.0), parts)
+    assert e.value.code == S.E_INVALID_ARG
