@@ -47,6 +47,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the CPU-oracle sample (0 disables it)")
     ap.add_argument("--small", action="store_true", help="a small tank, for quick checks")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="run one device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -63,6 +65,14 @@ def main():
     from paper_2002_03120_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy_mib:
+        src = torch.empty(args.calibrate_copy_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.small:
         p, parts, info = W.dam_break(tank=(64, 32, 48), column=(32, 32, 32), n_rigid=600,
                                      kBT=args.kT)

@@ -31,6 +31,8 @@ struct sdpdem_system {
   double* field_buf;
   double* tot_part;
   double* tot_out;
+  int* brank;
+  int* brick_of_rank;
   int64_t step = 0;
   bool cache_valid = false;
   bool noise = false;
@@ -108,7 +110,8 @@ bool valid_particles(const sdpdem_particles* q, std::vector<int>* slot_of, int* 
 
 // Cell grid: periodic axes are split into floor(L/cs0) equal cells; wall
 // axes cover the domain and every particle with one cell of slack.
-bool make_grid(const sdpdem_params& P, const sdpdem_particles& q, double cs0, Grid& g) {
+bool make_grid(const sdpdem_params& P, const sdpdem_particles& q, double cs0, int brick,
+               Grid& g) {
   double total = 1.0;
   for (int a = 0; a < 3; ++a) {
     g.per[a] = P.periodic[a] ? 1 : 0;
@@ -135,8 +138,12 @@ bool make_grid(const sdpdem_params& P, const sdpdem_particles& q, double cs0, Gr
     g.inv_cs[a] = 1.0 / g.cs[a];
     total *= g.nc[a];
   }
-  if (total > 2.0e9) return false;
-  g.ncells = g.nc[0] * g.nc[1] * g.nc[2];
+  g.brick = brick;
+  for (int a = 0; a < 3; ++a) g.nb[a] = (g.nc[a] + 3) / 4;
+  double keys = brick ? 64.0 * g.nb[0] * g.nb[1] * g.nb[2] : total;
+  if (keys > 1.0e9) return false;
+  g.ncells = brick ? 64 * g.nb[0] * g.nb[1] * g.nb[2] : g.nc[0] * g.nc[1] * g.nc[2];
+  g.nbricks = g.nb[0] * g.nb[1] * g.nb[2];
   return true;
 }
 
@@ -159,8 +166,32 @@ double lattice_sum(double h, double dx) {
 struct Sizes {
   int64_t n, npad, nr;
   int maxn, maxc;
+  int dem_reach = 1;
   Grid g, rg;
+  std::vector<int> brank;  // Morton rank of every brick of the main grid
 };
+
+uint64_t spread3(uint64_t v) {  // bits of v at every third position
+  uint64_t r = 0;
+  for (int b = 0; b < 21; ++b) r |= ((v >> b) & 1u) << (3 * b);
+  return r;
+}
+
+// rank of every brick along the Morton curve of its brick coordinates
+std::vector<int> morton_ranks(const Grid& g) {
+  const int n0 = g.nb[0], n1 = g.nb[1], n2 = g.nb[2];
+  std::vector<std::pair<uint64_t, int>> code((size_t)n0 * n1 * n2);
+  for (int z = 0; z < n2; ++z)
+    for (int y = 0; y < n1; ++y)
+      for (int x = 0; x < n0; ++x) {
+        int lin = (z * n1 + y) * n0 + x;
+        code[(size_t)lin] = {spread3(x) | (spread3(y) << 1) | (spread3(z) << 2), lin};
+      }
+  std::sort(code.begin(), code.end());
+  std::vector<int> rank(code.size());
+  for (size_t r = 0; r < code.size(); ++r) rank[(size_t)code[r].second] = (int)r;
+  return rank;
+}
 
 // Carve the workspace (base == nullptr: only measure it).
 size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
@@ -178,7 +209,11 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
   int* cursor = b.take<int>(nc);
   int* perm = b.take<int>(np);
   int* bsum = b.take<int>((size_t)scan_block_sums_size((int)nc) + 1);
-  int* nbr = b.take<int>((size_t)z.maxn * np);
+  int* brank = b.take<int>(z.brank.size());
+  int* brick_of_rank = b.take<int>(z.brank.size());
+  int* ovf_list = b.take<int>(3 * z.brank.size());
+  int* ovf_cnt = b.take<int>(16);
+  uint16_t* nbr16 = b.take<uint16_t>((size_t)z.maxn * np);
   int* nbr_cnt = b.take<int>(np);
   double* rho = b.take<double>(np);
   double* p = b.take<double>(np);
@@ -202,6 +237,12 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
   int* rcursor = b.take<int>(rnc);
   int* ritems = b.take<int>(nr);
   int* rbsum = b.take<int>((size_t)scan_block_sums_size((int)rnc) + 1);
+  D4* rpos_c = b.take<D4>(nr);
+  D4* rvel_c = b.take<D4>(nr);
+  D4* rom_c = b.take<D4>(nr);
+  D4* rdg_c = b.take<D4>(nr);
+  int* rslot_pos = b.take<int>(nr);
+  int* cstamp = b.take<int>(np);
   int *ctc0 = b.take<int>(nr), *ctc1 = b.take<int>(nr);
   int *ctp0 = b.take<int>(nr * z.maxc), *ctp1 = b.take<int>(nr * z.maxc);
   double *ctd0 = b.take<double>(3 * nr * z.maxc), *ctd1 = b.take<double>(3 * nr * z.maxc);
@@ -228,6 +269,8 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
     s->ct_dt[0] = ctd0;
     s->ct_dt[1] = ctd1;
     s->block_sums = bsum;
+    s->brank = brank;
+    s->brick_of_rank = brick_of_rank;
     s->rblock_sums = rbsum;
     s->field_buf = field_buf;
     s->tot_part = tot_part;
@@ -238,7 +281,9 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
     d.cstart = cstart;
     d.cursor = cursor;
     d.perm = perm;
-    d.nbr = nbr;
+    d.nbr16 = nbr16;
+    d.ovf_list = ovf_list;
+    d.ovf_cnt = ovf_cnt;
     d.nbr_cnt = nbr_cnt;
     d.rho = rho;
     d.p = p;
@@ -262,6 +307,12 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
     d.rcursor = rcursor;
     d.ritems = ritems;
     d.status = status;
+    d.rpos_c = rpos_c;
+    d.rvel_c = rvel_c;
+    d.rom_c = rom_c;
+    d.rdg_c = rdg_c;
+    d.rslot_pos = rslot_pos;
+    d.cstamp = cstamp;
   }
   return total;
 }
@@ -277,11 +328,17 @@ bool plan(const sdpdem_params* P, const sdpdem_particles* q, Sizes& z,
   z.nr = nr;
   z.maxn = P->max_neighbors;
   z.maxc = P->max_contacts;
-  if (!make_grid(*P, *q, P->h * (1.0 + 1e-6), z.g)) return false;
+  if (!make_grid(*P, *q, P->h * (1.0 + 1e-6), 1, z.g)) return false;
+  z.brank = morton_ranks(z.g);
   for (int a = 0; a < 3; ++a)
     if (P->periodic[a] && z.g.nc[a] < 3) return false;
-  double rcs = std::max(2.0 * rmax + P->h, P->h) * (1.0 + 1e-6);
-  if (!make_grid(*P, *q, rcs, z.rg)) return false;
+  // rigid grid: cells at least H_max = R_max + h wide, so that the fluid
+  // particles coupled to a sphere lie in its 27 neighbouring cells
+  double rcs = (rmax + P->h) * (1.0 + 1e-6);
+  if (!make_grid(*P, *q, rcs, 0, z.rg)) return false;
+  // DEM partners lie within R_s + R_k + h <= 2 R_max + h
+  double mincs = std::min(z.rg.cs[0], std::min(z.rg.cs[1], z.rg.cs[2]));
+  z.dem_reach = std::max(1, (int)std::ceil((2.0 * rmax + P->h) / mincs * (1.0 + 1e-9)));
   return true;
 }
 
@@ -339,6 +396,13 @@ void fill_constants(sdpdem_system* s, const Sizes& z) {
   d.kTf = (float)P.kBT;
   d.inv_sqrt_dtf = (float)(1.0 / std::sqrt(P.dt));
   d.cC = (float)P.coeff_c;
+  d.coef_c = P.coeff_c;
+  {
+    double CA = 20.0 * P.eta / 3.0 - 4.0 * P.xi, CB = 17.0 * P.xi - 40.0 * P.eta / 3.0;
+    d.kAf = (float)(-P.coeff_d * CA);
+    d.kBf = (float)(-P.coeff_d * (CA + 2.0 * CB) / 3.0);
+    d.kRf = (float)(-P.coeff_r * CA * 0.5);
+  }
   d.cD = (float)P.coeff_d;
   d.cR = (float)P.coeff_r;
   d.cT = (float)P.coeff_t;
@@ -346,7 +410,12 @@ void fill_constants(sdpdem_system* s, const Sizes& z) {
   d.key0 = (uint32_t)(P.seed & 0xffffffffu);
   d.key1 = (uint32_t)(P.seed >> 32);
   d.g = z.g;
+  d.g.brank = s->brank;
+  d.brick_of_rank = s->brick_of_rank;
   d.rg = z.rg;
+  d.rg.brank = nullptr;
+  d.dem_reach = z.dem_reach;
+  d.stamp = 0;
   s->noise = P.kBT > 0.0 && P.coeff_t != 0.0;
 }
 
@@ -465,6 +534,11 @@ void run_pass(sdpdem_system* s, int velver, int commit, bool integrate, hipStrea
   }
   const bool act = rigid_active(s);
   if (act) {
+    d.stamp += 1;  // marks the fluid particles coupled in this pass
+    {
+      Prof pr(s, SDPDEM_K_RIGID_GRID, st);
+      launch_rigid_gather(d, st);
+    }
     {
       Prof pr(s, SDPDEM_K_FPI_ACTION, st);
       launch_fpi_action(d, st);
@@ -511,24 +585,6 @@ int sync_status(sdpdem_system* s, hipStream_t st) {
 
 }  // namespace
 
-namespace sdpdem {
-
-__global__ void k_nbr_cols(Dev d, int k0, int kn, int* out) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= d.n) return;
-  int cnt = d.nbr_cnt[i];
-  const size_t np = (size_t)d.npad;
-  for (int k = 0; k < kn; ++k) {
-    int kk = k0 + k;
-    out[(size_t)k * np + i] = kk < cnt ? d.gid[d.nbr[(size_t)kk * np + i]] : -1;
-  }
-}
-
-void launch_nbr_cols(const Dev& d, int k0, int kn, int* out, hipStream_t st) {
-  k_nbr_cols<<<(d.n + 255) / 256, 256, 0, st>>>(d, k0, kn, out);
-}
-
-}  // namespace sdpdem
 
 // ---------------------------------------------------------------------------
 // C ABI
@@ -611,6 +667,10 @@ int sdpdem_create(const sdpdem_params* params, const sdpdem_particles* q, void* 
   ok &= hipMemcpyAsync(s->type[0], ht.data(), n, hipMemcpyHostToDevice, st) == hipSuccess;
   ok &= hipMemcpyAsync(s->gid[0], hg.data(), sizeof(int) * n, hipMemcpyHostToDevice, st) == hipSuccess;
   ok &= hipMemcpyAsync(d.gid2slot, slot_of.data(), sizeof(int) * n, hipMemcpyHostToDevice, st) == hipSuccess;
+  std::vector<int> inv(z.brank.size());
+  for (size_t b = 0; b < z.brank.size(); ++b) inv[(size_t)z.brank[b]] = (int)b;
+  ok &= hipMemcpyAsync(s->brank, z.brank.data(), sizeof(int) * z.brank.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipMemcpyAsync(s->brick_of_rank, inv.data(), sizeof(int) * inv.size(), hipMemcpyHostToDevice, st) == hipSuccess;
   if (z.nr) {
     ok &= hipMemcpyAsync(d.rig_gid, hrg.data(), sizeof(int) * z.nr, hipMemcpyHostToDevice, st) == hipSuccess;
     ok &= hipMemcpyAsync(d.rig_sorted, hsort.data(), sizeof(int) * z.nr, hipMemcpyHostToDevice, st) == hipSuccess;
@@ -618,8 +678,10 @@ int sdpdem_create(const sdpdem_params* params, const sdpdem_particles* q, void* 
   launch_fill_i32(s->ct_cnt[0], 0, (size_t)z.nr, st);
   launch_fill_i32(s->ct_cnt[1], 0, (size_t)z.nr, st);
   launch_fill_i32(d.status, 0, 64, st);
+  launch_fill_i32(d.cstamp, 0, (size_t)z.npad, st);
   launch_fill_i32(reinterpret_cast<int*>(d.fout), 0, 12 * (size_t)z.npad, st);
   launch_fill_i32(d.nbr_cnt, 0, (size_t)z.npad, st);
+  launch_fill_i32(d.cstart, 0, (size_t)z.g.ncells + 1, st);
   launch_fill_f64(d.f_dg, 0.0, 3 * (size_t)z.nr, st);
   launch_fill_f64(d.f_pg, 0.0, 3 * (size_t)z.nr, st);
   launch_fill_f64(d.f_dem, 0.0, 3 * (size_t)z.nr, st);
@@ -702,7 +764,8 @@ int sdpdem_read_neighbors(sdpdem_system* s, int64_t* row_ptr, int32_t* cols, int
   row_ptr[0] = 0;
   for (int g = 0; g < n; ++g) row_ptr[g + 1] = row_ptr[g] + rowlen[(size_t)g];
   *nnz = row_ptr[n];
-  if (!cols) return SDPDEM_OK;
+  if (!cols || *nnz == 0) return SDPDEM_OK;
+  if (!s->cache_valid) return SDPDEM_E_INVALID_ARG;  // lists exist only after a build
   if (cap < *nnz) return SDPDEM_E_INVALID_ARG;
   // columns in chunks that fit the field buffer (3n doubles = 6n ints)
   int* dbuf = reinterpret_cast<int*>(s->field_buf);

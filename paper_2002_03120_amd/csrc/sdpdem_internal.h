@@ -29,13 +29,21 @@ struct __align__(16) F4 {
 
 // A uniform cell grid.  Periodic axes span [org, org+L) with nc >= 3 cells;
 // wall axes span the particle bounding box plus one cell of slack.
+// Keys order the cells either linearly (x fastest) or brick-major: 4x4x4
+// bricks ranked along a Morton (Z-order) curve, cells linear inside a
+// brick, so that a cell's 3x3x3 neighbourhood lies in a few compact runs of
+// the sorted arrays and neighbouring bricks are processed close in time.
 struct Grid {
   double lo[3];
   double cs[3];
   double inv_cs[3];
   int nc[3];
   int per[3];
-  int ncells;
+  int brick;         // 1: brick-major keys
+  int nb[3];         // bricks per axis (brick-major keys)
+  const int* brank;  // brick (linear index) -> rank on the Morton curve
+  int ncells;        // number of keys (padded to whole bricks when brick-major)
+  int nbricks;       // bricks (brick-major keys)
 };
 
 // Everything a kernel reads, passed by value.  Particle arrays are in the
@@ -60,6 +68,8 @@ struct Dev {
   int clamp;   // negative pressure -> 0
   int smooth;  // Shepard filter of the pressure
   // single-precision pair constants
+  float kAf, kBf, kRf;  // folded coefficients of the pair force
+  double coef_c;
   float hf, inv_hf, cFf, CAf, CBf, kTf, inv_sqrt_dtf, cC, cD, cR, cT, leverf;
   uint32_t key0, key1;
   Grid g, rg;
@@ -76,13 +86,20 @@ struct Dev {
   int* cursor;
   int* perm;
   // neighbours and fields
-  int* nbr;  // [maxn * npad], column k of row i at k*npad + i
+  // neighbour k of particle i at k*npad + i: its slot in the footprint tile
+  // of i's brick (see the tile kernels)
+  uint16_t* nbr16;
+  const int* brick_of_rank;
+  // bricks deferred by the LDS tile kernels (three lists of nbricks) and
+  // their counters
+  int* ovf_list;
+  int* ovf_cnt;
   int* nbr_cnt;
   double* rho;
   double* p;
   float* ps;
-  F4* vrec;  // FP32 vx, vy, vz, p~/d^2
-  F4* wrec;  // FP32 wx, wy, wz, d = rho/m_f
+  F4* vrec;  // FP32 vx, vy, vz, c_C p~/d^2
+  F4* wrec;  // FP32 wx, wy, wz, 1/d with d = rho/m_f
   float* fout;  // 12 planes of npad: F_sdpd(3) N_sdpd(3) F_cd(3) F_rxn(3)
   // rigid
   int* gid2slot;
@@ -100,6 +117,16 @@ struct Dev {
   int* rstart;
   int* rcursor;
   int* ritems;
+  // rigid records in rigid-grid cell order (index t = position in ritems)
+  D4* rpos_c;
+  D4* rvel_c;
+  D4* rom_c;
+  D4* rdg_c;       // F^DG / Omega of the sphere, w = 1 if it couples
+  int* rslot_pos;  // slot -> t
+  int dem_reach;   // rigid-grid cells to search for DEM partners
+  // fluid particles coupled to a sphere in the current pass carry the stamp
+  int* cstamp;
+  int stamp;
   int* ct_cnt;      // current contact table
   int* ct_partner;  // partner id
   double* ct_dt;
@@ -124,6 +151,7 @@ void launch_permute(const Dev& d, const D4* spos, const D4* svel, const D4* som,
 void launch_build_density(const Dev& d, hipStream_t st);
 void launch_smooth(const Dev& d, hipStream_t st);
 void launch_fluid_forces(const Dev& d, uint32_t step, bool noise, hipStream_t st);
+void launch_rigid_gather(const Dev& d, hipStream_t st);
 void launch_fpi_action(const Dev& d, hipStream_t st);
 void launch_fpi_reaction(const Dev& d, hipStream_t st);
 void launch_dem(const Dev& d, int commit, int* nxt_cnt, int* nxt_partner, double* nxt_dt,

@@ -13,92 +13,9 @@
 // separation vectors taken as FP64 differences rounded once.
 #include <cmath>
 
-#include "sdpdem_internal.h"
+#include "sdpdem_device.h"
 
 namespace sdpdem {
-
-static constexpr int BS = 256;
-static constexpr double PI = 3.14159265358979323846;
-
-static inline int nblocks(size_t n, int bs = BS) {
-  size_t b = (n + bs - 1) / bs;
-  b = (b + 7) / 8 * 8;  // a multiple of the 8 XCDs
-  return (int)(b > 0 ? b : 8);
-}
-
-// Block index -> particle chunk, contiguous per XCD.
-__device__ __forceinline__ int xcd_tid() {
-  unsigned nb = gridDim.x, b = blockIdx.x;
-  unsigned lb = (nb % 8u == 0u) ? (b % 8u) * (nb / 8u) + (b / 8u) : b;
-  return (int)(lb * blockDim.x + threadIdx.x);
-}
-
-__device__ __forceinline__ double min_img(double d, int per, double L, double halfL) {
-  if (per) {
-    if (d > halfL)
-      d = d - L;
-    else if (d < -halfL)
-      d = d + L;
-  }
-  return d;
-}
-
-// r^2 = (dx*dx + dy*dy) + dz*dz with every product and sum rounded (no
-// contraction), so that neighbour membership is the same bit for bit as a
-// plain double-precision evaluation of the definition.
-__device__ __forceinline__ double r2_exact(double a, double b, double c) {
-#pragma clang fp contract(off)
-  double t = a * a;
-  double u = b * b;
-  double v = c * c;
-  return (t + u) + v;
-}
-
-__device__ __forceinline__ int cell_coord(double x, const Grid& g, int a, int* oob) {
-  double f = floor((x - g.lo[a]) * g.inv_cs[a]);
-  int n = g.nc[a];
-  if (g.per[a]) {
-    f = f - (double)n * floor(f / (double)n);
-    if (!(f >= 0.0 && f < (double)n)) {
-      *oob = 1;
-      return 0;
-    }
-    return (int)f;
-  }
-  if (!(f >= 0.0)) {
-    *oob = 1;
-    return 0;
-  }
-  if (f >= (double)n) {
-    *oob = 1;
-    return n - 1;
-  }
-  return (int)f;
-}
-
-__device__ __forceinline__ int cell_index(const Grid& g, int cx, int cy, int cz) {
-  return (cz * g.nc[1] + cy) * g.nc[0] + cx;
-}
-
-// wrap (periodic) or reject (wall) a neighbour cell coordinate
-__device__ __forceinline__ bool wrap_axis(int& c, int n, int per) {
-  if (c < 0) {
-    if (!per) return false;
-    c += n;
-  } else if (c >= n) {
-    if (!per) return false;
-    c -= n;
-  }
-  return true;
-}
-
-// Lucy kernel with support H (Eq. kernel), double precision
-__device__ __forceinline__ double lucy_w(double r, double H) {
-  if (r >= H) return 0.0;
-  double q = r / H;
-  double om = 1.0 - q;
-  return 105.0 / (16.0 * PI * H * H * H) * (1.0 + 3.0 * q) * om * om * om;
-}
 
 // ---------------------------------------------------------------------------
 // generic helpers
@@ -159,33 +76,6 @@ __global__ __launch_bounds__(BS) void k_bin_rigid(Dev d) {
 void launch_bin_rigid(const Dev& d, hipStream_t st) {
   if (d.nr == 0) return;
   k_bin_rigid<<<(d.nr + BS - 1) / BS, BS, 0, st>>>(d);
-}
-
-// Block-wide exclusive scan of one int per thread (wave64 shuffles + LDS).
-__device__ int block_exclusive_scan(int v, int* lds, int* total) {
-  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  int x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    int y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) lds[wid] = x;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int w = 0; w < BS / 64; ++w) {
-      int t = lds[w];
-      lds[w] = acc;
-      acc += t;
-    }
-    lds[BS / 64] = acc;
-  }
-  __syncthreads();
-  int res = x - v + lds[wid];
-  *total = lds[BS / 64];
-  __syncthreads();
-  return res;
 }
 
 static constexpr int SCAN_ITEMS = 8;
@@ -320,302 +210,36 @@ void launch_permute(const Dev& d, const D4* spos, const D4* svel, const D4* som,
 }
 
 // ---------------------------------------------------------------------------
-// (a2)+(a3) neighbour list fused with the density summation (Eq. compdens)
-// and the equation of state (Eq. prtcpres).  One thread per particle; the
-// 27-cell stencil is walked row by row, a row of three cells being one
-// contiguous slice of the sorted arrays unless it wraps.
+// Rigid particles in rigid-grid cell order: after the rigid counting sort,
+// copy position (+radius), velocity (+mass) and spin (+inertia) of every
+// rigid particle next to its cell neighbours, so the DEM and reaction
+// gathers read contiguous records.  Run at the start of every pass (the
+// velocities change between passes).
 
-__global__ __launch_bounds__(BS) void k_build_density(Dev d) {
-  int i = xcd_tid();
-  if (i >= d.n) return;
-  uint8_t ti = d.type[i];
-  if (ti == T_OUTER) {
-    d.nbr_cnt[i] = 0;
-    d.rho[i] = d.rho0;
-    d.p[i] = d.p_ref;
-    return;
-  }
-  D4 pi = d.pos[i];
-  int oob = 0;
-  int cx = cell_coord(pi.x, d.g, 0, &oob);
-  int cy = cell_coord(pi.y, d.g, 1, &oob);
-  int cz = cell_coord(pi.z, d.g, 2, &oob);
-  const double h = d.h, h2 = d.h2;
-  double acc = d.W0;
-  int cnt = 0;
-  const size_t npad = (size_t)d.npad;
-  for (int dz = -1; dz <= 1; ++dz) {
-    int z = cz + dz;
-    if (!wrap_axis(z, d.g.nc[2], d.g.per[2])) continue;
-    for (int dy = -1; dy <= 1; ++dy) {
-      int y = cy + dy;
-      if (!wrap_axis(y, d.g.nc[1], d.g.per[1])) continue;
-      // up to three x cells; a slice [c0, c1] of consecutive cells
-      int xs[3];
-      int nx = 0;
-      for (int dxx = -1; dxx <= 1; ++dxx) {
-        int x = cx + dxx;
-        if (wrap_axis(x, d.g.nc[0], d.g.per[0])) xs[nx++] = x;
-      }
-      int k = 0;
-      while (k < nx) {
-        int x0 = xs[k], x1 = xs[k];
-        while (k + 1 < nx && xs[k + 1] == x1 + 1) {
-          ++k;
-          x1 = xs[k];
-        }
-        ++k;
-        int jb = d.cstart[cell_index(d.g, x0, y, z)];
-        int je = d.cstart[cell_index(d.g, x1, y, z) + 1];
-        for (int j = jb; j < je; ++j) {
-          if (j == i) continue;
-          D4 pj = d.pos[j];
-          double ex = min_img(pi.x - pj.x, d.per[0], d.L[0], d.halfL[0]);
-          double ey = min_img(pi.y - pj.y, d.per[1], d.L[1], d.halfL[1]);
-          double ez = min_img(pi.z - pj.z, d.per[2], d.L[2], d.halfL[2]);
-          double r2 = r2_exact(ex, ey, ez);
-          if (r2 < h2) {
-            if (cnt < d.maxn) d.nbr[(size_t)cnt * npad + i] = j;
-            ++cnt;
-            double q = sqrt(r2) / h;
-            double om = 1.0 - q;
-            acc += d.w_norm * (1.0 + 3.0 * q) * om * om * om;
-          }
-        }
-      }
-    }
-  }
-  if (cnt > d.maxn) {
-    atomicOr(d.status, ST_NBR_OVERFLOW);
-    cnt = d.maxn;
-  }
-  d.nbr_cnt[i] = cnt;
-  double rho = d.cw_m * acc;
-  double p = d.p0 * pow(rho / d.rho0, d.alpha) - d.beta;
-  if (d.clamp && p < 0.0) p = 0.0;  // free-surface correction (Sec. 2.5)
-  d.rho[i] = rho;
-  d.p[i] = p;
+__global__ __launch_bounds__(BS) void k_rigid_gather(Dev d) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= d.nr) return;
+  int s = d.ritems[t];
+  int i = d.rig_sorted[s];
+  d.rpos_c[t] = d.pos[i];
+  d.rvel_c[t] = d.vel[i];
+  d.rom_c[t] = d.om[i];
+  d.rslot_pos[s] = t;
 }
 
-void launch_build_density(const Dev& d, hipStream_t st) {
-  k_build_density<<<nblocks(d.n), BS, 0, st>>>(d);
-}
-
-// (a4) Shepard filter of the pressure and the FP32 pair records:
-// v, p~/d^2 and spin, d = rho/m_f.
-__global__ __launch_bounds__(BS) void k_smooth(Dev d) {
-  int i = xcd_tid();
-  if (i >= d.n) return;
-  uint8_t ti = d.type[i];
-  double pi = d.p[i];
-  double ps = pi;
-  if (d.smooth && ti != T_OUTER) {
-    D4 xi = d.pos[i];
-    double num = pi * d.W0, den = d.W0;
-    int cnt = d.nbr_cnt[i];
-    const size_t npad = (size_t)d.npad;
-    for (int k = 0; k < cnt; ++k) {
-      int j = d.nbr[(size_t)k * npad + i];
-      D4 xj = d.pos[j];
-      double ex = min_img(xi.x - xj.x, d.per[0], d.L[0], d.halfL[0]);
-      double ey = min_img(xi.y - xj.y, d.per[1], d.L[1], d.halfL[1]);
-      double ez = min_img(xi.z - xj.z, d.per[2], d.L[2], d.halfL[2]);
-      double q = sqrt(ex * ex + ey * ey + ez * ez) / d.h;
-      double om = fmax(1.0 - q, 0.0);
-      double w = d.w_norm * (1.0 + 3.0 * q) * om * om * om;
-      num += d.p[j] * w;
-      den += w;
-    }
-    ps = num / den;
-  }
-  d.ps[i] = (float)ps;
-  double di = d.rho[i] / d.m_f;
-  D4 v = d.vel[i], w = d.om[i];
-  F4 vr, wr;
-  vr.x = (float)v.x;
-  vr.y = (float)v.y;
-  vr.z = (float)v.z;
-  vr.w = (float)(ps / (di * di));
-  wr.x = (float)w.x;
-  wr.y = (float)w.y;
-  wr.z = (float)w.z;
-  wr.w = (float)di;
-  d.vrec[i] = vr;
-  d.wrec[i] = wr;
-}
-
-void launch_smooth(const Dev& d, hipStream_t st) {
-  k_smooth<<<nblocks(d.n), BS, 0, st>>>(d);
-}
-
-// ---------------------------------------------------------------------------
-// (a5) SDPD+a pair forces, Eqs. FijC, FijD, FijR, FijT.
-
-// Philox4x32-10 (Salmon et al., SC'11): two 32x32 -> 64-bit products per
-// round with the published multipliers, Weyl key increments between rounds.
-__device__ __forceinline__ void philox10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
-                                         uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-    uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
-    uint32_t n0 = hi1 ^ c1 ^ k0;
-    uint32_t n2 = hi0 ^ c3 ^ k1;
-    c0 = n0;
-    c1 = lo1;
-    c2 = n2;
-    c3 = lo0;
-    k0 += 0x9E3779B9u;
-    k1 += 0xBB67AE85u;
-  }
-}
-
-__device__ __forceinline__ float u01(uint32_t x) {
-  return (float)((x >> 8) + 1u) * 5.9604644775390625e-8f;  // (0, 1], exact
-}
-
-// nine standard normals of the unordered pair {a, b} at a step; the tenth
-// Box-Muller output is not used
-__device__ __forceinline__ void pair_normals(uint32_t a, uint32_t b, uint32_t step, uint32_t k0,
-                                             uint32_t k1, float z[9]) {
-  uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
-  float u[12];
-#pragma unroll
-  for (uint32_t blk = 0; blk < 3; ++blk) {
-    uint32_t c0 = lo, c1 = hi, c2 = step, c3 = blk;
-    philox10(c0, c1, c2, c3, k0, k1);
-    u[4 * blk + 0] = u01(c0);
-    u[4 * blk + 1] = u01(c1);
-    u[4 * blk + 2] = u01(c2);
-    u[4 * blk + 3] = u01(c3);
-  }
-#pragma unroll
-  for (int m = 0; m < 5; ++m) {
-    float rad = sqrtf(-2.0f * logf(u[2 * m]));
-    float sn, cs;
-    sincospif(2.0f * u[2 * m + 1], &sn, &cs);
-    if (2 * m < 9) z[2 * m] = rad * cs;
-    if (2 * m + 1 < 9) z[2 * m + 1] = rad * sn;
-  }
-}
-
-template <bool NOISE>
-__global__ __launch_bounds__(BS) void k_fluid_forces(Dev d, uint32_t step) {
-  int i = xcd_tid();
-  if (i >= d.n) return;
-  uint8_t ti = d.type[i];
-  float F0 = 0.f, F1 = 0.f, F2 = 0.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, N0 = 0.f, N1 = 0.f, N2 = 0.f;
-  if (ti == T_FLUID || ti == T_INNER) {
-    const D4 pi = d.pos[i];
-    const F4 vi = d.vrec[i];
-    const F4 wi = d.wrec[i];
-    const uint32_t gi = NOISE ? (uint32_t)d.gid[i] : 0u;
-    const int cnt = d.nbr_cnt[i];
-    const size_t npad = (size_t)d.npad;
-    for (int k = 0; k < cnt; ++k) {
-      const int j = d.nbr[(size_t)k * npad + i];
-      const D4 pj = d.pos[j];
-      const F4 vj = d.vrec[j];
-      const F4 wj = d.wrec[j];
-      const double dx_ = min_img(pi.x - pj.x, d.per[0], d.L[0], d.halfL[0]);
-      const double dy_ = min_img(pi.y - pj.y, d.per[1], d.L[1], d.halfL[1]);
-      const double dz_ = min_img(pi.z - pj.z, d.per[2], d.L[2], d.halfL[2]);
-      const double r2d = dx_ * dx_ + dy_ * dy_ + dz_ * dz_;
-      const float rx = (float)dx_, ry = (float)dy_, rz = (float)dz_;
-      const float r = sqrtf((float)r2d);
-      const float inv_r = 1.0f / r;
-      const float ex = rx * inv_r, ey = ry * inv_r, ez = rz * inv_r;
-      // 1 - r/h = (h^2 - r^2) / (h (h + r)), the difference taken in FP64 so
-      // that pairs close to the cut-off keep full FP32 relative precision
-      const float omq = fmaxf((float)(d.h2 - r2d) * d.inv_hf / (d.hf + r), 0.0f);
-      const float Fk = d.cFf * omq * omq;  // F(r) = -W'(r)/r, Eq. F
-      // Pair force = along-e part + transverse part.  The torque takes the
-      // transverse part only: e x e = 0, and dropping the (often dominant)
-      // pressure term keeps the FP32 cross product free of cancellation.
-      // conservative force, Eq. FijC: (p_i/d_i^2 + p_j/d_j^2) F r_ij
-      const float pc = d.cC * ((vi.w + vj.w) * Fk);
-      // dissipative force, Eq. FijD: -ga v_ij - (ga + 2 gb)/3 (e.v_ij) e
-      const float fdd = Fk / (wi.w * wj.w);
-      const float ga = d.CAf * fdd, gb = d.CBf * fdd;
-      const float vx = vi.x - vj.x, vy = vi.y - vj.y, vz = vi.z - vj.z;
-      const float ev = ex * vx + ey * vy + ez * vz;
-      const float cde = -d.cD * (ga + 2.0f * gb) * ev * (1.0f / 3.0f);
-      const float cdv = -d.cD * ga;
-      float tx = cdv * vx, ty = cdv * vy, tz = cdv * vz;  // transverse-capable part
-      const float cx_ = pc * rx + cde * ex + tx;
-      const float cy_ = pc * ry + cde * ey + ty;
-      const float cz_ = pc * rz + cde * ez + tz;
-      C0 += cx_;
-      C1 += cy_;
-      C2 += cz_;
-      float fx = cx_, fy = cy_, fz = cz_;
-      // rotational force, Eq. FijR: -gamma^a (r_ij / 2) x (w_i + w_j)
-      const float sx = wi.x + wj.x, sy = wi.y + wj.y, sz = wi.z + wj.z;
-      const float gr = -d.cR * ga * 0.5f;
-      const float rrx = gr * (ry * sz - rz * sy);
-      const float rry = gr * (rz * sx - rx * sz);
-      const float rrz = gr * (rx * sy - ry * sx);
-      fx += rrx;
-      fy += rry;
-      fz += rrz;
-      tx += rrx;
-      ty += rry;
-      tz += rrz;
-      if (NOISE) {
-        // thermal force, Eq. FijT with dW^S = sym(dW) - tr(dW)/3
-        float z[9];
-        pair_normals(gi, (uint32_t)d.gid[j], step, d.key0, d.key1, z);
-        const float sa = 2.0f * sqrtf(d.kTf * ga);
-        const float sb = 2.0f * sqrtf(d.kTf * gb);
-        const float tr3 = (z[0] + z[4] + z[8]) * (1.0f / 3.0f);
-        const float s01 = 0.5f * (z[1] + z[3]), s02 = 0.5f * (z[2] + z[6]),
-                    s12 = 0.5f * (z[5] + z[7]);
-        const float se0 = (z[0] - tr3) * ex + s01 * ey + s02 * ez;
-        const float se1 = s01 * ex + (z[4] - tr3) * ey + s12 * ez;
-        const float se2 = s02 * ex + s12 * ey + (z[8] - tr3) * ez;
-        const float ca = d.cT * d.inv_sqrt_dtf * sa;
-        const float cb = d.cT * d.inv_sqrt_dtf * sb * tr3;
-        fx += ca * se0 + cb * ex;
-        fy += ca * se1 + cb * ey;
-        fz += ca * se2 + cb * ez;
-        tx += ca * se0;
-        ty += ca * se1;
-        tz += ca * se2;
-      }
-      F0 += fx;
-      F1 += fy;
-      F2 += fz;
-      // torque with the lever dx/2 along -e_ij (Sec. 2.6)
-      N0 -= d.leverf * (ey * tz - ez * ty);
-      N1 -= d.leverf * (ez * tx - ex * tz);
-      N2 -= d.leverf * (ex * ty - ey * tx);
-    }
-  }
-  const size_t np = (size_t)d.npad;
-  float* o = d.fout;
-  o[0 * np + i] = F0;
-  o[1 * np + i] = F1;
-  o[2 * np + i] = F2;
-  o[3 * np + i] = N0;
-  o[4 * np + i] = N1;
-  o[5 * np + i] = N2;
-  o[6 * np + i] = C0;
-  o[7 * np + i] = C1;
-  o[8 * np + i] = C2;
-}
-
-void launch_fluid_forces(const Dev& d, uint32_t step, bool noise, hipStream_t st) {
-  if (noise)
-    k_fluid_forces<true><<<nblocks(d.n), BS, 0, st>>>(d, step);
-  else
-    k_fluid_forces<false><<<nblocks(d.n), BS, 0, st>>>(d, step);
+void launch_rigid_gather(const Dev& d, hipStream_t st) {
+  if (d.nr == 0) return;
+  k_rigid_gather<<<(d.nr + BS - 1) / BS, BS, 0, st>>>(d);
 }
 
 // ---------------------------------------------------------------------------
 // (a6) fluid-particle action: one wavefront per rigid particle gathers the
 // fluid inside H_s = R_s + h (Sec. 2.4): Omega_s, the W-weighted fluid
 // velocity, the W-weighted F^C + F^D of the neighbours and the number of
-// other rigid centres inside H_s, then forms eps, F^DG and F^PG.
+// other rigid centres inside H_s, then forms eps, F^DG and F^PG.  The cell
+// rows of the search box are contiguous slices of the sorted arrays; the
+// wave walks their concatenation with one candidate per lane, and stamps
+// every fluid particle it couples to, so that the reaction visits only those.
 
 __device__ double drag_b(double eps, double dv, double dd, double rho, double mu) {
   // beta / (1 - eps) of the Ergun (eps <= 0.8) and Wen-Yu branches
@@ -653,7 +277,9 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
   const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
   if (wave >= d.nr) return;
-  const int si = d.rig_sorted[wave];
+  // spheres in rigid-grid cell order: neighbouring waves share cache lines
+  const int s = d.ritems[wave];
+  const int si = d.rig_sorted[s];
   const D4 ps = d.pos[si];
   const double R = ps.w, H = R + d.h, H2 = H * H;
   int oob = 0;
@@ -661,43 +287,71 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
               cell_coord(ps.z, d.g, 2, &oob)};
   int lo[3], cnt[3];
   for (int a = 0; a < 3; ++a) reach(d.g, a, c[a], H, lo[a], cnt[a]);
-  const int nrows = cnt[1] * cnt[2];
+  const int nbox = cnt[0] * cnt[1] * cnt[2];
   const size_t np = (size_t)d.npad;
   double om = 0, v0 = 0, v1 = 0, v2 = 0, f0 = 0, f1 = 0, f2 = 0;
   int nrig = 0;
-  for (int row = lane; row < nrows; row += 64) {
-    int z = lo[2] + row / cnt[1];
-    int y = lo[1] + row % cnt[1];
-    if (!wrap_axis(z, d.g.nc[2], d.g.per[2]) || !wrap_axis(y, d.g.nc[1], d.g.per[1])) continue;
-    for (int kx = 0; kx < cnt[0]; ++kx) {
-      int x = lo[0] + kx;
-      if (!wrap_axis(x, d.g.nc[0], d.g.per[0])) continue;
-      int cc = cell_index(d.g, x, y, z);
-      int jb = d.cstart[cc], je = d.cstart[cc + 1];
-      for (int j = jb; j < je; ++j) {
-        if (j == si) continue;
-        uint8_t tj = d.type[j];
-        if (tj != T_FLUID && tj != T_RIGID) continue;
-        D4 pj = d.pos[j];
-        double ex = min_img(ps.x - pj.x, d.per[0], d.L[0], d.halfL[0]);
-        double ey = min_img(ps.y - pj.y, d.per[1], d.L[1], d.halfL[1]);
-        double ez = min_img(ps.z - pj.z, d.per[2], d.L[2], d.halfL[2]);
-        double r2 = r2_exact(ex, ey, ez);
-        if (!(r2 < H2)) continue;
-        if (tj == T_RIGID) {
-          ++nrig;
-          continue;
-        }
-        double w = lucy_w(sqrt(r2), H);
-        D4 vj = d.vel[j];
-        om += w;
-        v0 += w * vj.x;
-        v1 += w * vj.y;
-        v2 += w * vj.z;
-        f0 += w * (double)d.fout[6 * np + j];
-        f1 += w * (double)d.fout[7 * np + j];
-        f2 += w * (double)d.fout[8 * np + j];
+  for (int cb = 0; cb < nbox; cb += 64) {
+    // lane r describes cell cb + r of the search box: one contiguous slice
+    int s0 = 0, l0 = 0;
+    int cidx = cb + lane;
+    if (cidx < nbox) {
+      int x = lo[0] + cidx % cnt[0];
+      int y = lo[1] + (cidx / cnt[0]) % cnt[1];
+      int z = lo[2] + cidx / (cnt[0] * cnt[1]);
+      if (wrap_axis(x, d.g.nc[0], d.g.per[0]) && wrap_axis(y, d.g.nc[1], d.g.per[1]) &&
+          wrap_axis(z, d.g.nc[2], d.g.per[2])) {
+        int key = cell_index(d.g, x, y, z);
+        s0 = d.cstart[key];
+        l0 = d.cstart[key + 1] - s0;
       }
+    }
+    int inc = l0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      int t = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += t;
+    }
+    const int total = __shfl(inc, 63, 64);
+    const int off = inc - l0;
+    // every lane takes one candidate of the concatenated slices per round;
+    // all lanes stay active through the shuffles
+    for (int base = 0; base < total; base += 64) {
+      const int t = base + lane;
+      int r = 0;  // last cell whose offset is <= t
+#pragma unroll
+      for (int stp = 32; stp > 0; stp >>= 1) {
+        int cand = r + stp;
+        int v = __shfl(off, cand & 63, 64);
+        if (cand < 64 && v <= t) r = cand;
+      }
+      const int offr = __shfl(off, r, 64);
+      const int s0r = __shfl(s0, r, 64);
+      if (t >= total) continue;
+      const int j = s0r + (t - offr);
+      if (j == si) continue;
+      uint8_t tj = d.type[j];
+      if (tj != T_FLUID && tj != T_RIGID) continue;
+      D4 pj = d.pos[j];
+      double ex = min_img(ps.x - pj.x, d.per[0], d.L[0], d.halfL[0]);
+      double ey = min_img(ps.y - pj.y, d.per[1], d.L[1], d.halfL[1]);
+      double ez = min_img(ps.z - pj.z, d.per[2], d.L[2], d.halfL[2]);
+      double r2 = r2_exact(ex, ey, ez);
+      if (!(r2 < H2)) continue;
+      if (tj == T_RIGID) {
+        ++nrig;
+        continue;
+      }
+      double w = lucy_w(sqrt(r2), H);
+      D4 vj = d.vel[j];
+      om += w;
+      v0 += w * vj.x;
+      v1 += w * vj.y;
+      v2 += w * vj.z;
+      f0 += w * (double)d.fout[6 * np + j];
+      f1 += w * (double)d.fout[7 * np + j];
+      f2 += w * (double)d.fout[8 * np + j];
+      d.cstamp[j] = d.stamp;
     }
   }
   om = wave_sum(om);
@@ -709,7 +363,6 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
   f2 = wave_sum(f2);
   nrig = wave_sum_i(nrig);
   if (lane != 0) return;
-  const int s = wave;
   const double Vs = 4.0 / 3.0 * PI * R * R * R;
   const double VH = 4.0 / 3.0 * PI * H * H * H;
   double eps = 1.0 - Vs * (double)nrig / VH;
@@ -732,6 +385,13 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
     d.f_dg[3 * s + a] = dg[a];
     d.f_pg[3 * s + a] = pg[a];
   }
+  // F^DG / Omega beside the sphere's cell-ordered record, for the reaction
+  D4 rc;
+  rc.x = om > 0.0 ? dg[0] / om : 0.0;
+  rc.y = om > 0.0 ? dg[1] / om : 0.0;
+  rc.z = om > 0.0 ? dg[2] / om : 0.0;
+  rc.w = om > 0.0 ? 1.0 : 0.0;
+  d.rdg_c[wave] = rc;
 }
 
 void launch_fpi_action(const Dev& d, hipStream_t st) {
@@ -740,18 +400,18 @@ void launch_fpi_action(const Dev& d, hipStream_t st) {
   k_fpi_action<<<(d.nr + waves_per_block - 1) / waves_per_block, BS, 0, st>>>(d);
 }
 
-// 27 cells of the rigid grid around a coordinate (all cells of a periodic
-// axis shorter than three cells, each once)
+// cells of the rigid grid (linear keys) within `k` cells of a coordinate
+// (each at most once on a periodic axis shorter than 2k+1 cells)
 template <class Fn>
-__device__ __forceinline__ void for_rigid_stencil(const Grid& G, int cx, int cy, int cz, Fn&& fn) {
-  int lo[3], cnt[3], cc[3] = {cx, cy, cz};
+__device__ __forceinline__ void for_rigid_stencil(const Grid& G, const int cc[3], int k, Fn&& fn) {
+  int lo[3], cnt[3];
   for (int a = 0; a < 3; ++a) {
-    if (G.per[a] && G.nc[a] < 3) {
+    if (G.per[a] && G.nc[a] < 2 * k + 1) {
       lo[a] = 0;
       cnt[a] = G.nc[a];
     } else {
-      lo[a] = cc[a] - 1;
-      cnt[a] = 3;
+      lo[a] = cc[a] - k;
+      cnt[a] = 2 * k + 1;
     }
   }
   for (int kz = 0; kz < cnt[2]; ++kz) {
@@ -760,47 +420,52 @@ __device__ __forceinline__ void for_rigid_stencil(const Grid& G, int cx, int cy,
     for (int ky = 0; ky < cnt[1]; ++ky) {
       int y = lo[1] + ky;
       if (!wrap_axis(y, G.nc[1], G.per[1])) continue;
-      for (int kx = 0; kx < cnt[0]; ++kx) {
-        int x = lo[0] + kx;
-        if (!wrap_axis(x, G.nc[0], G.per[0])) continue;
-        fn(cell_index(G, x, y, z));
+      int x0 = lo[0], x1 = lo[0] + cnt[0] - 1;
+      if (!G.per[0]) {
+        x0 = max(x0, 0);
+        x1 = min(x1, G.nc[0] - 1);
+        if (x0 <= x1) fn(cell_index(G, x0, y, z), cell_index(G, x1, y, z) + 1);
+      } else {
+        for (int kx = 0; kx < cnt[0]; ++kx) {
+          int x = lo[0] + kx;
+          wrap_axis(x, G.nc[0], 1);
+          fn(cell_index(G, x, y, z), cell_index(G, x, y, z) + 1);
+        }
       }
     }
   }
 }
 
-// (a7) reaction on each fluid particle, Eq. F_fpi_DG_reac normalised per
-// rigid particle: -sum_s F^DG_s w_sj / Omega_s over rigid s with j in C_s.
+// (a7) reaction on the stamped fluid particles, Eq. F_fpi_DG_reac
+// normalised per rigid particle: -sum_s F^DG_s w_sj / Omega_s over the
+// rigid s with j in C_s.  The rigid grid's cells are at least H_max wide.
 __global__ __launch_bounds__(BS) void k_fpi_reaction(Dev d) {
   int i = xcd_tid();
   if (i >= d.n) return;
+  if (d.cstamp[i] != d.stamp || d.type[i] != T_FLUID) return;
+  D4 pi = d.pos[i];
+  int oob = 0;
+  int cc[3] = {cell_coord(pi.x, d.rg, 0, &oob), cell_coord(pi.y, d.rg, 1, &oob),
+               cell_coord(pi.z, d.rg, 2, &oob)};
   double a0 = 0, a1 = 0, a2 = 0;
-  if (d.type[i] == T_FLUID) {
-    D4 pi = d.pos[i];
-    int oob = 0;
-    int cx = cell_coord(pi.x, d.rg, 0, &oob);
-    int cy = cell_coord(pi.y, d.rg, 1, &oob);
-    int cz = cell_coord(pi.z, d.rg, 2, &oob);
-    for_rigid_stencil(d.rg, cx, cy, cz, [&](int cell) {
-      int tb = d.rstart[cell], te = d.rstart[cell + 1];
-      for (int t = tb; t < te; ++t) {
-        int s = d.ritems[t];
-        double oms = d.omega[s];
-        if (!(oms > 0.0)) continue;
-        D4 ps = d.pos[d.rig_sorted[s]];
-        double H = ps.w + d.h;
-        double ex = min_img(ps.x - pi.x, d.per[0], d.L[0], d.halfL[0]);
-        double ey = min_img(ps.y - pi.y, d.per[1], d.L[1], d.halfL[1]);
-        double ez = min_img(ps.z - pi.z, d.per[2], d.L[2], d.halfL[2]);
-        double r2 = r2_exact(ex, ey, ez);
-        if (!(r2 < H * H)) continue;
-        double c = lucy_w(sqrt(r2), H) / oms;
-        a0 -= d.f_dg[3 * s + 0] * c;
-        a1 -= d.f_dg[3 * s + 1] * c;
-        a2 -= d.f_dg[3 * s + 2] * c;
-      }
-    });
-  }
+  for_rigid_stencil(d.rg, cc, 1, [&](int cb, int ce) {
+    int tb = d.rstart[cb], te = d.rstart[ce];
+    for (int t = tb; t < te; ++t) {
+      D4 g = d.rdg_c[t];
+      if (g.w == 0.0) continue;
+      D4 ps = d.rpos_c[t];
+      double H = ps.w + d.h;
+      double ex = min_img(ps.x - pi.x, d.per[0], d.L[0], d.halfL[0]);
+      double ey = min_img(ps.y - pi.y, d.per[1], d.L[1], d.halfL[1]);
+      double ez = min_img(ps.z - pi.z, d.per[2], d.L[2], d.halfL[2]);
+      double r2 = r2_exact(ex, ey, ez);
+      if (!(r2 < H * H)) continue;
+      double w = lucy_w(sqrt(r2), H);
+      a0 -= g.x * w;
+      a1 -= g.y * w;
+      a2 -= g.z * w;
+    }
+  });
   const size_t np = (size_t)d.npad;
   d.fout[9 * np + i] = (float)a0;
   d.fout[10 * np + i] = (float)a1;
@@ -813,34 +478,34 @@ void launch_fpi_reaction(const Dev& d, hipStream_t st) {
 
 // ---------------------------------------------------------------------------
 // (a8) DEM contacts (Sec. 2.2) and lubrication (Sec. 2.3), one thread per
-// rigid particle, FP64.  The contact table row of a particle holds partner
-// ids and tangential displacements; commit (second pass) writes the next
-// table: the updated history of every pair still in contact.
+// rigid particle, FP64, over the cell-ordered rigid records.  The contact
+// table row of a particle holds partner ids and tangential displacements;
+// commit (second pass) writes the next table: the updated history of
+// every pair still in contact.
 
-__global__ __launch_bounds__(BS) void k_dem(Dev d, int commit, int* nxt_cnt, int* nxt_partner,
-                                           double* nxt_dt) {
+static constexpr int DEM_BS = 64;
+
+__global__ __launch_bounds__(DEM_BS) void k_dem(Dev d, int commit, int* nxt_cnt,
+                                               int* nxt_partner, double* nxt_dt) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= d.nr) return;
-  const int si = d.rig_sorted[s];
-  const D4 ps = d.pos[si], vs = d.vel[si], ws = d.om[si];
+  const int me = d.rslot_pos[s];
+  const D4 ps = d.rpos_c[me], vs = d.rvel_c[me], ws = d.rom_c[me];
   const double Rs = ps.w, ms = vs.w;
   const double Di = (1.0 - d.nu * d.nu) / (d.E * PI);
   int oob = 0;
-  int cx = cell_coord(ps.x, d.rg, 0, &oob);
-  int cy = cell_coord(ps.y, d.rg, 1, &oob);
-  int cz = cell_coord(ps.z, d.rg, 2, &oob);
+  int cc[3] = {cell_coord(ps.x, d.rg, 0, &oob), cell_coord(ps.y, d.rg, 1, &oob),
+               cell_coord(ps.z, d.rg, 2, &oob)};
   const int mc = d.maxc;
   const int ocnt = d.ct_cnt[s];
   double F[3] = {0, 0, 0}, FL[3] = {0, 0, 0}, N[3] = {0, 0, 0};
   int ncnt = 0;
   int overflow = 0;
-  for_rigid_stencil(d.rg, cx, cy, cz, [&](int cell) {
-    int tb = d.rstart[cell], te = d.rstart[cell + 1];
+  for_rigid_stencil(d.rg, cc, d.dem_reach, [&](int cb, int ce) {
+    int tb = d.rstart[cb], te = d.rstart[ce];
     for (int t = tb; t < te; ++t) {
-      int k = d.ritems[t];
-      if (k == s) continue;
-      int sk = d.rig_sorted[k];
-      D4 pk = d.pos[sk];
+      if (t == me) continue;
+      D4 pk = d.rpos_c[t];
       double Rk = pk.w;
       double e0 = min_img(ps.x - pk.x, d.per[0], d.L[0], d.halfL[0]);
       double e1 = min_img(ps.y - pk.y, d.per[1], d.L[1], d.halfL[1]);
@@ -849,10 +514,10 @@ __global__ __launch_bounds__(BS) void k_dem(Dev d, int commit, int* nxt_cnt, int
       double reachk = Rs + Rk + d.h;
       if (!(L2 < reachk * reachk)) continue;
       double L = sqrt(L2);
-      D4 vk = d.vel[sk];
+      D4 vk = d.rvel_c[t];
       if (L < Rs + Rk) {
-        D4 wk = d.om[sk];
-        int gk = d.rig_gid[k];
+        D4 wk = d.rom_c[t];
+        int gk = d.rig_gid[d.ritems[t]];
         double dt0 = 0, dt1 = 0, dt2 = 0;
         for (int q = 0; q < ocnt; ++q) {
           if (d.ct_partner[s * mc + q] == gk) {
@@ -954,7 +619,7 @@ __global__ __launch_bounds__(BS) void k_dem(Dev d, int commit, int* nxt_cnt, int
 void launch_dem(const Dev& d, int commit, int* nxt_cnt, int* nxt_partner, double* nxt_dt,
                 hipStream_t st) {
   if (d.nr == 0) return;
-  k_dem<<<(d.nr + BS - 1) / BS, BS, 0, st>>>(d, commit, nxt_cnt, nxt_partner, nxt_dt);
+  k_dem<<<(d.nr + DEM_BS - 1) / DEM_BS, DEM_BS, 0, st>>>(d, commit, nxt_cnt, nxt_partner, nxt_dt);
 }
 
 // ---------------------------------------------------------------------------
@@ -972,7 +637,7 @@ __device__ __forceinline__ void total_force(const Dev& d, int i, uint8_t t, cons
   for (int a = 0; a < 3; ++a) {
     double body = m * d.body[a] * sg;
     if (t == T_FLUID) {
-      double rx = d.have_rxn ? (double)d.fout[(9 + a) * np + i] : 0.0;
+      double rx = (d.have_rxn && d.cstamp[i] == d.stamp) ? (double)d.fout[(9 + a) * np + i] : 0.0;
       F[a] = (double)d.fout[a * np + i] + rx + body;
       N[a] = (double)d.fout[(3 + a) * np + i];
     } else if (t == T_INNER) {
@@ -1108,7 +773,7 @@ __global__ __launch_bounds__(BS) void k_read_field(Dev d, int field, int rigid_a
     case SDPDEM_F_CD:
     case SDPDEM_F_RXN: {
       int base = field == SDPDEM_F_SDPD ? 0 : field == SDPDEM_N_SDPD ? 3 : field == SDPDEM_F_CD ? 6 : 9;
-      if (field != SDPDEM_F_RXN || d.have_rxn)
+      if (field != SDPDEM_F_RXN || (d.have_rxn && d.cstamp[i] == d.stamp))
         for (int a = 0; a < 3; ++a) v[a] = (double)d.fout[(base + a) * np + i];
     } break;
     case SDPDEM_F_DG:
