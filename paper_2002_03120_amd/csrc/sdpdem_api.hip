@@ -31,8 +31,6 @@ struct sdpdem_system {
   double* field_buf;
   double* tot_part;
   double* tot_out;
-  int* brank;
-  int* brick_of_rank;
   int64_t step = 0;
   bool cache_valid = false;
   bool noise = false;
@@ -110,8 +108,7 @@ bool valid_particles(const sdpdem_particles* q, std::vector<int>* slot_of, int* 
 
 // Cell grid: periodic axes are split into floor(L/cs0) equal cells; wall
 // axes cover the domain and every particle with one cell of slack.
-bool make_grid(const sdpdem_params& P, const sdpdem_particles& q, double cs0, int brick,
-               Grid& g) {
+bool make_grid(const sdpdem_params& P, const sdpdem_particles& q, double cs0, Grid& g) {
   double total = 1.0;
   for (int a = 0; a < 3; ++a) {
     g.per[a] = P.periodic[a] ? 1 : 0;
@@ -138,12 +135,8 @@ bool make_grid(const sdpdem_params& P, const sdpdem_particles& q, double cs0, in
     g.inv_cs[a] = 1.0 / g.cs[a];
     total *= g.nc[a];
   }
-  g.brick = brick;
-  for (int a = 0; a < 3; ++a) g.nb[a] = (g.nc[a] + 3) / 4;
-  double keys = brick ? 64.0 * g.nb[0] * g.nb[1] * g.nb[2] : total;
-  if (keys > 1.0e9) return false;
-  g.ncells = brick ? 64 * g.nb[0] * g.nb[1] * g.nb[2] : g.nc[0] * g.nc[1] * g.nc[2];
-  g.nbricks = g.nb[0] * g.nb[1] * g.nb[2];
+  if (total > 1.0e9) return false;
+  g.ncells = g.nc[0] * g.nc[1] * g.nc[2];
   return true;
 }
 
@@ -168,30 +161,7 @@ struct Sizes {
   int maxn, maxc;
   int dem_reach = 1;
   Grid g, rg;
-  std::vector<int> brank;  // Morton rank of every brick of the main grid
 };
-
-uint64_t spread3(uint64_t v) {  // bits of v at every third position
-  uint64_t r = 0;
-  for (int b = 0; b < 21; ++b) r |= ((v >> b) & 1u) << (3 * b);
-  return r;
-}
-
-// rank of every brick along the Morton curve of its brick coordinates
-std::vector<int> morton_ranks(const Grid& g) {
-  const int n0 = g.nb[0], n1 = g.nb[1], n2 = g.nb[2];
-  std::vector<std::pair<uint64_t, int>> code((size_t)n0 * n1 * n2);
-  for (int z = 0; z < n2; ++z)
-    for (int y = 0; y < n1; ++y)
-      for (int x = 0; x < n0; ++x) {
-        int lin = (z * n1 + y) * n0 + x;
-        code[(size_t)lin] = {spread3(x) | (spread3(y) << 1) | (spread3(z) << 2), lin};
-      }
-  std::sort(code.begin(), code.end());
-  std::vector<int> rank(code.size());
-  for (size_t r = 0; r < code.size(); ++r) rank[(size_t)code[r].second] = (int)r;
-  return rank;
-}
 
 // Carve the workspace (base == nullptr: only measure it).
 size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
@@ -209,11 +179,7 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
   int* cursor = b.take<int>(nc);
   int* perm = b.take<int>(np);
   int* bsum = b.take<int>((size_t)scan_block_sums_size((int)nc) + 1);
-  int* brank = b.take<int>(z.brank.size());
-  int* brick_of_rank = b.take<int>(z.brank.size());
-  int* ovf_list = b.take<int>(3 * z.brank.size());
-  int* ovf_cnt = b.take<int>(16);
-  uint16_t* nbr16 = b.take<uint16_t>((size_t)z.maxn * np);
+  int* nbr = b.take<int>((size_t)z.maxn * np);
   int* nbr_cnt = b.take<int>(np);
   double* rho = b.take<double>(np);
   double* p = b.take<double>(np);
@@ -269,8 +235,6 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
     s->ct_dt[0] = ctd0;
     s->ct_dt[1] = ctd1;
     s->block_sums = bsum;
-    s->brank = brank;
-    s->brick_of_rank = brick_of_rank;
     s->rblock_sums = rbsum;
     s->field_buf = field_buf;
     s->tot_part = tot_part;
@@ -281,9 +245,7 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
     d.cstart = cstart;
     d.cursor = cursor;
     d.perm = perm;
-    d.nbr16 = nbr16;
-    d.ovf_list = ovf_list;
-    d.ovf_cnt = ovf_cnt;
+    d.nbr = nbr;
     d.nbr_cnt = nbr_cnt;
     d.rho = rho;
     d.p = p;
@@ -328,14 +290,13 @@ bool plan(const sdpdem_params* P, const sdpdem_particles* q, Sizes& z,
   z.nr = nr;
   z.maxn = P->max_neighbors;
   z.maxc = P->max_contacts;
-  if (!make_grid(*P, *q, P->h * (1.0 + 1e-6), 1, z.g)) return false;
-  z.brank = morton_ranks(z.g);
+  if (!make_grid(*P, *q, P->h * (1.0 + 1e-6), z.g)) return false;
   for (int a = 0; a < 3; ++a)
     if (P->periodic[a] && z.g.nc[a] < 3) return false;
   // rigid grid: cells at least H_max = R_max + h wide, so that the fluid
   // particles coupled to a sphere lie in its 27 neighbouring cells
   double rcs = (rmax + P->h) * (1.0 + 1e-6);
-  if (!make_grid(*P, *q, rcs, 0, z.rg)) return false;
+  if (!make_grid(*P, *q, rcs, z.rg)) return false;
   // DEM partners lie within R_s + R_k + h <= 2 R_max + h
   double mincs = std::min(z.rg.cs[0], std::min(z.rg.cs[1], z.rg.cs[2]));
   z.dem_reach = std::max(1, (int)std::ceil((2.0 * rmax + P->h) / mincs * (1.0 + 1e-9)));
@@ -410,10 +371,7 @@ void fill_constants(sdpdem_system* s, const Sizes& z) {
   d.key0 = (uint32_t)(P.seed & 0xffffffffu);
   d.key1 = (uint32_t)(P.seed >> 32);
   d.g = z.g;
-  d.g.brank = s->brank;
-  d.brick_of_rank = s->brick_of_rank;
   d.rg = z.rg;
-  d.rg.brank = nullptr;
   d.dem_reach = z.dem_reach;
   d.stamp = 0;
   s->noise = P.kBT > 0.0 && P.coeff_t != 0.0;
@@ -667,10 +625,6 @@ int sdpdem_create(const sdpdem_params* params, const sdpdem_particles* q, void* 
   ok &= hipMemcpyAsync(s->type[0], ht.data(), n, hipMemcpyHostToDevice, st) == hipSuccess;
   ok &= hipMemcpyAsync(s->gid[0], hg.data(), sizeof(int) * n, hipMemcpyHostToDevice, st) == hipSuccess;
   ok &= hipMemcpyAsync(d.gid2slot, slot_of.data(), sizeof(int) * n, hipMemcpyHostToDevice, st) == hipSuccess;
-  std::vector<int> inv(z.brank.size());
-  for (size_t b = 0; b < z.brank.size(); ++b) inv[(size_t)z.brank[b]] = (int)b;
-  ok &= hipMemcpyAsync(s->brank, z.brank.data(), sizeof(int) * z.brank.size(), hipMemcpyHostToDevice, st) == hipSuccess;
-  ok &= hipMemcpyAsync(s->brick_of_rank, inv.data(), sizeof(int) * inv.size(), hipMemcpyHostToDevice, st) == hipSuccess;
   if (z.nr) {
     ok &= hipMemcpyAsync(d.rig_gid, hrg.data(), sizeof(int) * z.nr, hipMemcpyHostToDevice, st) == hipSuccess;
     ok &= hipMemcpyAsync(d.rig_sorted, hsort.data(), sizeof(int) * z.nr, hipMemcpyHostToDevice, st) == hipSuccess;

@@ -66,15 +66,7 @@ __device__ __forceinline__ int cell_coord(double x, const Grid& g, int a, int* o
 }
 
 __device__ __forceinline__ int cell_index(const Grid& g, int cx, int cy, int cz) {
-  if (g.brick)
-    return g.brank[((cz >> 2) * g.nb[1] + (cy >> 2)) * g.nb[0] + (cx >> 2)] * 64 +
-           (((cz & 3) * 4 + (cy & 3)) * 4 + (cx & 3));
   return (cz * g.nc[1] + cy) * g.nc[0] + cx;
-}
-
-// cells x and x + 1 of a row have consecutive keys
-__device__ __forceinline__ bool x_contiguous(const Grid& g, int x) {
-  return !g.brick || (x & 3) != 3;
 }
 
 // wrap (periodic) or reject (wall) a neighbour cell coordinate

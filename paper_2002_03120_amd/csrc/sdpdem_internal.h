@@ -28,22 +28,15 @@ struct __align__(16) F4 {
 };
 
 // A uniform cell grid.  Periodic axes span [org, org+L) with nc >= 3 cells;
-// wall axes span the particle bounding box plus one cell of slack.
-// Keys order the cells either linearly (x fastest) or brick-major: 4x4x4
-// bricks ranked along a Morton (Z-order) curve, cells linear inside a
-// brick, so that a cell's 3x3x3 neighbourhood lies in a few compact runs of
-// the sorted arrays and neighbouring bricks are processed close in time.
+// wall axes span the particle bounding box plus one cell of slack.  Cell
+// keys are linear, x fastest.
 struct Grid {
   double lo[3];
   double cs[3];
   double inv_cs[3];
   int nc[3];
   int per[3];
-  int brick;         // 1: brick-major keys
-  int nb[3];         // bricks per axis (brick-major keys)
-  const int* brank;  // brick (linear index) -> rank on the Morton curve
-  int ncells;        // number of keys (padded to whole bricks when brick-major)
-  int nbricks;       // bricks (brick-major keys)
+  int ncells;
 };
 
 // Everything a kernel reads, passed by value.  Particle arrays are in the
@@ -86,14 +79,7 @@ struct Dev {
   int* cursor;
   int* perm;
   // neighbours and fields
-  // neighbour k of particle i at k*npad + i: its slot in the footprint tile
-  // of i's brick (see the tile kernels)
-  uint16_t* nbr16;
-  const int* brick_of_rank;
-  // bricks deferred by the LDS tile kernels (three lists of nbricks) and
-  // their counters
-  int* ovf_list;
-  int* ovf_cnt;
+  int* nbr;  // [maxn * npad], neighbour k of particle i at k*npad + i
   int* nbr_cnt;
   double* rho;
   double* p;

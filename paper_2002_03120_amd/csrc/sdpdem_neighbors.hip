@@ -1,0 +1,277 @@
+// sdpdem_neighbors.hip -- neighbour build with density, pressure filter and
+// SDPD pair forces: one thread per particle in cell-sorted order, blocks
+// mapped to XCDs in contiguous chunks, neighbour data gathered through L1/L2
+// (the sorted order keeps a wave's neighbourhood compact).
+#include "sdpdem_device.h"
+
+namespace sdpdem {
+
+// ---------------------------------------------------------------------------
+// (a2)+(a3) neighbour sets {j : r_ij^2 < h^2} (double precision, no
+// contraction) fused with the density summation (Eq. compdens), the
+// equation of state (Eq. prtcpres) and the free-surface clamp.  The
+// 27-cell stencil is walked row by row; three cells of a row are one
+// contiguous slice of the sorted arrays unless the row wraps.
+
+__global__ __launch_bounds__(BS) void k_build_density(Dev d) {
+  int i = xcd_tid();
+  if (i >= d.n) return;
+  uint8_t ti = d.type[i];
+  if (ti == T_OUTER) {
+    d.nbr_cnt[i] = 0;
+    d.rho[i] = d.rho0;
+    d.p[i] = d.p_ref;
+    return;
+  }
+  const D4 pi = d.pos[i];
+  int oob = 0;
+  const int cx = cell_coord(pi.x, d.g, 0, &oob);
+  const int cy = cell_coord(pi.y, d.g, 1, &oob);
+  const int cz = cell_coord(pi.z, d.g, 2, &oob);
+  const double h = d.h, h2 = d.h2;
+  double acc = d.W0;
+  int cnt = 0;
+  const size_t npad = (size_t)d.npad;
+  for (int dz = -1; dz <= 1; ++dz) {
+    int z = cz + dz;
+    if (!wrap_axis(z, d.g.nc[2], d.g.per[2])) continue;
+    for (int dy = -1; dy <= 1; ++dy) {
+      int y = cy + dy;
+      if (!wrap_axis(y, d.g.nc[1], d.g.per[1])) continue;
+      int xs[3];
+      int nx = 0;
+      for (int dxx = -1; dxx <= 1; ++dxx) {
+        int x = cx + dxx;
+        if (wrap_axis(x, d.g.nc[0], d.g.per[0])) xs[nx++] = x;
+      }
+      int k = 0;
+      while (k < nx) {  // maximal runs of consecutive cells
+        int x0 = xs[k], x1 = xs[k];
+        while (k + 1 < nx && xs[k + 1] == x1 + 1) {
+          ++k;
+          x1 = xs[k];
+        }
+        ++k;
+        const int jb = d.cstart[cell_index(d.g, x0, y, z)];
+        const int je = d.cstart[cell_index(d.g, x1, y, z) + 1];
+        for (int j = jb; j < je; ++j) {
+          if (j == i) continue;
+          const D4 pj = d.pos[j];
+          const double ex = min_img(pi.x - pj.x, d.per[0], d.L[0], d.halfL[0]);
+          const double ey = min_img(pi.y - pj.y, d.per[1], d.L[1], d.halfL[1]);
+          const double ez = min_img(pi.z - pj.z, d.per[2], d.L[2], d.halfL[2]);
+          const double r2 = r2_exact(ex, ey, ez);
+          if (r2 < h2) {
+            if (cnt < d.maxn) d.nbr[(size_t)cnt * npad + i] = j;
+            ++cnt;
+            const double q = sqrt(r2) / h;
+            const double om = 1.0 - q;
+            acc += d.w_norm * (1.0 + 3.0 * q) * om * om * om;
+          }
+        }
+      }
+    }
+  }
+  if (cnt > d.maxn) {
+    atomicOr(d.status, ST_NBR_OVERFLOW);
+    cnt = d.maxn;
+  }
+  d.nbr_cnt[i] = cnt;
+  const double rho = d.cw_m * acc;
+  double p = d.p0 * pow(rho / d.rho0, d.alpha) - d.beta;
+  if (d.clamp && p < 0.0) p = 0.0;  // free-surface correction (Sec. 2.5)
+  d.rho[i] = rho;
+  d.p[i] = p;
+}
+
+void launch_build_density(const Dev& d, hipStream_t st) {
+  k_build_density<<<nblocks(d.n), BS, 0, st>>>(d);
+}
+
+// ---------------------------------------------------------------------------
+// (a4) Shepard filter of the pressure and the FP32 pair records
+// (v, c_C p~/d^2; spin, 1/d with d = rho/m_f).
+
+__global__ __launch_bounds__(BS) void k_smooth(Dev d) {
+  int i = xcd_tid();
+  if (i >= d.n) return;
+  const uint8_t ti = d.type[i];
+  const double pi = d.p[i];
+  double ps = pi;
+  if (d.smooth && ti != T_OUTER) {
+    const D4 xi = d.pos[i];
+    double num = pi * d.W0, den = d.W0;
+    const int cnt = d.nbr_cnt[i];
+    const size_t npad = (size_t)d.npad;
+    const double inv_h = 1.0 / d.h;
+    for (int k = 0; k < cnt; ++k) {
+      const int j = d.nbr[(size_t)k * npad + i];
+      const D4 xj = d.pos[j];
+      const double ex = min_img(xi.x - xj.x, d.per[0], d.L[0], d.halfL[0]);
+      const double ey = min_img(xi.y - xj.y, d.per[1], d.L[1], d.halfL[1]);
+      const double ez = min_img(xi.z - xj.z, d.per[2], d.L[2], d.halfL[2]);
+      const double q = sqrt(ex * ex + ey * ey + ez * ez) * inv_h;
+      const double om = fmax(1.0 - q, 0.0);
+      const double w = d.w_norm * (1.0 + 3.0 * q) * om * om * om;
+      num += d.p[j] * w;
+      den += w;
+    }
+    ps = num / den;
+  }
+  d.ps[i] = (float)ps;
+  const double di = d.rho[i] / d.m_f;
+  const D4 v = d.vel[i], w = d.om[i];
+  F4 vr, wr;
+  vr.x = (float)v.x;
+  vr.y = (float)v.y;
+  vr.z = (float)v.z;
+  vr.w = (float)(d.coef_c * ps / (di * di));
+  wr.x = (float)w.x;
+  wr.y = (float)w.y;
+  wr.z = (float)w.z;
+  wr.w = (float)(1.0 / di);
+  d.vrec[i] = vr;
+  d.wrec[i] = wr;
+}
+
+void launch_smooth(const Dev& d, hipStream_t st) {
+  k_smooth<<<nblocks(d.n), BS, 0, st>>>(d);
+}
+
+// ---------------------------------------------------------------------------
+// (a5) SDPD+a pair forces, Eqs. FijC, FijD, FijR, FijT, for fluid and
+// inner-wall particles: FP32 math on FP64-differenced separations, FP32
+// per-particle sums; outputs F^SDPD, its torque and the F^C + F^D sum.
+
+template <bool NOISE>
+__global__ __launch_bounds__(BS) void k_fluid_forces(Dev d, uint32_t step) {
+  const int i = xcd_tid();
+  if (i >= d.n) return;
+  const uint8_t ti = d.type[i];
+  float F0 = 0.f, F1 = 0.f, F2 = 0.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, N0 = 0.f, N1 = 0.f, N2 = 0.f;
+  if (ti == T_FLUID || ti == T_INNER) {
+    const D4 pi = d.pos[i];
+    const F4 vi = d.vrec[i];
+    const F4 wi = d.wrec[i];
+    const uint32_t gi = NOISE ? (uint32_t)d.gid[i] : 0u;
+    const int cnt = d.nbr_cnt[i];
+    const int* nb = d.nbr + i;
+    const size_t npad = (size_t)d.npad;
+    for (int k = 0; k < cnt; ++k) {
+      const int j = nb[(size_t)k * npad];
+      const D4 pj = d.pos[j];
+      const F4 vj = d.vrec[j];
+      const F4 wj = d.wrec[j];
+      const double dx_ = min_img(pi.x - pj.x, d.per[0], d.L[0], d.halfL[0]);
+      const double dy_ = min_img(pi.y - pj.y, d.per[1], d.L[1], d.halfL[1]);
+      const double dz_ = min_img(pi.z - pj.z, d.per[2], d.L[2], d.halfL[2]);
+      const double r2d = dx_ * dx_ + dy_ * dy_ + dz_ * dz_;
+      const float rx = (float)dx_, ry = (float)dy_, rz = (float)dz_;
+      const float inv_r = __builtin_amdgcn_rsqf((float)r2d);
+      const float r = (float)r2d * inv_r;
+      const float ex = rx * inv_r, ey = ry * inv_r, ez = rz * inv_r;
+      // 1 - r/h = (h^2 - r^2) / (h (h + r)), the difference taken in FP64 so
+      // that pairs close to the cut-off keep full FP32 relative precision
+      const float omq =
+          fmaxf((float)(d.h2 - r2d) * d.inv_hf * __builtin_amdgcn_rcpf(d.hf + r), 0.0f);
+      const float Fk = d.cFf * omq * omq;  // F(r) = -W'(r)/r, Eq. F
+      // Pair force = along-e part + transverse part.  The torque takes the
+      // transverse part only (e x e = 0), which keeps the FP32 cross product
+      // free of the cancellation of the dominant pressure term.
+      // conservative force, Eq. FijC: (p_i/d_i^2 + p_j/d_j^2) F r_ij
+      const float pc = (vi.w + vj.w) * Fk;
+      // F / (d_i d_j): the two inverse densities multiply symmetrically so
+      // that F_ji = -F_ij holds bit for bit
+      const float fdd = Fk * (wi.w * wj.w);
+      // dissipative force, Eq. FijD: -ga v_ij - (ga + 2 gb)/3 (e.v_ij) e
+      const float vx = vi.x - vj.x, vy = vi.y - vj.y, vz = vi.z - vj.z;
+      const float ev = ex * vx + ey * vy + ez * vz;
+      const float cde = d.kBf * fdd * ev;
+      const float cdv = d.kAf * fdd;
+      float tx = cdv * vx, ty = cdv * vy, tz = cdv * vz;
+      const float cx_ = pc * rx + cde * ex + tx;
+      const float cy_ = pc * ry + cde * ey + ty;
+      const float cz_ = pc * rz + cde * ez + tz;
+      C0 += cx_;
+      C1 += cy_;
+      C2 += cz_;
+      // rotational force, Eq. FijR: -gamma^a (r_ij / 2) x (w_i + w_j)
+      const float sx = wi.x + wj.x, sy = wi.y + wj.y, sz = wi.z + wj.z;
+      const float gr = d.kRf * fdd;
+      const float rrx = gr * (ry * sz - rz * sy);
+      const float rry = gr * (rz * sx - rx * sz);
+      const float rrz = gr * (rx * sy - ry * sx);
+      float fx = cx_ + rrx, fy = cy_ + rry, fz = cz_ + rrz;
+      tx += rrx;
+      ty += rry;
+      tz += rrz;
+      if (NOISE) {
+        // thermal force, Eq. FijT with dW^S = sym(dW) - tr(dW)/3
+        float z[9];
+        pair_normals(gi, (uint32_t)d.gid[j], step, d.key0, d.key1, z);
+        const float sa = 2.0f * sqrtf(d.kTf * d.CAf * fdd);
+        const float sb = 2.0f * sqrtf(d.kTf * d.CBf * fdd);
+        const float tr3 = (z[0] + z[4] + z[8]) * (1.0f / 3.0f);
+        const float s01 = 0.5f * (z[1] + z[3]), s02 = 0.5f * (z[2] + z[6]),
+                    s12 = 0.5f * (z[5] + z[7]);
+        const float se0 = (z[0] - tr3) * ex + s01 * ey + s02 * ez;
+        const float se1 = s01 * ex + (z[4] - tr3) * ey + s12 * ez;
+        const float se2 = s02 * ex + s12 * ey + (z[8] - tr3) * ez;
+        const float ca = d.cT * d.inv_sqrt_dtf * sa;
+        const float cb = d.cT * d.inv_sqrt_dtf * sb * tr3;
+        fx += ca * se0 + cb * ex;
+        fy += ca * se1 + cb * ey;
+        fz += ca * se2 + cb * ez;
+        tx += ca * se0;
+        ty += ca * se1;
+        tz += ca * se2;
+      }
+      F0 += fx;
+      F1 += fy;
+      F2 += fz;
+      // torque: lever dx/2 along -e_ij (Sec. 2.6), lever applied below
+      N0 += ey * tz - ez * ty;
+      N1 += ez * tx - ex * tz;
+      N2 += ex * ty - ey * tx;
+    }
+    N0 *= -d.leverf;
+    N1 *= -d.leverf;
+    N2 *= -d.leverf;
+  }
+  const size_t np = (size_t)d.npad;
+  float* o = d.fout;
+  o[0 * np + i] = F0;
+  o[1 * np + i] = F1;
+  o[2 * np + i] = F2;
+  o[3 * np + i] = N0;
+  o[4 * np + i] = N1;
+  o[5 * np + i] = N2;
+  o[6 * np + i] = C0;
+  o[7 * np + i] = C1;
+  o[8 * np + i] = C2;
+}
+
+void launch_fluid_forces(const Dev& d, uint32_t step, bool noise, hipStream_t st) {
+  if (noise)
+    k_fluid_forces<true><<<nblocks(d.n), BS, 0, st>>>(d, step);
+  else
+    k_fluid_forces<false><<<nblocks(d.n), BS, 0, st>>>(d, step);
+}
+
+// neighbour columns k0..k0+kn-1 as ids (-1 past a row's end), for export
+__global__ __launch_bounds__(BS) void k_nbr_cols(Dev d, int k0, int kn, int* out) {
+  const int i = xcd_tid();
+  if (i >= d.n) return;
+  const int cnt = d.nbr_cnt[i];
+  const size_t np = (size_t)d.npad;
+  for (int k = 0; k < kn; ++k) {
+    const int kk = k0 + k;
+    out[(size_t)k * np + i] = kk < cnt ? d.gid[d.nbr[(size_t)kk * np + i]] : -1;
+  }
+}
+
+void launch_nbr_cols(const Dev& d, int k0, int kn, int* out, hipStream_t st) {
+  k_nbr_cols<<<nblocks(d.n), BS, 0, st>>>(d, k0, kn, out);
+}
+
+}  // namespace sdpdem
