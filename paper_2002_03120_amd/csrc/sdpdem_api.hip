@@ -184,8 +184,7 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
   double* rho = b.take<double>(np);
   double* p = b.take<double>(np);
   float* ps = b.take<float>(np);
-  F4* vrec = b.take<F4>(np);
-  F4* wrec = b.take<F4>(np);
+  PR* prec = b.take<PR>(np);
   float* fout = b.take<float>(12 * np);
   int* gid2slot = b.take<int>(np);
   int* rig_sorted = b.take<int>(nr);
@@ -250,8 +249,7 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
     d.rho = rho;
     d.p = p;
     d.ps = ps;
-    d.vrec = vrec;
-    d.wrec = wrec;
+    d.prec = prec;
     d.fout = fout;
     d.gid2slot = gid2slot;
     d.rig_sorted = rig_sorted;
@@ -322,6 +320,7 @@ void fill_constants(sdpdem_system* s, const Sizes& z) {
   d.noslip = P.noslip;
   d.h = P.h;
   d.h2 = P.h * P.h;
+  d.inv_h = 1.0 / P.h;
   d.dx = P.dx;
   d.lever = 0.5 * P.dx;
   d.rho0 = P.rho0;

@@ -27,6 +27,19 @@ struct __align__(16) F4 {
   float x, y, z, w;
 };
 
+// Pair record of one particle for the SDPD force pass, 64 bytes (half a
+// cache line, four 16-byte loads): FP64 position, FP32 velocity,
+// c_C p~/d^2, spin, 1/d with d = rho/m_f, and the id.  Written with the
+// pressure filter after every neighbour build; the velocity and spin are
+// refreshed after the second half-kick.
+struct __align__(64) PR {
+  double x, y, z;
+  float vx, vy, vz, pc;
+  float wx, wy, wz, invd;
+  int gid, pad;
+};
+static_assert(sizeof(PR) == 64, "pair record must be 64 bytes");
+
 // A uniform cell grid.  Periodic axes span [org, org+L) with nc >= 3 cells;
 // wall axes span the particle bounding box plus one cell of slack.  Cell
 // keys are linear, x fastest.
@@ -49,7 +62,7 @@ struct Dev {
   double org[3], L[3], halfL[3];
   int per[3];
   int noslip;
-  double h, h2, dx, lever;
+  double h, h2, inv_h, dx, lever;
   double rho0, p0, alpha, beta, p_ref, m_f, I_f;
   double cw_m;    // C_W * m_f, density per unit kernel sum
   double w_norm;  // 105 / (16 pi h^3)
@@ -84,8 +97,7 @@ struct Dev {
   double* rho;
   double* p;
   float* ps;
-  F4* vrec;  // FP32 vx, vy, vz, c_C p~/d^2
-  F4* wrec;  // FP32 wx, wy, wz, 1/d with d = rho/m_f
+  PR* prec;  // pair records, sorted order
   float* fout;  // 12 planes of npad: F_sdpd(3) N_sdpd(3) F_cd(3) F_rxn(3)
   // rigid
   int* gid2slot;

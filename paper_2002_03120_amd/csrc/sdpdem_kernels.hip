@@ -709,16 +709,14 @@ __global__ __launch_bounds__(BS) void k_integrate(Dev d, int velver, int rigid_a
   d.vel[i] = v;
   d.om[i] = w;
   if (velver == 2) {
-    // positions did not move: refresh the FP32 records for the next pass
-    F4 vr = d.vrec[i], wr = d.wrec[i];
-    vr.x = (float)v.x;
-    vr.y = (float)v.y;
-    vr.z = (float)v.z;
-    wr.x = (float)w.x;
-    wr.y = (float)w.y;
-    wr.z = (float)w.z;
-    d.vrec[i] = vr;
-    d.wrec[i] = wr;
+    // positions did not move: refresh the pair record for the next pass
+    PR* r = d.prec + i;
+    r->vx = (float)v.x;
+    r->vy = (float)v.y;
+    r->vz = (float)v.z;
+    r->wx = (float)w.x;
+    r->wy = (float)w.y;
+    r->wz = (float)w.z;
   }
 }
 

@@ -28,10 +28,11 @@ __global__ __launch_bounds__(BS) void k_build_density(Dev d) {
   const int cx = cell_coord(pi.x, d.g, 0, &oob);
   const int cy = cell_coord(pi.y, d.g, 1, &oob);
   const int cz = cell_coord(pi.z, d.g, 2, &oob);
-  const double h = d.h, h2 = d.h2;
+  const double h2 = d.h2, inv_h = d.inv_h;
   double acc = d.W0;
   int cnt = 0;
   const size_t npad = (size_t)d.npad;
+  int* const nb = d.nbr + i;
   for (int dz = -1; dz <= 1; ++dz) {
     int z = cz + dz;
     if (!wrap_axis(z, d.g.nc[2], d.g.per[2])) continue;
@@ -55,18 +56,18 @@ __global__ __launch_bounds__(BS) void k_build_density(Dev d) {
         const int jb = d.cstart[cell_index(d.g, x0, y, z)];
         const int je = d.cstart[cell_index(d.g, x1, y, z) + 1];
         for (int j = jb; j < je; ++j) {
-          if (j == i) continue;
           const D4 pj = d.pos[j];
           const double ex = min_img(pi.x - pj.x, d.per[0], d.L[0], d.halfL[0]);
           const double ey = min_img(pi.y - pj.y, d.per[1], d.L[1], d.halfL[1]);
           const double ez = min_img(pi.z - pj.z, d.per[2], d.L[2], d.halfL[2]);
           const double r2 = r2_exact(ex, ey, ez);
-          if (r2 < h2) {
-            if (cnt < d.maxn) d.nbr[(size_t)cnt * npad + i] = j;
-            ++cnt;
-            const double q = sqrt(r2) / h;
+          if (r2 < h2 && j != i) {
+            const double q = sqrt_nr(r2) * inv_h;
             const double om = 1.0 - q;
-            acc += d.w_norm * (1.0 + 3.0 * q) * om * om * om;
+            const double w = d.w_norm * (1.0 + 3.0 * q) * om * om * om;
+            if (cnt < d.maxn) nb[(size_t)cnt * npad] = j;
+            ++cnt;
+            acc += w;
           }
         }
       }
@@ -89,28 +90,29 @@ void launch_build_density(const Dev& d, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// (a4) Shepard filter of the pressure and the FP32 pair records
-// (v, c_C p~/d^2; spin, 1/d with d = rho/m_f).
+// (a4) Shepard filter of the pressure (weights recomputed from the FP64
+// positions) and the pair records of the force pass.
 
 __global__ __launch_bounds__(BS) void k_smooth(Dev d) {
   int i = xcd_tid();
   if (i >= d.n) return;
   const uint8_t ti = d.type[i];
   const double pi = d.p[i];
+  const D4 x = d.pos[i];
   double ps = pi;
   if (d.smooth && ti != T_OUTER) {
-    const D4 xi = d.pos[i];
     double num = pi * d.W0, den = d.W0;
     const int cnt = d.nbr_cnt[i];
     const size_t npad = (size_t)d.npad;
-    const double inv_h = 1.0 / d.h;
+    const int* nb = d.nbr + i;
+    const double inv_h = d.inv_h;
     for (int k = 0; k < cnt; ++k) {
-      const int j = d.nbr[(size_t)k * npad + i];
+      const int j = nb[(size_t)k * npad];
       const D4 xj = d.pos[j];
-      const double ex = min_img(xi.x - xj.x, d.per[0], d.L[0], d.halfL[0]);
-      const double ey = min_img(xi.y - xj.y, d.per[1], d.L[1], d.halfL[1]);
-      const double ez = min_img(xi.z - xj.z, d.per[2], d.L[2], d.halfL[2]);
-      const double q = sqrt(ex * ex + ey * ey + ez * ez) * inv_h;
+      const double ex = min_img(x.x - xj.x, d.per[0], d.L[0], d.halfL[0]);
+      const double ey = min_img(x.y - xj.y, d.per[1], d.L[1], d.halfL[1]);
+      const double ez = min_img(x.z - xj.z, d.per[2], d.L[2], d.halfL[2]);
+      const double q = sqrt_nr(r2_exact(ex, ey, ez)) * inv_h;
       const double om = fmax(1.0 - q, 0.0);
       const double w = d.w_norm * (1.0 + 3.0 * q) * om * om * om;
       num += d.p[j] * w;
@@ -121,17 +123,21 @@ __global__ __launch_bounds__(BS) void k_smooth(Dev d) {
   d.ps[i] = (float)ps;
   const double di = d.rho[i] / d.m_f;
   const D4 v = d.vel[i], w = d.om[i];
-  F4 vr, wr;
-  vr.x = (float)v.x;
-  vr.y = (float)v.y;
-  vr.z = (float)v.z;
-  vr.w = (float)(d.coef_c * ps / (di * di));
-  wr.x = (float)w.x;
-  wr.y = (float)w.y;
-  wr.z = (float)w.z;
-  wr.w = (float)(1.0 / di);
-  d.vrec[i] = vr;
-  d.wrec[i] = wr;
+  PR r;
+  r.x = x.x;
+  r.y = x.y;
+  r.z = x.z;
+  r.vx = (float)v.x;
+  r.vy = (float)v.y;
+  r.vz = (float)v.z;
+  r.pc = (float)(d.coef_c * ps / (di * di));
+  r.wx = (float)w.x;
+  r.wy = (float)w.y;
+  r.wz = (float)w.z;
+  r.invd = (float)(1.0 / di);
+  r.gid = d.gid[i];
+  r.pad = 0;
+  d.prec[i] = r;
 }
 
 void launch_smooth(const Dev& d, hipStream_t st) {
@@ -150,21 +156,23 @@ __global__ __launch_bounds__(BS) void k_fluid_forces(Dev d, uint32_t step) {
   const uint8_t ti = d.type[i];
   float F0 = 0.f, F1 = 0.f, F2 = 0.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, N0 = 0.f, N1 = 0.f, N2 = 0.f;
   if (ti == T_FLUID || ti == T_INNER) {
-    const D4 pi = d.pos[i];
-    const F4 vi = d.vrec[i];
-    const F4 wi = d.wrec[i];
-    const uint32_t gi = NOISE ? (uint32_t)d.gid[i] : 0u;
+    const PR ri = load_pr(d.prec, i);
+    const uint32_t gi = (uint32_t)ri.gid;
     const int cnt = d.nbr_cnt[i];
     const int* nb = d.nbr + i;
     const size_t npad = (size_t)d.npad;
+    // software-pipelined: the record of slot k+1 and the index of slot k+2
+    // are in flight while slot k is evaluated
+    int jn = cnt > 0 ? nb[0] : i;
+    PR rn = load_pr(d.prec, jn);
+    jn = cnt > 1 ? nb[npad] : i;
     for (int k = 0; k < cnt; ++k) {
-      const int j = nb[(size_t)k * npad];
-      const D4 pj = d.pos[j];
-      const F4 vj = d.vrec[j];
-      const F4 wj = d.wrec[j];
-      const double dx_ = min_img(pi.x - pj.x, d.per[0], d.L[0], d.halfL[0]);
-      const double dy_ = min_img(pi.y - pj.y, d.per[1], d.L[1], d.halfL[1]);
-      const double dz_ = min_img(pi.z - pj.z, d.per[2], d.L[2], d.halfL[2]);
+      const PR rj = rn;
+      rn = load_pr(d.prec, jn);
+      jn = k + 2 < cnt ? nb[(size_t)(k + 2) * npad] : i;
+      const double dx_ = min_img(ri.x - rj.x, d.per[0], d.L[0], d.halfL[0]);
+      const double dy_ = min_img(ri.y - rj.y, d.per[1], d.L[1], d.halfL[1]);
+      const double dz_ = min_img(ri.z - rj.z, d.per[2], d.L[2], d.halfL[2]);
       const double r2d = dx_ * dx_ + dy_ * dy_ + dz_ * dz_;
       const float rx = (float)dx_, ry = (float)dy_, rz = (float)dz_;
       const float inv_r = __builtin_amdgcn_rsqf((float)r2d);
@@ -179,12 +187,12 @@ __global__ __launch_bounds__(BS) void k_fluid_forces(Dev d, uint32_t step) {
       // transverse part only (e x e = 0), which keeps the FP32 cross product
       // free of the cancellation of the dominant pressure term.
       // conservative force, Eq. FijC: (p_i/d_i^2 + p_j/d_j^2) F r_ij
-      const float pc = (vi.w + vj.w) * Fk;
+      const float pc = (ri.pc + rj.pc) * Fk;
       // F / (d_i d_j): the two inverse densities multiply symmetrically so
       // that F_ji = -F_ij holds bit for bit
-      const float fdd = Fk * (wi.w * wj.w);
+      const float fdd = Fk * (ri.invd * rj.invd);
       // dissipative force, Eq. FijD: -ga v_ij - (ga + 2 gb)/3 (e.v_ij) e
-      const float vx = vi.x - vj.x, vy = vi.y - vj.y, vz = vi.z - vj.z;
+      const float vx = ri.vx - rj.vx, vy = ri.vy - rj.vy, vz = ri.vz - rj.vz;
       const float ev = ex * vx + ey * vy + ez * vz;
       const float cde = d.kBf * fdd * ev;
       const float cdv = d.kAf * fdd;
@@ -196,7 +204,7 @@ __global__ __launch_bounds__(BS) void k_fluid_forces(Dev d, uint32_t step) {
       C1 += cy_;
       C2 += cz_;
       // rotational force, Eq. FijR: -gamma^a (r_ij / 2) x (w_i + w_j)
-      const float sx = wi.x + wj.x, sy = wi.y + wj.y, sz = wi.z + wj.z;
+      const float sx = ri.wx + rj.wx, sy = ri.wy + rj.wy, sz = ri.wz + rj.wz;
       const float gr = d.kRf * fdd;
       const float rrx = gr * (ry * sz - rz * sy);
       const float rry = gr * (rz * sx - rx * sz);
@@ -208,7 +216,7 @@ __global__ __launch_bounds__(BS) void k_fluid_forces(Dev d, uint32_t step) {
       if (NOISE) {
         // thermal force, Eq. FijT with dW^S = sym(dW) - tr(dW)/3
         float z[9];
-        pair_normals(gi, (uint32_t)d.gid[j], step, d.key0, d.key1, z);
+        pair_normals(gi, (uint32_t)rj.gid, step, d.key0, d.key1, z);
         const float sa = 2.0f * sqrtf(d.kTf * d.CAf * fdd);
         const float sb = 2.0f * sqrtf(d.kTf * d.CBf * fdd);
         const float tr3 = (z[0] + z[4] + z[8]) * (1.0f / 3.0f);
