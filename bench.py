@@ -38,6 +38,56 @@ def pair_kernel_bytes(n, n_act, nnz_act, noise):
     return n * (1 + 36) + n_act * (32 + 16 + 16 + 4 + (4 if noise else 0)) + 4 * nnz_act
 
 
+def viscometer_leg(k_steps, n_cells=256, run_steps=5000):
+    """Batched viscometer: the 256 Lees-Edwards shear cells of uneven size
+    advanced together (one launch per kernel for all cells) against the same
+    cells run one after another as plain systems.  Each configuration is
+    timed over k_steps steps after 3 warm-up steps; runs/hr extrapolates to
+    run_steps steps per run."""
+    import torch
+
+    from paper_2002_03120_amd import sdpdem as S
+    from paper_2002_03120_amd import workloads as W
+
+    shared, cells = W.viscometer_batch(n_cells, seed=0, steps=run_steps)
+    parts, boxes, box_of = W.stack_cells(cells)
+    n_all = int(parts["id"].shape[0])
+    g = S.System(shared, parts, boxes=boxes, box_of=box_of)
+    g.set_stress(True)
+    g.step(3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(k_steps)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / k_steps
+    del g
+    torch.cuda.empty_cache()
+    t_plain = 0.0
+    for p, pp, info in cells:
+        c = S.System(p, pp)
+        c.set_stress(True)
+        c.step(3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.step(k_steps)
+        torch.cuda.synchronize()
+        t_plain += (time.perf_counter() - t0) / k_steps
+        del c
+    torch.cuda.empty_cache()
+    rb = n_cells / (t_batch * run_steps) * 3600.0
+    rp = n_cells / (t_plain * run_steps) * 3600.0
+    return {
+        "cells": n_cells, "particles": n_all, "steps_per_run": run_steps,
+        "batched_runs_per_hour": round(rb, 1), "plain_runs_per_hour": round(rp, 1),
+        "speedup": round(rb / rp, 2),
+        "batched_ms_per_step": round(t_batch * 1e3, 3),
+        "plain_ms_per_step_all_cells": round(t_plain * 1e3, 3),
+        "batched_particle_steps_per_s": round(n_all / t_batch, 1),
+        "sample": f"{k_steps} timed steps per configuration after 3 warm-up steps, "
+                  f"extrapolated to {run_steps} steps per run",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -49,6 +99,8 @@ def main():
     ap.add_argument("--small", action="store_true", help="a small tank, for quick checks")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration)")
+    ap.add_argument("--viscometer-steps", type=int, default=20,
+                    help="timed steps per configuration of the batched-viscometer leg (0: skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -142,6 +194,11 @@ def main():
         "status_after": {"max_speed": float(tot[8]), "rho_min": float(tot[9]),
                          "rho_max": float(tot[10])},
     }
+
+    if args.viscometer_steps > 0:
+        del sysm
+        torch.cuda.empty_cache()
+        result["viscometer"] = viscometer_leg(args.viscometer_steps)
 
     if args.cpu_seconds > 0:
         from oracle import oracle as O

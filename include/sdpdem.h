@@ -84,6 +84,10 @@ typedef struct sdpdem_params {
   uint64_t seed;           /* key of the Philox4x32-10 noise                      */
   int32_t max_neighbors;   /* capacity of a neighbour row                         */
   int32_t max_contacts;    /* capacity of a rigid contact row                     */
+  double shear_rate;       /* Lees-Edwards shear rate (0: plain periodic images);
+                              non-zero needs all axes periodic: flow along x,
+                              gradient along z, the image above shifted by
+                              shear_rate L_z t in x and moving at +shear_rate L_z */
 } sdpdem_params;
 
 /* Particles, host memory, n rows in any order (ids must cover 0..n-1).
@@ -100,6 +104,19 @@ typedef struct sdpdem_particles {
   const double* inertia;  /* [n]   */
   const double* radius;   /* [n]   */
 } sdpdem_particles;
+
+/* One box of a batch: an independent domain (its own periodic or wall
+ * axes, Lees-Edwards shear rate, thermal energy and noise key).  The
+ * parameters' own org/L/periodic/shear_rate/kBT/seed are ignored by the
+ * batch calls; every other parameter is shared by all boxes. */
+typedef struct sdpdem_box {
+  double org[3], L[3];
+  int32_t periodic[3];
+  int32_t reserved;        /* 0 */
+  double shear_rate;       /* as in sdpdem_params                            */
+  double kBT;              /* thermal energy of this box                     */
+  uint64_t seed;           /* noise key of this box                          */
+} sdpdem_box;
 
 /* Fields readable with sdpdem_read_field: n rows in id order, 1 or 3
  * doubles per row.  Force fields hold the last force evaluation. */
@@ -146,6 +163,20 @@ int sdpdem_create(const sdpdem_params* params, const sdpdem_particles* particles
                   void* d_workspace, size_t workspace_bytes, void* hip_stream,
                   sdpdem_system** out);
 
+/* Batched systems: nbox independent boxes advanced together, every kernel
+ * launch covering all of them (the batched viscometer).  box_of[k] gives
+ * the box of particle row k; ids run over 0..n-1 across all boxes.  No
+ * pair, contact or coupling ever joins particles of different boxes.
+ * Rejects what sdpdem_create rejects, per box, and box_of entries outside
+ * 0..nbox-1; a box with shear_rate != 0 must be periodic on all axes. */
+int sdpdem_batch_workspace_bytes(const sdpdem_params* params, const sdpdem_box* boxes,
+                                 int32_t nbox, const sdpdem_particles* particles,
+                                 const int32_t* box_of, size_t* bytes);
+int sdpdem_create_batch(const sdpdem_params* params, const sdpdem_box* boxes, int32_t nbox,
+                        const sdpdem_particles* particles, const int32_t* box_of,
+                        void* d_workspace, size_t workspace_bytes, void* hip_stream,
+                        sdpdem_system** out);
+
 /* Algorithm 1: nsteps steps of two velocity-Verlet passes each.  Returns the
  * device status (overflow, non-finite, out of domain) seen at the end. */
 int sdpdem_step(sdpdem_system* sys, int64_t nsteps, void* hip_stream);
@@ -180,8 +211,28 @@ int sdpdem_totals(sdpdem_system* sys, double out[16], void* hip_stream);
 
 int64_t sdpdem_get_step(const sdpdem_system* sys);
 
-/* Diagnostics: out = [n, n_rigid, cells x, y, z, rigid cells x, y, z,
- * max neighbour count of the last build, pairs of the last build, 0...]. */
+/* Shear-stress sampling for viscometry (not in the paper; Lees-Edwards
+ * boxes).  With sampling on, every step ends with one sample per box of
+ * the pressure-tensor component
+ *   P_zx = ( sum_i m_i v'_z v'_x + sum_pairs r_z F_x ) / V,
+ * v' = v - shear_rate (z - z_mid) e_x, the pair sum over the SDPD pair
+ * forces (a pair with a rigid or outer-wall partner counted once), the DEM
+ * contact and lubrication pairs and the fluid-particle coupling of every
+ * sphere (lever sum_j w_sj r_sj / Omega_s times F^DG + F^PG), all from the
+ * second force pass of the step, velocities at the end of the step.  The
+ * effective viscosity of a sheared box is -<P_zx> / shear_rate.
+ * sdpdem_set_stress switches sampling on or off and clears the sums;
+ * sdpdem_compute_forces then also refreshes the instantaneous sample
+ * (without adding it to the sums).  sdpdem_box_stress copies the last
+ * sample and the running sums (nbox doubles each, either may be NULL) and
+ * the number of summed samples; it synchronises the stream. */
+int sdpdem_set_stress(sdpdem_system* sys, int on, void* hip_stream);
+int sdpdem_box_stress(sdpdem_system* sys, double* inst, double* sum, int64_t* nsamples,
+                      void* hip_stream);
+
+/* Diagnostics: out = [n, n_rigid, cells x, y, z of box 0, rigid cells x,
+ * y, z of box 0, max neighbour count of the last build, pairs of the last
+ * build, number of boxes, 0...]. */
 int sdpdem_info(sdpdem_system* sys, int64_t out[16], void* hip_stream);
 
 /* Time every launch of one kernel (enum sdpdem_kernel) with HIP events on

@@ -62,6 +62,7 @@ class OracleParams(ctypes.Structure):
         ("itr_start", ctypes.c_int64), ("itr_actv_rigid", ctypes.c_int64),
         ("seed", ctypes.c_uint64),
         ("max_neighbors", ctypes.c_int32), ("max_contacts", ctypes.c_int32),
+        ("shear_rate", ctypes.c_double),
     ]
 
 
@@ -131,6 +132,7 @@ def lib():
         L.oracle_load_contacts.argtypes = [ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_int64]
         L.oracle_totals.argtypes = [ctypes.c_void_p, dp]
+        L.oracle_stress.argtypes = [ctypes.c_void_p, dp]
         L.oracle_get_step.restype = ctypes.c_int64
         L.oracle_get_step.argtypes = [ctypes.c_void_p]
         L.oracle_field_comps.argtypes = [ctypes.c_int]
@@ -248,6 +250,15 @@ class Oracle:
         out = np.zeros(16, dtype=np.float64)
         lib().oracle_totals(self._h, _dp(out))
         return out
+
+    def stress(self) -> np.ndarray:
+        """Pressure tensor (3x3) of the box: kinetic part from the current
+        velocities, virial of the last force evaluation."""
+        out = np.zeros(9)
+        rc = lib().oracle_stress(self._h, _dp(out))
+        if rc:
+            raise OracleError(rc, "stress")
+        return out.reshape(3, 3)
 
     @property
     def current_step(self) -> int:

@@ -50,6 +50,21 @@
  *      (all components for no-slip, the normal one for slip).
  *  R15 The neighbour test is r^2 < h^2, strict, with
  *      r^2 = (dx*dx + dy*dy) + dz*dz in double precision.
+ *  R16 Lees-Edwards shear (not in the paper; for the viscometer): flow
+ *      along x, gradient along z.  The image of the box above sits at
+ *      x + delta(t), delta = fmod(shear_rate L_z t, L_x) with t the time of
+ *      the current positions, and moves with +shear_rate L_z in x.  The
+ *      minimum image takes the z image first, then wraps x and y; pair
+ *      terms see the image's velocity.  A particle leaving through a z face
+ *      re-enters shifted by -/+ delta in x with v_x -/+ shear_rate L_z.
+ *  R17 Pressure tensor of the box: P_ab = (sum_i m v'_a v'_b + W_ab) / V
+ *      with v' = v - shear_rate (z - z_mid) e_x over fluid, rigid and
+ *      inner-wall particles, and W the virial of the pair forces of the
+ *      last evaluation: sum over pairs of r_ij,a F_ij,b, a pair computed
+ *      from both sides counted half on each side, one-sided SDPD pairs
+ *      (fluid on rigid or outer wall) counted once; the fluid-particle
+ *      coupling of sphere s counts M_s,a (F^DG_s + F^PG_s)_b with the lever
+ *      M_s = sum_j w_sj r_sj / Omega_s.  Body forces are external.
  */
 #include "sdpdem_oracle.h"
 
@@ -91,6 +106,9 @@ struct oracle_system {
   int32_t* ct_partner;
   double* ct_dt;
   int64_t step;
+  int64_t pos_step;  /* step index of the time of the current positions */
+  double le_shift;   /* Lees-Edwards offset at that time (R16) */
+  double* vir;       /* per-particle virial W_ab of the last evaluation */
   /* background grid with linked lists (Sec. 3.2) */
   double glo[3], gcs[3];
   int64_t gnc[3];
@@ -316,12 +334,47 @@ void oracle_dem_pair(const oracle_params* P, const double dij[3],
 /* ------------------------------------------------------------------------ */
 /* geometry helpers                                                        */
 
-static void min_image(const oracle_params* P, const double* xi,
-                      const double* xj, double d[3]) {
-  for (int a = 0; a < 3; ++a) {
-    d[a] = xi[a] - xj[a];
-    if (P->periodic[a]) d[a] = d[a] - P->L[a] * nearbyint(d[a] / P->L[a]);
+/* Lees-Edwards offset delta(t) of the image above (R16) */
+static double le_shift_at(const oracle_params* P, int64_t pstep) {
+  if (P->shear_rate == 0.0) return 0.0;
+  double t = (double)pstep * P->dt;
+  double v = (P->shear_rate * P->L[2]) * t;
+  double sft = fmod(v, P->L[0]);
+  if (sft < 0.0) sft += P->L[0];
+  return sft;
+}
+
+static void set_pos_step(oracle_system* s, int64_t pstep) {
+  s->pos_step = pstep;
+  s->le_shift = le_shift_at(&s->P, pstep);
+}
+
+/* minimum-image separation x_i - x_j' (R14, R16); returns k_z, the number
+ * of boxes (in z) by which the image j' is displaced, so that j' moves with
+ * v_j + k_z shear_rate L_z e_x */
+static int min_image(const oracle_system* s, const double* xi,
+                     const double* xj, double d[3]) {
+  const oracle_params* P = &s->P;
+  for (int a = 0; a < 3; ++a) d[a] = xi[a] - xj[a];
+  if (P->shear_rate != 0.0) {
+    double k = nearbyint(d[2] / P->L[2]);
+    d[2] = d[2] - P->L[2] * k;
+    d[0] = d[0] - s->le_shift * k;
+    d[0] = d[0] - P->L[0] * nearbyint(d[0] / P->L[0]);
+    d[1] = d[1] - P->L[1] * nearbyint(d[1] / P->L[1]);
+    return (int)k;
   }
+  for (int a = 0; a < 3; ++a)
+    if (P->periodic[a]) d[a] = d[a] - P->L[a] * nearbyint(d[a] / P->L[a]);
+  return 0;
+}
+
+/* velocity of the image of j displaced by kz boxes (R16) */
+static void image_vel(const oracle_system* s, const double* vj, int kz,
+                      double out[3]) {
+  out[0] = vj[0] + (double)kz * (s->P.shear_rate * s->P.L[2]);
+  out[1] = vj[1];
+  out[2] = vj[2];
 }
 
 static double norm2(const double d[3]) {
@@ -416,16 +469,23 @@ static void query_ball(const oracle_system* s, const double* x, double R,
     }
   }
   double R2 = R * R;
+  /* Lees-Edwards: rows seen through a z face are shifted in x, so every x
+   * cell of such a row is searched (a superset; the distance test decides) */
+  int le = P->shear_rate != 0.0;
+  int le_all = le && cnt[2] == s->gnc[2];
   for (int64_t kz = 0; kz < cnt[2]; ++kz) {
     int64_t cz = lo[2] + kz;
+    int crossing = le_all || (le && (cz < 0 || cz >= s->gnc[2]));
     if (P->periodic[2]) cz = ((cz % s->gnc[2]) + s->gnc[2]) % s->gnc[2];
     else if (cz < 0 || cz >= s->gnc[2]) continue;
+    int64_t xlo = crossing ? 0 : lo[0];
+    int64_t xcnt = crossing ? s->gnc[0] : cnt[0];
     for (int64_t ky = 0; ky < cnt[1]; ++ky) {
       int64_t cy = lo[1] + ky;
       if (P->periodic[1]) cy = ((cy % s->gnc[1]) + s->gnc[1]) % s->gnc[1];
       else if (cy < 0 || cy >= s->gnc[1]) continue;
-      for (int64_t kx = 0; kx < cnt[0]; ++kx) {
-        int64_t cx = lo[0] + kx;
+      for (int64_t kx = 0; kx < xcnt; ++kx) {
+        int64_t cx = xlo + kx;
         if (P->periodic[0]) cx = ((cx % s->gnc[0]) + s->gnc[0]) % s->gnc[0];
         else if (cx < 0 || cx >= s->gnc[0]) continue;
         int64_t c = (cz * s->gnc[1] + cy) * s->gnc[0] + cx;
@@ -433,7 +493,7 @@ static void query_ball(const oracle_system* s, const double* x, double R,
           if (j == self) continue;
           if (!((type_mask >> s->type[j]) & 1u)) continue;
           double d[3];
-          min_image(P, x, &s->pos[3 * j], d);
+          min_image(s, x, &s->pos[3 * j], d);
           if (norm2(d) < R2) ibuf_push(out, (int32_t)j);
         }
       }
@@ -497,7 +557,7 @@ static void density_pressure(oracle_system* s) {
     const int32_t* nb = &s->nb_col[i * (int64_t)P->max_neighbors];
     for (int k = 0; k < s->nb_cnt[i]; ++k) {
       double d[3];
-      min_image(P, &s->pos[3 * i], &s->pos[3 * (int64_t)nb[k]], d);
+      min_image(s, &s->pos[3 * i], &s->pos[3 * (int64_t)nb[k]], d);
       acc += oracle_lucy_w(sqrt(norm2(d)), P->h);
     }
     s->rho[i] = s->CW * P->mass_fluid * acc;
@@ -518,7 +578,7 @@ static void density_pressure(oracle_system* s) {
     for (int k = 0; k < s->nb_cnt[i]; ++k) {
       int64_t j = nb[k];
       double d[3];
-      min_image(P, &s->pos[3 * i], &s->pos[3 * j], d);
+      min_image(s, &s->pos[3 * i], &s->pos[3 * j], d);
       double wij = oracle_lucy_w(sqrt(norm2(d)), P->h);
       num += s->p[j] * wij;
       den += wij;
@@ -543,16 +603,19 @@ static void compute_fluid(oracle_system* s) {
   for (int64_t i = 0; i < s->n; ++i) {
     double F[3] = {0, 0, 0}, Fcd[3] = {0, 0, 0}, N[3] = {0, 0, 0};
     double aF = 0, aCD = 0, aN = 0;
+    double* W = &s->vir[9 * i];
+    for (int a = 0; a < 9; ++a) W[a] = 0.0;
     if (s->type[i] == O_FLUID || s->type[i] == O_INNER_WALL) {
       double di = s->rho[i] / P->mass_fluid;
       const int32_t* nb = &s->nb_col[i * (int64_t)P->max_neighbors];
       for (int k = 0; k < s->nb_cnt[i]; ++k) {
         int64_t j = nb[k];
-        double rij[3];
-        min_image(P, &s->pos[3 * i], &s->pos[3 * j], rij);
+        double rij[3], vj[3];
+        int kz = min_image(s, &s->pos[3 * i], &s->pos[3 * j], rij);
+        image_vel(s, &s->vel[3 * j], kz, vj);
         double dj = s->rho[j] / P->mass_fluid;
         double fc[3], fd[3], fr[3], ft[3];
-        oracle_pair_force(P, rij, &s->vel[3 * i], &s->vel[3 * j], &s->w[3 * i],
+        oracle_pair_force(P, rij, &s->vel[3 * i], vj, &s->w[3 * i],
                           &s->w[3 * j], di, dj, s->ps[i], s->ps[j], i, j,
                           s->step, fc, fd, fr, ft);
         double r = sqrt(norm2(rij));
@@ -570,6 +633,10 @@ static void compute_fluid(oracle_system* s) {
           Fcd[a] += cd[a];
           N[a] += tq[a];
         }
+        /* virial (R17): half of a pair that j also evaluates */
+        double c = (s->type[j] == O_FLUID || s->type[j] == O_INNER_WALL) ? 0.5 : 1.0;
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) W[3 * a + b] += c * rij[a] * f[b];
         aF += vabs3(f);
         aCD += vabs3(cd);
         aN += vabs3(tq);
@@ -624,17 +691,20 @@ static int compute_fpi_action(oracle_system* s) {
         b.n = s->cp_cap;
       }
       double omega = 0.0, vf[3] = {0, 0, 0}, fcd[3] = {0, 0, 0}, acd = 0.0;
+      double lev[3] = {0, 0, 0};
       for (int64_t k = 0; k < b.n; ++k) {
         int64_t j = b.v[k];
-        double d[3];
-        min_image(P, xs, &s->pos[3 * j], d);
+        double d[3], vj[3];
+        int kz = min_image(s, xs, &s->pos[3 * j], d);
+        image_vel(s, &s->vel[3 * j], kz, vj);
         double wsj = oracle_lucy_w(sqrt(norm2(d)), H);
         s->cp_col[r * s->cp_cap + k] = (int32_t)j;
         s->cp_w[r * s->cp_cap + k] = wsj;
         omega += wsj;
         for (int a = 0; a < 3; ++a) {
-          vf[a] += wsj * s->vel[3 * j + a];
+          vf[a] += wsj * vj[a];
           fcd[a] += wsj * s->f_cd[3 * j + a];
+          lev[a] += wsj * d[a];
         }
         acd += wsj * s->a_cd[j];
       }
@@ -657,6 +727,11 @@ static int compute_fpi_action(oracle_system* s) {
         s->f_dg[3 * si + a] = -B * Vs * dv[a];
         s->f_pg[3 * si + a] = P->rho0 * Vs / P->mass_fluid * (fcd[a] / omega);
       }
+      /* virial of the coupling (R17), lever M_s = sum_j w_sj r_sj / Omega_s */
+      for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c)
+          s->vir[9 * si + 3 * a + c] +=
+              (lev[a] / omega) * (s->f_dg[3 * si + c] + s->f_pg[3 * si + c]);
       s->a_dg[si] = vabs3(&s->f_dg[3 * si]);
       s->a_pg[si] = P->rho0 * Vs / P->mass_fluid * (acd / omega);
     }
@@ -713,8 +788,9 @@ static int compute_rigid(oracle_system* s, int commit) {
       for (int64_t q = 0; q < b.n; ++q) {
         int64_t k = b.v[q];
         double Rk = s->rad[k];
-        double d[3];
-        min_image(P, &s->pos[3 * si], &s->pos[3 * k], d);
+        double d[3], vk[3];
+        int kz = min_image(s, &s->pos[3 * si], &s->pos[3 * k], d);
+        image_vel(s, &s->vel[3 * k], kz, vk);
         double L = sqrt(norm2(d));
         if (L < Rs + Rk) {
           double dtin[3] = {0, 0, 0};
@@ -725,7 +801,7 @@ static int compute_rigid(oracle_system* s, int commit) {
             }
           double fn[3], ft[3], dto[3];
           int sl;
-          oracle_dem_pair(P, d, &s->vel[3 * si], &s->vel[3 * k],
+          oracle_dem_pair(P, d, &s->vel[3 * si], vk,
                           &s->w[3 * si], &s->w[3 * k], Rs, Rk, s->mass[si],
                           s->mass[k], dtin, fn, ft, dto, &sl);
           double tq[3], me[3];
@@ -739,6 +815,8 @@ static int compute_rigid(oracle_system* s, int commit) {
             F[a] += f[a];
             N[a] += tq[a];
           }
+          for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c) s->vir[9 * si + 3 * a + c] += 0.5 * d[a] * f[c];
           aF += vabs3(f);
           aN += vabs3(tq);
           if (ncnt >= mc) {
@@ -756,9 +834,11 @@ static int compute_rigid(oracle_system* s, int commit) {
             double c = 3.0 * M_PI * P->eta * dbar * dbar / (8.0 * gg);
             double fl[3];
             for (int a = 0; a < 3; ++a) {
-              fl[a] = c * (s->vel[3 * k + a] - s->vel[3 * si + a]);
+              fl[a] = c * (vk[a] - s->vel[3 * si + a]);
               Fl[a] += fl[a];
             }
+            for (int a = 0; a < 3; ++a)
+              for (int e = 0; e < 3; ++e) s->vir[9 * si + 3 * a + e] += 0.5 * d[a] * fl[e];
             aL += vabs3(fl);
           }
         }
@@ -844,6 +924,10 @@ static int update(oracle_system* s, int velver) {
   const oracle_params* P = &s->P;
   int bad = 0, out = 0;
   int act = rigid_active(s);
+  /* Lees-Edwards offset at the time the drift moves to (R16) */
+  const int le = P->shear_rate != 0.0;
+  const double le_new = le_shift_at(P, s->step + 1);
+  const double le_dv = P->shear_rate * P->L[2];
 #pragma omp parallel for schedule(static) reduction(| : bad, out)
   for (int64_t i = 0; i < s->n; ++i) {
     uint8_t t = s->type[i];
@@ -857,6 +941,21 @@ static int update(oracle_system* s, int velver) {
     }
     if (velver == 1 && (t == O_FLUID || t == O_RIGID)) {
       for (int a = 0; a < 3; ++a) s->pos[3 * i + a] += P->dt * s->vel[3 * i + a];
+      if (le) {
+        /* leaving through a z face: re-enter as the image of the next box */
+        double* x = &s->pos[3 * i];
+        if (x[2] < P->org[2]) {
+          x[2] += P->L[2];
+          x[0] += le_new;
+          s->vel[3 * i] += le_dv;
+        } else if (x[2] >= P->org[2] + P->L[2]) {
+          x[2] -= P->L[2];
+          x[0] -= le_new;
+          s->vel[3 * i] -= le_dv;
+        }
+        if (x[0] < P->org[0]) x[0] += P->L[0];
+        else if (x[0] >= P->org[0] + P->L[0]) x[0] -= P->L[0];
+      }
       for (int a = 0; a < 3; ++a) {
         double lo = P->org[a], hi = P->org[a] + P->L[a];
         double* x = &s->pos[3 * i + a];
@@ -894,6 +993,7 @@ int oracle_step(oracle_system* s, int64_t nsteps) {
       if (rc) return rc;
       rc = update(s, velver);
       if (rc) return rc;
+      if (velver == 1) set_pos_step(s, s->step + 1);
     }
     s->step += 1;
   }
@@ -934,11 +1034,15 @@ int oracle_create(const oracle_params* p, int64_t n, const int64_t* id,
       return ORACLE_E_INVALID_ARG;
   }
   if (p->gravity_axis < 0 || p->gravity_axis > 2) return ORACLE_E_INVALID_ARG;
+  if (p->shear_rate != 0.0 &&
+      (!p->periodic[0] || !p->periodic[1] || !p->periodic[2] || !isfinite(p->shear_rate)))
+    return ORACLE_E_INVALID_ARG;
   oracle_system* s = (oracle_system*)calloc(1, sizeof(oracle_system));
   if (!s) return ORACLE_E_NOMEM;
   s->P = *p;
   s->n = n;
   s->step = p->itr_start;
+  set_pos_step(s, p->itr_start);
   ALLOC(s->type, n);
   ALLOC(s->pos, 3 * n);
   ALLOC(s->vel, 3 * n);
@@ -968,6 +1072,7 @@ int oracle_create(const oracle_params* p, int64_t n, const int64_t* id,
   ALLOC(s->a_dem, n);
   ALLOC(s->a_lub, n);
   ALLOC(s->a_ndem, n);
+  ALLOC(s->vir, 9 * n);
   ALLOC(s->nb_cnt, n);
   ALLOC(s->nb_col, n * (int64_t)p->max_neighbors);
   ALLOC(s->next, n);
@@ -1048,7 +1153,7 @@ void oracle_destroy(oracle_system* s) {
                   s->a_dem, s->a_lub, s->a_ndem, s->nb_cnt, s->nb_col,
                   s->rig_id, s->rig_of, s->cp_cnt, s->cp_col, s->cp_w,
                   s->cp_omega, s->ct_cnt, s->ct_partner, s->ct_dt, s->head,
-                  s->next};
+                  s->next, s->vir};
   for (size_t k = 0; k < sizeof(ptrs) / sizeof(ptrs[0]); ++k) free(ptrs[k]);
   free(s);
 }
@@ -1232,6 +1337,26 @@ int oracle_totals(oracle_system* s, double out[16]) {
 }
 
 int64_t oracle_get_step(const oracle_system* s) { return s ? s->step : -1; }
+
+/* pressure tensor of the box (R17): kinetic part from the current
+ * velocities, virial from the last force evaluation */
+int oracle_stress(oracle_system* s, double out[9]) {
+  if (!s || !out) return ORACLE_E_INVALID_ARG;
+  const oracle_params* P = &s->P;
+  double V = P->L[0] * P->L[1] * P->L[2];
+  double zmid = P->org[2] + 0.5 * P->L[2];
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t i = 0; i < s->n; ++i) {
+    if (s->type[i] == O_OUTER_WALL) continue;
+    double v[3] = {s->vel[3 * i], s->vel[3 * i + 1], s->vel[3 * i + 2]};
+    v[0] -= P->shear_rate * (s->pos[3 * i + 2] - zmid);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        acc[3 * a + b] += s->mass[i] * v[a] * v[b] + s->vir[9 * i + 3 * a + b];
+  }
+  for (int k = 0; k < 9; ++k) out[k] = acc[k] / V;
+  return ORACLE_OK;
+}
 
 int oracle_num_threads(void) { return omp_get_max_threads(); }
 

@@ -69,6 +69,11 @@ typedef struct oracle_params {
   int64_t itr_actv_rigid;   /* --itr_actv_rigid                                 */
   uint64_t seed;            /* key of the counter-based generator               */
   int32_t max_neighbors, max_contacts;
+  /* Lees-Edwards shear rate (0: plain periodic images).  Non-zero needs all
+   * three axes periodic: flow along x, gradient along z; the image of the
+   * box above is shifted by shear_rate L_z t in x and moves with
+   * +shear_rate L_z in x. */
+  double shear_rate;
 } oracle_params;
 
 typedef struct oracle_system oracle_system;
@@ -107,6 +112,10 @@ int oracle_load_contacts(oracle_system* s, const int32_t* pairs,
                          const double* delta_t, int64_t n_contacts);
 int oracle_totals(oracle_system* s, double out[16]);
 int64_t oracle_get_step(const oracle_system* s);
+/* pressure tensor P_ab (row-major 3x3) of the box: kinetic part from the
+ * current velocities (peculiar to the Lees-Edwards profile), virial of the
+ * pair forces of the last force evaluation, divided by the box volume */
+int oracle_stress(oracle_system* s, double out[9]);
 int oracle_num_threads(void);
 void oracle_set_num_threads(int n);
 

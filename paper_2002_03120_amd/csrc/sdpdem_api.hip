@@ -34,6 +34,10 @@ struct sdpdem_system {
   int64_t step = 0;
   bool cache_valid = false;
   bool noise = false;
+  bool stress = false;
+  int64_t stress_samples = 0;
+  BoxD* boxes = nullptr;  // device copy of the box table
+  std::vector<BoxD> h_boxes;
   std::vector<int> h_gid2slot;
   // profiling
   int prof_kernel = SDPDEM_K_NONE;
@@ -67,10 +71,16 @@ bool valid_params(const sdpdem_params* P) {
   if (P->max_neighbors < 1 || P->max_contacts < 1) return false;
   if (P->xi < 40.0 * P->eta / 51.0 || P->xi > 5.0 * P->eta / 3.0) return false;
   if (P->gravity_axis < 0 || P->gravity_axis > 2) return false;
+  return true;
+}
+
+bool valid_box(const sdpdem_params* P, const sdpdem_box& b) {
   for (int a = 0; a < 3; ++a) {
-    if (!(P->L[a] > 0)) return false;
-    if (P->periodic[a] && P->L[a] < 3.0 * P->h * (1.0 + 1e-6)) return false;
+    if (!(b.L[a] > 0) || !std::isfinite(b.org[a]) || !std::isfinite(b.L[a])) return false;
+    if (b.periodic[a] && b.L[a] < 3.0 * P->h * (1.0 + 1e-6)) return false;
   }
+  if (!(b.kBT >= 0) || !std::isfinite(b.kBT) || !std::isfinite(b.shear_rate)) return false;
+  if (b.shear_rate != 0.0 && (!b.periodic[0] || !b.periodic[1] || !b.periodic[2])) return false;
   return true;
 }
 
@@ -106,21 +116,23 @@ bool valid_particles(const sdpdem_particles* q, std::vector<int>* slot_of, int* 
   return true;
 }
 
-// Cell grid: periodic axes are split into floor(L/cs0) equal cells; wall
-// axes cover the domain and every particle with one cell of slack.
-bool make_grid(const sdpdem_params& P, const sdpdem_particles& q, double cs0, Grid& g) {
+// Cell grid of one box: periodic axes are split into floor(L/cs0) equal
+// cells; wall axes cover the box and every one of its particles with one
+// cell of slack.
+bool make_grid(const sdpdem_box& B, const sdpdem_particles& q, const std::vector<int64_t>& rows,
+               double cs0, Grid& g) {
   double total = 1.0;
   for (int a = 0; a < 3; ++a) {
-    g.per[a] = P.periodic[a] ? 1 : 0;
+    g.per[a] = B.periodic[a] ? 1 : 0;
     if (g.per[a]) {
-      int nc = (int)std::floor(P.L[a] / cs0);
+      int nc = (int)std::floor(B.L[a] / cs0);
       if (nc < 1) nc = 1;
-      g.lo[a] = P.org[a];
+      g.lo[a] = B.org[a];
       g.nc[a] = nc;
-      g.cs[a] = P.L[a] / nc;
+      g.cs[a] = B.L[a] / nc;
     } else {
-      double mn = P.org[a], mx = P.org[a] + P.L[a];
-      for (int64_t k = 0; k < q.n; ++k) {
+      double mn = B.org[a], mx = B.org[a] + B.L[a];
+      for (int64_t k : rows) {
         double x = q.pos[3 * k + a];
         if (!std::isfinite(x)) return false;
         mn = std::min(mn, x);
@@ -159,15 +171,19 @@ double lattice_sum(double h, double dx) {
 struct Sizes {
   int64_t n, npad, nr;
   int maxn, maxc;
-  int dem_reach = 1;
-  Grid g, rg;
+  int nbox = 1;
+  int64_t ncells_all = 0, rncells_all = 0;
+  std::vector<BoxD> boxes;
+  std::vector<int2> blk;       // launch blocks (box, first sorted index)
+  std::vector<int> rbox;       // box of every rigid slot
+  std::vector<int64_t> order;  // initial sorted position -> input row
 };
 
 // Carve the workspace (base == nullptr: only measure it).
 size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
   Bump b{base};
   size_t n = (size_t)z.n, np = (size_t)z.npad, nr = (size_t)z.nr;
-  size_t nc = (size_t)z.g.ncells, rnc = (size_t)z.rg.ncells;
+  size_t nc = (size_t)z.ncells_all, rnc = (size_t)z.rncells_all;
   D4 *pos0 = b.take<D4>(np), *pos1 = b.take<D4>(np);
   D4 *vel0 = b.take<D4>(np), *vel1 = b.take<D4>(np);
   D4 *om0 = b.take<D4>(np), *om1 = b.take<D4>(np);
@@ -185,7 +201,7 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
   double* p = b.take<double>(np);
   float* ps = b.take<float>(np);
   PR* prec = b.take<PR>(np);
-  float* fout = b.take<float>(12 * np);
+  float* fout = b.take<float>(13 * np);
   int* gid2slot = b.take<int>(np);
   int* rig_sorted = b.take<int>(nr);
   int* rig_gid = b.take<int>(nr);
@@ -196,6 +212,12 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
   double* n_dem = b.take<double>(3 * nr);
   double* eps = b.take<double>(nr);
   double* omega = b.take<double>(nr);
+  double* wzx_r = b.take<double>(nr);
+  BoxD* boxes = b.take<BoxD>((size_t)z.nbox);
+  int2* blk = b.take<int2>(z.blk.size());
+  int* rbox = b.take<int>(nr);
+  double* st_inst = b.take<double>((size_t)z.nbox);
+  double* st_sum = b.take<double>((size_t)z.nbox);
   uint32_t* rkey = b.take<uint32_t>(nr);
   int* rcount = b.take<int>(rnc);
   int* rstart = b.take<int>(rnc + 1);
@@ -261,6 +283,13 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
     d.n_dem = n_dem;
     d.eps = eps;
     d.omega = omega;
+    d.wzx_r = wzx_r;
+    s->boxes = boxes;
+    d.boxes = boxes;
+    d.blk = blk;
+    d.rbox = rbox;
+    d.st_inst = st_inst;
+    d.st_sum = st_sum;
     d.rkey = rkey;
     d.rcount = rcount;
     d.rstart = rstart;
@@ -277,28 +306,103 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
   return total;
 }
 
-bool plan(const sdpdem_params* P, const sdpdem_particles* q, Sizes& z,
+bool plan(const sdpdem_params* P, const sdpdem_box* boxes, int nbox,
+          const sdpdem_particles* q, const int32_t* box_of, Sizes& z,
           std::vector<int>* slot_of) {
-  if (!valid_params(P)) return false;
+  if (!valid_params(P) || !boxes || nbox < 1 || nbox > (1 << 20)) return false;
+  for (int b = 0; b < nbox; ++b)
+    if (!valid_box(P, boxes[b])) return false;
   int nr = 0;
-  double rmax = 0.0;
-  if (!valid_particles(q, slot_of, &nr, &rmax)) return false;
-  z.n = q->n;
-  z.npad = (q->n + 63) / 64 * 64;
+  double rmax_all = 0.0;
+  std::vector<int> slots;
+  if (!valid_particles(q, &slots, &nr, &rmax_all)) return false;
+  const int64_t n = q->n;
+  std::vector<std::vector<int64_t>> rows((size_t)nbox);
+  for (int64_t k = 0; k < n; ++k) {
+    int b = box_of ? box_of[k] : 0;
+    if (b < 0 || b >= nbox) return false;
+    rows[(size_t)b].push_back(k);
+  }
+  z.n = n;
+  z.npad = (n + 63) / 64 * 64;
   z.nr = nr;
   z.maxn = P->max_neighbors;
   z.maxc = P->max_contacts;
-  if (!make_grid(*P, *q, P->h * (1.0 + 1e-6), z.g)) return false;
-  for (int a = 0; a < 3; ++a)
-    if (P->periodic[a] && z.g.nc[a] < 3) return false;
-  // rigid grid: cells at least H_max = R_max + h wide, so that the fluid
-  // particles coupled to a sphere lie in its 27 neighbouring cells
-  double rcs = (rmax + P->h) * (1.0 + 1e-6);
-  if (!make_grid(*P, *q, rcs, z.rg)) return false;
-  // DEM partners lie within R_s + R_k + h <= 2 R_max + h
-  double mincs = std::min(z.rg.cs[0], std::min(z.rg.cs[1], z.rg.cs[2]));
-  z.dem_reach = std::max(1, (int)std::ceil((2.0 * rmax + P->h) / mincs * (1.0 + 1e-9)));
+  z.nbox = nbox;
+  z.boxes.assign((size_t)nbox, BoxD{});
+  z.blk.clear();
+  z.rbox.assign((size_t)nr, 0);
+  z.order.clear();
+  z.order.reserve((size_t)n);
+  int64_t coff = 0, rcoff = 0, first = 0;
+  for (int b = 0; b < nbox; ++b) {
+    const sdpdem_box& hb = boxes[b];
+    auto& r = rows[(size_t)b];
+    // ids ascending inside a box: the initial order before the first sort
+    std::sort(r.begin(), r.end(), [&](int64_t a, int64_t c) { return q->id[a] < q->id[c]; });
+    double rmax = 0.0;
+    for (int64_t k : r)
+      if (q->type[k] == SDPDEM_RIGID) {
+        rmax = std::max(rmax, q->radius[k]);
+        z.rbox[(size_t)slots[(size_t)q->id[k]]] = b;
+      }
+    BoxD& B = z.boxes[(size_t)b];
+    for (int a = 0; a < 3; ++a) {
+      B.org[a] = hb.org[a];
+      B.L[a] = hb.L[a];
+      B.halfL[a] = 0.5 * hb.L[a];
+      B.per[a] = hb.periodic[a] ? 1 : 0;
+    }
+    B.shear = hb.shear_rate;
+    B.le = hb.shear_rate != 0.0 ? 1 : 0;
+    B.le_jump = hb.shear_rate * hb.L[2];
+    B.le_shift = 0.0;
+    B.le_next = 0.0;
+    B.vol = hb.L[0] * hb.L[1] * hb.L[2];
+    if (!make_grid(hb, *q, r, P->h * (1.0 + 1e-6), B.g)) return false;
+    for (int a = 0; a < 3; ++a)
+      if (B.per[a] && B.g.nc[a] < 3) return false;
+    // rigid grid: cells at least H_max = R_max + h wide, so that the fluid
+    // particles coupled to a sphere lie in its 27 neighbouring cells
+    if (!make_grid(hb, *q, r, (rmax + P->h) * (1.0 + 1e-6), B.rg)) return false;
+    // DEM partners lie within R_s + R_k + h <= 2 R_max + h
+    double mincs = std::min(B.rg.cs[0], std::min(B.rg.cs[1], B.rg.cs[2]));
+    B.dem_reach = std::max(1, (int)std::ceil((2.0 * rmax + P->h) / mincs * (1.0 + 1e-9)));
+    B.cell_off = (int)coff;
+    B.rcell_off = (int)rcoff;
+    coff += B.g.ncells;
+    rcoff += B.rg.ncells;
+    if (coff > (int64_t)1 << 30 || rcoff > (int64_t)1 << 30) return false;
+    B.first = (int)first;
+    B.count = (int)r.size();
+    first += (int64_t)r.size();
+    B.noise = (hb.kBT > 0.0 && P->coeff_t != 0.0) ? 1 : 0;
+    B.kTf = (float)hb.kBT;
+    B.key0 = (uint32_t)(hb.seed & 0xffffffffu);
+    B.key1 = (uint32_t)(hb.seed >> 32);
+    for (int c = 0; c < (B.count + BS - 1) / BS; ++c)
+      z.blk.push_back(make_int2(b, B.first + c * BS));
+    for (int64_t k : r) z.order.push_back(k);
+  }
+  while (z.blk.size() < 8 || z.blk.size() % 8) z.blk.push_back(make_int2(-1, 0));
+  z.ncells_all = coff;
+  z.rncells_all = rcoff;
+  if (slot_of) *slot_of = slots;
   return true;
+}
+
+// the one box of a plain (non-batched) system, from the parameters
+sdpdem_box box_from_params(const sdpdem_params* P) {
+  sdpdem_box b{};
+  for (int a = 0; a < 3; ++a) {
+    b.org[a] = P->org[a];
+    b.L[a] = P->L[a];
+    b.periodic[a] = P->periodic[a];
+  }
+  b.shear_rate = P->shear_rate;
+  b.kBT = P->kBT;
+  b.seed = P->seed;
+  return b;
 }
 
 void fill_constants(sdpdem_system* s, const Sizes& z) {
@@ -309,14 +413,13 @@ void fill_constants(sdpdem_system* s, const Sizes& z) {
   d.npad = (int)z.npad;
   d.maxn = z.maxn;
   d.maxc = z.maxc;
+  d.nbox = z.nbox;
+  d.nblk = (int)z.blk.size();
+  d.ncells_all = (int)z.ncells_all;
+  d.rncells_all = (int)z.rncells_all;
   d.have_rxn = 0;
-  for (int a = 0; a < 3; ++a) {
-    d.org[a] = P.org[a];
-    d.L[a] = P.L[a];
-    d.halfL[a] = 0.5 * P.L[a];
-    d.per[a] = P.periodic[a] ? 1 : 0;
-    d.body[a] = P.g[a] + P.f[a];
-  }
+  d.stress = 0;
+  for (int a = 0; a < 3; ++a) d.body[a] = P.g[a] + P.f[a];
   d.noslip = P.noslip;
   d.h = P.h;
   d.h2 = P.h * P.h;
@@ -353,7 +456,6 @@ void fill_constants(sdpdem_system* s, const Sizes& z) {
   d.cFf = (float)(315.0 / (4.0 * kPi * std::pow(P.h, 5)));
   d.CAf = (float)(20.0 * P.eta / 3.0 - 4.0 * P.xi);
   d.CBf = (float)(17.0 * P.xi - 40.0 * P.eta / 3.0);
-  d.kTf = (float)P.kBT;
   d.inv_sqrt_dtf = (float)(1.0 / std::sqrt(P.dt));
   d.cC = (float)P.coeff_c;
   d.coef_c = P.coeff_c;
@@ -367,13 +469,10 @@ void fill_constants(sdpdem_system* s, const Sizes& z) {
   d.cR = (float)P.coeff_r;
   d.cT = (float)P.coeff_t;
   d.leverf = (float)(0.5 * P.dx);
-  d.key0 = (uint32_t)(P.seed & 0xffffffffu);
-  d.key1 = (uint32_t)(P.seed >> 32);
-  d.g = z.g;
-  d.rg = z.rg;
-  d.dem_reach = z.dem_reach;
   d.stamp = 0;
-  s->noise = P.kBT > 0.0 && P.coeff_t != 0.0;
+  s->noise = false;
+  for (const BoxD& B : z.boxes) s->noise = s->noise || B.noise;
+  s->h_boxes = z.boxes;
 }
 
 void bind_current(sdpdem_system* s) {
@@ -441,7 +540,7 @@ struct Prof {
 // pressure, smoothing, and the rigid grid.
 void run_build(sdpdem_system* s, hipStream_t st) {
   Dev& d = s->d;
-  const int nc = d.g.ncells;
+  const int nc = d.ncells_all;
   {
     Prof pr(s, SDPDEM_K_BIN, st);
     launch_fill_i32(d.count, 0, (size_t)nc, st);
@@ -470,11 +569,11 @@ void run_build(sdpdem_system* s, hipStream_t st) {
   }
   if (d.nr > 0) {
     Prof pr(s, SDPDEM_K_RIGID_GRID, st);
-    launch_fill_i32(d.rcount, 0, (size_t)d.rg.ncells, st);
+    launch_fill_i32(d.rcount, 0, (size_t)d.rncells_all, st);
     launch_bin_rigid(d, st);
-    launch_scan(d.rcount, d.rg.ncells, d.rstart, d.rcursor, s->rblock_sums, st);
+    launch_scan(d.rcount, d.rncells_all, d.rstart, d.rcursor, s->rblock_sums, st);
     launch_scatter(d.rkey, d.nr, d.rcursor, d.ritems, st);
-    launch_cell_sort(d.rstart, d.rg.ncells, d.ritems, nullptr, st);
+    launch_cell_sort(d.rstart, d.rncells_all, d.ritems, nullptr, st);
   }
 }
 
@@ -543,6 +642,109 @@ int sync_status(sdpdem_system* s, hipStream_t st) {
 }  // namespace
 
 
+namespace {
+
+int create_impl(const sdpdem_params* params, const sdpdem_box* boxes, int nbox,
+                const sdpdem_particles* q, const int32_t* box_of, void* d_workspace,
+                size_t workspace_bytes, void* hip_stream, sdpdem_system** out) {
+  if (!out) return SDPDEM_E_INVALID_ARG;
+  *out = nullptr;
+  Sizes z;
+  std::vector<int> slot_of;
+  if (!plan(params, boxes, nbox, q, box_of, z, &slot_of)) return SDPDEM_E_INVALID_ARG;
+  size_t need = layout(z, nullptr, nullptr);
+  if (!d_workspace) return SDPDEM_E_INVALID_ARG;
+  if (workspace_bytes < need) return SDPDEM_E_WORKSPACE_TOO_SMALL;
+  char* base = reinterpret_cast<char*>(((uintptr_t)d_workspace + 255) & ~(uintptr_t)255);
+  if ((size_t)(base - (char*)d_workspace) + need - 256 > workspace_bytes)
+    return SDPDEM_E_WORKSPACE_TOO_SMALL;
+  sdpdem_system* s = new (std::nothrow) sdpdem_system();
+  if (!s) return SDPDEM_E_INVALID_ARG;
+  s->P = *params;
+  layout(z, base, s);
+  fill_constants(s, z);
+  s->step = params->itr_start;
+  s->cur = 0;
+  s->ct_cur = 0;
+  s->h_gid2slot = slot_of;
+  bind_current(s);
+  hipStream_t st = (hipStream_t)hip_stream;
+  // stage the particles box by box, ids ascending inside a box: the order
+  // the kernels expect before the first sort
+  const int64_t n = q->n;
+  std::vector<D4> hp((size_t)n), hv((size_t)n), hw((size_t)n);
+  std::vector<uint8_t> ht((size_t)n);
+  std::vector<int> hg((size_t)n), hrg((size_t)z.nr, 0), hsort((size_t)z.nr, 0);
+  for (int64_t at = 0; at < n; ++at) {
+    const int64_t k = z.order[(size_t)at];
+    int64_t g = q->id[k];
+    uint8_t t = q->type[k];
+    bool rig = t == SDPDEM_RIGID;
+    hp[(size_t)at] = D4{q->pos[3 * k], q->pos[3 * k + 1], q->pos[3 * k + 2],
+                        rig ? q->radius[k] : 0.5 * params->dx};
+    hv[(size_t)at] = D4{q->vel[3 * k], q->vel[3 * k + 1], q->vel[3 * k + 2],
+                        rig ? q->mass[k] : params->mass_fluid};
+    hw[(size_t)at] = D4{q->angvel[3 * k], q->angvel[3 * k + 1], q->angvel[3 * k + 2],
+                        rig ? q->inertia[k] : params->inertia_fluid};
+    ht[(size_t)at] = t;
+    hg[(size_t)at] = (int)g;
+    if (rig) {
+      int sl = slot_of[(size_t)g];
+      hrg[(size_t)sl] = (int)g;
+      hsort[(size_t)sl] = (int)at;
+    }
+  }
+  Dev& d = s->d;
+  bool ok = true;
+  ok &= hipMemcpyAsync(s->pos[0], hp.data(), sizeof(D4) * n, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipMemcpyAsync(s->vel[0], hv.data(), sizeof(D4) * n, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipMemcpyAsync(s->om[0], hw.data(), sizeof(D4) * n, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipMemcpyAsync(s->type[0], ht.data(), n, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipMemcpyAsync(s->gid[0], hg.data(), sizeof(int) * n, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipMemcpyAsync(d.gid2slot, slot_of.data(), sizeof(int) * n, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipMemcpyAsync(s->boxes, z.boxes.data(), sizeof(BoxD) * z.nbox, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipMemcpyAsync(const_cast<int2*>(d.blk), z.blk.data(), sizeof(int2) * z.blk.size(),
+                       hipMemcpyHostToDevice, st) == hipSuccess;
+  if (z.nr) {
+    ok &= hipMemcpyAsync(d.rig_gid, hrg.data(), sizeof(int) * z.nr, hipMemcpyHostToDevice, st) == hipSuccess;
+    ok &= hipMemcpyAsync(d.rig_sorted, hsort.data(), sizeof(int) * z.nr, hipMemcpyHostToDevice, st) == hipSuccess;
+    ok &= hipMemcpyAsync(const_cast<int*>(d.rbox), z.rbox.data(), sizeof(int) * z.nr,
+                         hipMemcpyHostToDevice, st) == hipSuccess;
+  }
+  // the staging copies read pageable host memory: finish them before the
+  // host vectors go out of scope
+  ok &= hipStreamSynchronize(st) == hipSuccess;
+  launch_fill_i32(s->ct_cnt[0], 0, (size_t)z.nr, st);
+  launch_fill_i32(s->ct_cnt[1], 0, (size_t)z.nr, st);
+  launch_fill_i32(d.status, 0, 64, st);
+  launch_fill_i32(d.cstamp, 0, (size_t)z.npad, st);
+  launch_fill_i32(reinterpret_cast<int*>(d.fout), 0, 13 * (size_t)z.npad, st);
+  launch_fill_i32(d.nbr_cnt, 0, (size_t)z.npad, st);
+  launch_fill_i32(d.cstart, 0, (size_t)z.ncells_all + 1, st);
+  launch_fill_f64(d.f_dg, 0.0, 3 * (size_t)z.nr, st);
+  launch_fill_f64(d.f_pg, 0.0, 3 * (size_t)z.nr, st);
+  launch_fill_f64(d.f_dem, 0.0, 3 * (size_t)z.nr, st);
+  launch_fill_f64(d.f_lub, 0.0, 3 * (size_t)z.nr, st);
+  launch_fill_f64(d.n_dem, 0.0, 3 * (size_t)z.nr, st);
+  launch_fill_f64(d.eps, 0.0, (size_t)z.nr, st);
+  launch_fill_f64(d.omega, 0.0, (size_t)z.nr, st);
+  launch_fill_f64(d.wzx_r, 0.0, (size_t)z.nr, st);
+  launch_fill_f64(d.st_inst, 0.0, (size_t)z.nbox, st);
+  launch_fill_f64(d.st_sum, 0.0, (size_t)z.nbox, st);
+  launch_fill_f64(d.rho, params->rho0, (size_t)z.npad, st);
+  launch_fill_f64(d.p, 0.0, (size_t)z.npad, st);
+  ok &= hipStreamSynchronize(st) == hipSuccess;
+  ok &= hipGetLastError() == hipSuccess;
+  if (!ok) {
+    delete s;
+    return SDPDEM_E_HIP;
+  }
+  *out = s;
+  return SDPDEM_OK;
+}
+
+}  // namespace
+
 // ---------------------------------------------------------------------------
 // C ABI
 
@@ -562,108 +764,58 @@ int sdpdem_field_comps(int field) {
 
 int sdpdem_workspace_bytes(const sdpdem_params* params, const sdpdem_particles* particles,
                            size_t* bytes) {
-  if (!bytes) return SDPDEM_E_INVALID_ARG;
+  if (!bytes || !params) return SDPDEM_E_INVALID_ARG;
   Sizes z;
-  if (!plan(params, particles, z, nullptr)) return SDPDEM_E_INVALID_ARG;
+  sdpdem_box b = box_from_params(params);
+  if (!plan(params, &b, 1, particles, nullptr, z, nullptr)) return SDPDEM_E_INVALID_ARG;
   *bytes = layout(z, nullptr, nullptr);
   return SDPDEM_OK;
 }
 
 int sdpdem_create(const sdpdem_params* params, const sdpdem_particles* q, void* d_workspace,
                   size_t workspace_bytes, void* hip_stream, sdpdem_system** out) {
-  if (!out) return SDPDEM_E_INVALID_ARG;
-  *out = nullptr;
+  if (!params) return SDPDEM_E_INVALID_ARG;
+  sdpdem_box b = box_from_params(params);
+  return create_impl(params, &b, 1, q, nullptr, d_workspace, workspace_bytes, hip_stream, out);
+}
+
+int sdpdem_batch_workspace_bytes(const sdpdem_params* params, const sdpdem_box* boxes,
+                                 int32_t nbox, const sdpdem_particles* particles,
+                                 const int32_t* box_of, size_t* bytes) {
+  if (!bytes || !box_of) return SDPDEM_E_INVALID_ARG;
   Sizes z;
-  std::vector<int> slot_of;
-  if (!plan(params, q, z, &slot_of)) return SDPDEM_E_INVALID_ARG;
-  size_t need = layout(z, nullptr, nullptr);
-  if (!d_workspace) return SDPDEM_E_INVALID_ARG;
-  if (workspace_bytes < need) return SDPDEM_E_WORKSPACE_TOO_SMALL;
-  char* base = reinterpret_cast<char*>(((uintptr_t)d_workspace + 255) & ~(uintptr_t)255);
-  if ((size_t)(base - (char*)d_workspace) + need - 256 > workspace_bytes)
-    return SDPDEM_E_WORKSPACE_TOO_SMALL;
-  sdpdem_system* s = new (std::nothrow) sdpdem_system();
-  if (!s) return SDPDEM_E_INVALID_ARG;
-  s->P = *params;
-  layout(z, base, s);
-  fill_constants(s, z);
-  s->step = params->itr_start;
-  s->cur = 0;
-  s->ct_cur = 0;
-  s->h_gid2slot = slot_of;
-  bind_current(s);
-  hipStream_t st = (hipStream_t)hip_stream;
-  // stage the particles in id order
-  const int64_t n = q->n;
-  std::vector<D4> hp((size_t)n), hv((size_t)n), hw((size_t)n);
-  std::vector<uint8_t> ht((size_t)n);
-  std::vector<int> hg((size_t)n), hrg((size_t)z.nr, 0), hsort((size_t)z.nr, 0);
-  for (int64_t k = 0; k < n; ++k) {
-    int64_t g = q->id[k];
-    uint8_t t = q->type[k];
-    bool rig = t == SDPDEM_RIGID;
-    hp[(size_t)g] = D4{q->pos[3 * k], q->pos[3 * k + 1], q->pos[3 * k + 2],
-                       rig ? q->radius[k] : 0.5 * params->dx};
-    hv[(size_t)g] = D4{q->vel[3 * k], q->vel[3 * k + 1], q->vel[3 * k + 2],
-                       rig ? q->mass[k] : params->mass_fluid};
-    hw[(size_t)g] = D4{q->angvel[3 * k], q->angvel[3 * k + 1], q->angvel[3 * k + 2],
-                       rig ? q->inertia[k] : params->inertia_fluid};
-    ht[(size_t)g] = t;
-    hg[(size_t)g] = (int)g;
-    if (rig) {
-      int sl = slot_of[(size_t)g];
-      hrg[(size_t)sl] = (int)g;
-      hsort[(size_t)sl] = (int)g;
-    }
-  }
-  Dev& d = s->d;
-  bool ok = true;
-  ok &= hipMemcpyAsync(s->pos[0], hp.data(), sizeof(D4) * n, hipMemcpyHostToDevice, st) == hipSuccess;
-  ok &= hipMemcpyAsync(s->vel[0], hv.data(), sizeof(D4) * n, hipMemcpyHostToDevice, st) == hipSuccess;
-  ok &= hipMemcpyAsync(s->om[0], hw.data(), sizeof(D4) * n, hipMemcpyHostToDevice, st) == hipSuccess;
-  ok &= hipMemcpyAsync(s->type[0], ht.data(), n, hipMemcpyHostToDevice, st) == hipSuccess;
-  ok &= hipMemcpyAsync(s->gid[0], hg.data(), sizeof(int) * n, hipMemcpyHostToDevice, st) == hipSuccess;
-  ok &= hipMemcpyAsync(d.gid2slot, slot_of.data(), sizeof(int) * n, hipMemcpyHostToDevice, st) == hipSuccess;
-  if (z.nr) {
-    ok &= hipMemcpyAsync(d.rig_gid, hrg.data(), sizeof(int) * z.nr, hipMemcpyHostToDevice, st) == hipSuccess;
-    ok &= hipMemcpyAsync(d.rig_sorted, hsort.data(), sizeof(int) * z.nr, hipMemcpyHostToDevice, st) == hipSuccess;
-  }
-  launch_fill_i32(s->ct_cnt[0], 0, (size_t)z.nr, st);
-  launch_fill_i32(s->ct_cnt[1], 0, (size_t)z.nr, st);
-  launch_fill_i32(d.status, 0, 64, st);
-  launch_fill_i32(d.cstamp, 0, (size_t)z.npad, st);
-  launch_fill_i32(reinterpret_cast<int*>(d.fout), 0, 12 * (size_t)z.npad, st);
-  launch_fill_i32(d.nbr_cnt, 0, (size_t)z.npad, st);
-  launch_fill_i32(d.cstart, 0, (size_t)z.g.ncells + 1, st);
-  launch_fill_f64(d.f_dg, 0.0, 3 * (size_t)z.nr, st);
-  launch_fill_f64(d.f_pg, 0.0, 3 * (size_t)z.nr, st);
-  launch_fill_f64(d.f_dem, 0.0, 3 * (size_t)z.nr, st);
-  launch_fill_f64(d.f_lub, 0.0, 3 * (size_t)z.nr, st);
-  launch_fill_f64(d.n_dem, 0.0, 3 * (size_t)z.nr, st);
-  launch_fill_f64(d.eps, 0.0, (size_t)z.nr, st);
-  launch_fill_f64(d.omega, 0.0, (size_t)z.nr, st);
-  launch_fill_f64(d.rho, params->rho0, (size_t)z.npad, st);
-  launch_fill_f64(d.p, 0.0, (size_t)z.npad, st);
-  ok &= hipStreamSynchronize(st) == hipSuccess;
-  ok &= hipGetLastError() == hipSuccess;
-  if (!ok) {
-    delete s;
-    return SDPDEM_E_HIP;
-  }
-  *out = s;
+  if (!plan(params, boxes, nbox, particles, box_of, z, nullptr)) return SDPDEM_E_INVALID_ARG;
+  *bytes = layout(z, nullptr, nullptr);
   return SDPDEM_OK;
+}
+
+int sdpdem_create_batch(const sdpdem_params* params, const sdpdem_box* boxes, int32_t nbox,
+                        const sdpdem_particles* particles, const int32_t* box_of,
+                        void* d_workspace, size_t workspace_bytes, void* hip_stream,
+                        sdpdem_system** out) {
+  if (!box_of) return SDPDEM_E_INVALID_ARG;
+  return create_impl(params, boxes, nbox, particles, box_of, d_workspace, workspace_bytes,
+                     hip_stream, out);
 }
 
 int sdpdem_step(sdpdem_system* s, int64_t nsteps, void* hip_stream) {
   if (!s || nsteps < 0) return SDPDEM_E_INVALID_ARG;
   hipStream_t st = (hipStream_t)hip_stream;
+  Dev& d = s->d;
   for (int64_t it = 0; it < nsteps; ++it) {
+    // Lees-Edwards offsets for positions at this step and after the drift
+    launch_le_shift(s->boxes, d.nbox, s->step, d.dt, st);
     if (!s->cache_valid) run_build(s, st);
     run_pass(s, 1, 0, true, st);
     // positions moved: sort, neighbours, density and smoothing at x(n+1);
     // they stay valid for the first pass of the next step
+    launch_le_shift(s->boxes, d.nbox, s->step + 1, d.dt, st);
     run_build(s, st);
     run_pass(s, 2, 1, true, st);
+    if (s->stress) {
+      launch_box_stress(d, 1, st);
+      s->stress_samples += 1;
+    }
     s->cache_valid = true;
     s->step += 1;
   }
@@ -673,12 +825,45 @@ int sdpdem_step(sdpdem_system* s, int64_t nsteps, void* hip_stream) {
 int sdpdem_compute_forces(sdpdem_system* s, void* hip_stream) {
   if (!s) return SDPDEM_E_INVALID_ARG;
   hipStream_t st = (hipStream_t)hip_stream;
+  launch_le_shift(s->boxes, s->d.nbox, s->step, s->d.dt, st);
   if (!s->cache_valid) {
     run_build(s, st);
     s->cache_valid = true;
   }
   run_pass(s, 1, 0, false, st);
+  if (s->stress) launch_box_stress(s->d, 0, st);
   return sync_status(s, st);
+}
+
+int sdpdem_set_stress(sdpdem_system* s, int on, void* hip_stream) {
+  if (!s) return SDPDEM_E_INVALID_ARG;
+  hipStream_t st = (hipStream_t)hip_stream;
+  s->stress = on != 0;
+  s->d.stress = on ? 1 : 0;
+  s->stress_samples = 0;
+  launch_fill_f64(s->d.st_sum, 0.0, (size_t)s->d.nbox, st);
+  launch_fill_f64(s->d.st_inst, 0.0, (size_t)s->d.nbox, st);
+  if (s->d.nr) launch_fill_f64(s->d.wzx_r, 0.0, (size_t)s->d.nr, st);
+  launch_fill_i32(reinterpret_cast<int*>(s->d.fout + 12 * (size_t)s->d.npad), 0,
+                  (size_t)s->d.npad, st);
+  if (hipStreamSynchronize(st) != hipSuccess) return SDPDEM_E_HIP;
+  return hipGetLastError() == hipSuccess ? SDPDEM_OK : SDPDEM_E_HIP;
+}
+
+int sdpdem_box_stress(sdpdem_system* s, double* inst, double* sum, int64_t* nsamples,
+                      void* hip_stream) {
+  if (!s) return SDPDEM_E_INVALID_ARG;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const size_t nb = (size_t)s->d.nbox;
+  if (inst && hipMemcpyAsync(inst, s->d.st_inst, sizeof(double) * nb, hipMemcpyDeviceToHost,
+                             st) != hipSuccess)
+    return SDPDEM_E_HIP;
+  if (sum && hipMemcpyAsync(sum, s->d.st_sum, sizeof(double) * nb, hipMemcpyDeviceToHost, st) !=
+                 hipSuccess)
+    return SDPDEM_E_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return SDPDEM_E_HIP;
+  if (nsamples) *nsamples = s->stress_samples;
+  return hipGetLastError() == hipSuccess ? SDPDEM_OK : SDPDEM_E_HIP;
 }
 
 int sdpdem_read_field(sdpdem_system* s, int field, double* dst, size_t bytes, void* hip_stream) {
@@ -854,9 +1039,10 @@ int sdpdem_info(sdpdem_system* s, int64_t out[16], void* hip_stream) {
   out[0] = s->d.n;
   out[1] = s->d.nr;
   for (int a = 0; a < 3; ++a) {
-    out[2 + a] = s->d.g.nc[a];
-    out[5 + a] = s->d.rg.nc[a];
+    out[2 + a] = s->h_boxes[0].g.nc[a];
+    out[5 + a] = s->h_boxes[0].rg.nc[a];
   }
+  out[10] = s->d.nbox;
   std::vector<int> cnt((size_t)s->d.n);
   hipStream_t st = (hipStream_t)hip_stream;
   if (hipMemcpyAsync(cnt.data(), s->d.nbr_cnt, sizeof(int) * s->d.n, hipMemcpyDeviceToHost, st) !=

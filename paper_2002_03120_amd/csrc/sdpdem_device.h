@@ -6,7 +6,6 @@
 
 namespace sdpdem {
 
-static constexpr int BS = 256;
 static constexpr double PI = 3.14159265358979323846;
 
 inline int nblocks(size_t n, int bs = BS) {
@@ -20,6 +19,17 @@ __device__ __forceinline__ int xcd_tid() {
   unsigned nb = gridDim.x, b = blockIdx.x;
   unsigned lb = (nb % 8u == 0u) ? (b % 8u) * (nb / 8u) + (b / 8u) : b;
   return (int)(lb * blockDim.x + threadIdx.x);
+}
+
+// Launch block -> (box, first sorted particle): the box is uniform over a
+// block, so its constants are scalar loads.  Blocks are taken in XCD order
+// (block b runs on XCD b % 8; each XCD gets a contiguous run of the table).
+__device__ __forceinline__ int blk_box(const Dev& d, int& i) {
+  unsigned nb = gridDim.x, b = blockIdx.x;
+  unsigned lb = (nb % 8u == 0u) ? (b % 8u) * (nb / 8u) + (b / 8u) : b;
+  const int2 e = d.blk[lb];
+  i = e.y + (int)threadIdx.x;
+  return __builtin_amdgcn_readfirstlane(e.x);
 }
 
 __device__ __forceinline__ double min_img(double d, int per, double L, double halfL) {
@@ -41,6 +51,45 @@ __device__ __forceinline__ double r2_exact(double a, double b, double c) {
   double u = b * b;
   double v = c * c;
   return (t + u) + v;
+}
+
+// Minimum-image separation in box B, in place; returns k_z, the number of
+// boxes by which the partner's image is displaced along z (its velocity is
+// then v + k_z le_jump e_x).  With Lees-Edwards shear the z image is taken
+// first, its x offset applied, and x wrapped; otherwise axis by axis.
+__device__ __forceinline__ Geo geo_of(const BoxD& B) {
+  Geo g;
+  for (int a = 0; a < 3; ++a) {
+    g.L[a] = B.L[a];
+    g.halfL[a] = B.halfL[a];
+    g.per[a] = B.per[a];
+  }
+  g.le_shift = B.le_shift;
+  g.le_jump = B.le_jump;
+  g.le = B.le;
+  return g;
+}
+
+__device__ __forceinline__ int min_img_box(const Geo& B, double& ex, double& ey, double& ez) {
+#pragma clang fp contract(off)
+  int kz = 0;
+  if (B.per[2]) {
+    if (ez > B.halfL[2]) {
+      ez = ez - B.L[2];
+      kz = 1;
+    } else if (ez < -B.halfL[2]) {
+      ez = ez + B.L[2];
+      kz = -1;
+    }
+  }
+  if (B.le) {
+    ex = ex - B.le_shift * (double)kz;
+    ex = ex - B.L[0] * rint(ex / B.L[0]);
+  } else {
+    ex = min_img(ex, B.per[0], B.L[0], B.halfL[0]);
+  }
+  ey = min_img(ey, B.per[1], B.L[1], B.halfL[1]);
+  return kz;
 }
 
 __device__ __forceinline__ int cell_coord(double x, const Grid& g, int a, int* oob) {
@@ -94,6 +143,84 @@ __device__ __forceinline__ double sqrt_nr(double x) {
 
 // one 64-byte pair record (four 16-byte loads from one cache line)
 __device__ __forceinline__ PR load_pr(const PR* base, int j) { return base[j]; }
+
+// The cells within k of cell cc (local coordinates, particle x coordinate
+// px) of box B in grid G, as runs of consecutive x cells of one row:
+// fn(first_key, end_key) with global keys (off = the box's cell offset).
+// Rows seen through a Lees-Edwards z face are centred on the shifted x
+// coordinate and widened by one cell on each side; when the stencil wraps
+// onto itself along z under shear, every x cell is taken.
+template <class Fn>
+__device__ __forceinline__ void for_stencil(const Geo& B, const Grid& G, int off, double px,
+                                            const int cc[3], int k, Fn&& fn) {
+  const int nx = G.nc[0], ny = G.nc[1], nz = G.nc[2];
+  const bool zall = G.per[2] && 2 * k + 1 > nz;
+  const bool yall = G.per[1] && 2 * k + 1 > ny;
+  const int zlo = zall ? 0 : cc[2] - k, zn = zall ? nz : 2 * k + 1;
+  const int ylo = yall ? 0 : cc[1] - k, yn = yall ? ny : 2 * k + 1;
+  for (int iz = 0; iz < zn; ++iz) {
+    int z = zlo + iz, wz = 0;
+    if (z < 0) {
+      if (!G.per[2]) continue;
+      z += nz;
+      wz = -1;
+    } else if (z >= nz) {
+      if (!G.per[2]) continue;
+      z -= nz;
+      wz = 1;
+    }
+    int x0 = cc[0] - k, xn = 2 * k + 1;
+    if (B.le && (zall || wz != 0)) {
+      if (zall) {
+        x0 = 0;
+        xn = nx;
+      } else {
+        // candidates sit around x - k_z delta, k_z = wz
+        double xc = px - (double)wz * B.le_shift;
+        double f = floor((xc - G.lo[0]) * G.inv_cs[0]);
+        f = f - (double)nx * floor(f / (double)nx);
+        int c = (int)f;
+        if (c < 0) c = 0;
+        if (c >= nx) c = nx - 1;
+        x0 = c - k - 1;
+        xn = 2 * k + 3;
+      }
+    }
+    bool xall = G.per[0] && xn >= nx;
+    if (xall) {
+      x0 = 0;
+      xn = nx;
+    }
+    for (int iy = 0; iy < yn; ++iy) {
+      int y = ylo + iy;
+      if (y < 0) {
+        if (!G.per[1]) continue;
+        y += ny;
+      } else if (y >= ny) {
+        if (!G.per[1]) continue;
+        y -= ny;
+      }
+      const int rowkey = off + (z * ny + y) * nx;
+      if (xall) {
+        fn(rowkey, rowkey + nx);
+      } else if (!G.per[0]) {
+        int a = max(x0, 0), b = min(x0 + xn - 1, nx - 1);
+        if (a <= b) fn(rowkey + a, rowkey + b + 1);
+      } else {
+        int a = x0, b = x0 + xn - 1;  // at most one wrap
+        if (a < 0) {
+          fn(rowkey + a + nx, rowkey + nx);
+          fn(rowkey, rowkey + b + 1);
+        } else if (b >= nx) {
+          fn(rowkey + a, rowkey + nx);
+          fn(rowkey, rowkey + b - nx + 1);
+        } else {
+          fn(rowkey + a, rowkey + b + 1);
+        }
+      }
+    }
+  }
+}
 
 // Lucy kernel with support H (Eq. kernel), double precision
 __device__ __forceinline__ double lucy_w(double r, double H) {

@@ -10,6 +10,8 @@
 
 namespace sdpdem {
 
+static constexpr int BS = 256;  // threads per block of the particle kernels
+
 enum : uint8_t { T_FLUID = 0, T_RIGID = 1, T_INNER = 2, T_OUTER = 3 };
 
 // status bits raised by kernels (sticky until the system is destroyed)
@@ -36,7 +38,7 @@ struct __align__(64) PR {
   double x, y, z;
   float vx, vy, vz, pc;
   float wx, wy, wz, invd;
-  int gid, pad;
+  int gid, type;
 };
 static_assert(sizeof(PR) == 64, "pair record must be 64 bytes");
 
@@ -52,15 +54,48 @@ struct Grid {
   int ncells;
 };
 
+// One box of a batch: an independent domain with its own periodic or wall
+// axes, optional Lees-Edwards shear (flow x, gradient z), thermal energy and
+// noise key, and its own fluid and rigid cell grids.  The boxes' cells are
+// numbered consecutively (cell_off, rcell_off), so the counting sort puts
+// the particles of a box into one fixed contiguous range [first, first +
+// count) of the sorted arrays.
+struct BoxD {
+  double org[3], L[3], halfL[3];
+  double shear;       // shear rate (0: plain images)
+  double le_jump;     // shear * L_z: x velocity of the image above
+  double le_shift;    // x offset of the image above at the current position time
+  double le_next;     // the same at the time the drift of this step moves to
+  double vol;         // L_x L_y L_z
+  Grid g, rg;         // fluid and rigid grids (local cell numbers)
+  int per[3];
+  int le;             // shear != 0
+  int cell_off, rcell_off;
+  int first, count;   // sorted particle range
+  int dem_reach;      // rigid-grid cells to search for DEM partners
+  int noise;          // thermal forces on
+  float kTf;
+  uint32_t key0, key1;
+};
+
+// The part of a box the pair loops need, copied into registers once per
+// thread (the box table itself could alias the loops' stores).
+struct Geo {
+  double L[3], halfL[3];
+  double le_shift, le_jump;
+  int per[3];
+  int le;
+};
+
 // Everything a kernel reads, passed by value.  Particle arrays are in the
 // current cell-sorted order; rigid arrays are indexed by rigid slot (the
 // rank of the rigid particle's id among all rigid ids).
 struct Dev {
   int n, nr, npad, maxn, maxc;
+  int nbox;
   int have_rxn;  // the drag reaction of the last evaluation is valid
+  int stress;    // accumulate the pair virial of the force pass
   // constants
-  double org[3], L[3], halfL[3];
-  int per[3];
   int noslip;
   double h, h2, inv_h, dx, lever;
   double rho0, p0, alpha, beta, p_ref, m_f, I_f;
@@ -76,9 +111,12 @@ struct Dev {
   // single-precision pair constants
   float kAf, kBf, kRf;  // folded coefficients of the pair force
   double coef_c;
-  float hf, inv_hf, cFf, CAf, CBf, kTf, inv_sqrt_dtf, cC, cD, cR, cT, leverf;
-  uint32_t key0, key1;
-  Grid g, rg;
+  float hf, inv_hf, cFf, CAf, CBf, inv_sqrt_dtf, cC, cD, cR, cT, leverf;
+  int ncells_all, rncells_all;  // cells of all boxes
+  const BoxD* boxes;
+  const int2* blk;   // per launch block: (box, first sorted index); box -1 = idle
+  int nblk;          // a multiple of 8
+  const int* rbox;   // box of every rigid slot
   // particles (current buffer)
   D4* pos;  // x, y, z, radius (lever for fluid and walls)
   D4* vel;  // vx, vy, vz, mass
@@ -88,7 +126,7 @@ struct Dev {
   // sort scratch
   uint32_t* key;
   int* count;
-  int* cstart;  // ncells + 1
+  int* cstart;  // ncells_all + 1
   int* cursor;
   int* perm;
   // neighbours and fields
@@ -98,7 +136,7 @@ struct Dev {
   double* p;
   float* ps;
   PR* prec;  // pair records, sorted order
-  float* fout;  // 12 planes of npad: F_sdpd(3) N_sdpd(3) F_cd(3) F_rxn(3)
+  float* fout;  // 13 planes of npad: F_sdpd(3) N_sdpd(3) F_cd(3) F_rxn(3) W_zx
   // rigid
   int* gid2slot;
   int* rig_sorted;
@@ -110,6 +148,7 @@ struct Dev {
   double* n_dem;
   double* eps;
   double* omega;
+  double* wzx_r;  // virial W_zx of every rigid slot (coupling + contacts)
   uint32_t* rkey;
   int* rcount;
   int* rstart;
@@ -121,13 +160,15 @@ struct Dev {
   D4* rom_c;
   D4* rdg_c;       // F^DG / Omega of the sphere, w = 1 if it couples
   int* rslot_pos;  // slot -> t
-  int dem_reach;   // rigid-grid cells to search for DEM partners
   // fluid particles coupled to a sphere in the current pass carry the stamp
   int* cstamp;
   int stamp;
   int* ct_cnt;      // current contact table
   int* ct_partner;  // partner id
   double* ct_dt;
+  // per-box pressure-tensor samples: P_zx now, its running sum and count
+  double* st_inst;
+  double* st_sum;
   int* status;
 };
 
@@ -147,6 +188,10 @@ void launch_cell_sort(const int* start, int ncells, int* perm, const int* sortke
 void launch_permute(const Dev& d, const D4* spos, const D4* svel, const D4* som,
                     const uint8_t* stype, const int* sgid, hipStream_t st);
 void launch_build_density(const Dev& d, hipStream_t st);
+// Lees-Edwards offsets of every box for positions at step pos_step
+void launch_le_shift(BoxD* boxes, int nbox, int64_t pos_step, double dt, hipStream_t st);
+// per-box sample of P_zx; with accumulate, also added to the running sums
+void launch_box_stress(const Dev& d, int accumulate, hipStream_t st);
 void launch_smooth(const Dev& d, hipStream_t st);
 void launch_fluid_forces(const Dev& d, uint32_t step, bool noise, hipStream_t st);
 void launch_rigid_gather(const Dev& d, hipStream_t st);

@@ -42,33 +42,37 @@ void launch_fill_f64(double* a, double v, size_t count, hipStream_t st) {
 // (a1) binning and counting sort
 
 __global__ __launch_bounds__(BS) void k_bin(Dev d) {
-  int i = xcd_tid();
-  if (i >= d.n) return;
+  int i;
+  const int b = blk_box(d, i);
+  if (b < 0) return;
+  const BoxD& B = d.boxes[b];
+  if (i >= B.first + B.count) return;
   D4 p = d.pos[i];
   int oob = 0;
-  int cx = cell_coord(p.x, d.g, 0, &oob);
-  int cy = cell_coord(p.y, d.g, 1, &oob);
-  int cz = cell_coord(p.z, d.g, 2, &oob);
+  int cx = cell_coord(p.x, B.g, 0, &oob);
+  int cy = cell_coord(p.y, B.g, 1, &oob);
+  int cz = cell_coord(p.z, B.g, 2, &oob);
   if (oob) atomicOr(d.status, ST_OUT_OF_DOMAIN);
-  int c = cell_index(d.g, cx, cy, cz);
+  int c = B.cell_off + cell_index(B.g, cx, cy, cz);
   d.key[i] = (uint32_t)c;
   atomicAdd(&d.count[c], 1);
 }
 
 void launch_bin(const Dev& d, hipStream_t st) {
-  k_bin<<<nblocks(d.n), BS, 0, st>>>(d);
+  k_bin<<<d.nblk, BS, 0, st>>>(d);
 }
 
 __global__ __launch_bounds__(BS) void k_bin_rigid(Dev d) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= d.nr) return;
+  const BoxD& B = d.boxes[d.rbox[s]];
   D4 p = d.pos[d.rig_sorted[s]];
   int oob = 0;
-  int cx = cell_coord(p.x, d.rg, 0, &oob);
-  int cy = cell_coord(p.y, d.rg, 1, &oob);
-  int cz = cell_coord(p.z, d.rg, 2, &oob);
+  int cx = cell_coord(p.x, B.rg, 0, &oob);
+  int cy = cell_coord(p.y, B.rg, 1, &oob);
+  int cz = cell_coord(p.z, B.rg, 2, &oob);
   if (oob) atomicOr(d.status, ST_OUT_OF_DOMAIN);
-  int c = cell_index(d.rg, cx, cy, cz);
+  int c = B.rcell_off + cell_index(B.rg, cx, cy, cz);
   d.rkey[s] = (uint32_t)c;
   atomicAdd(&d.rcount[c], 1);
 }
@@ -76,6 +80,34 @@ __global__ __launch_bounds__(BS) void k_bin_rigid(Dev d) {
 void launch_bin_rigid(const Dev& d, hipStream_t st) {
   if (d.nr == 0) return;
   k_bin_rigid<<<(d.nr + BS - 1) / BS, BS, 0, st>>>(d);
+}
+
+// Lees-Edwards offsets delta(t) = fmod(shear L_z t, L_x) of every box for
+// positions at step pos_step and at the step after
+__global__ void k_le_shift(BoxD* boxes, int nbox, int64_t pos_step, double dt) {
+#pragma clang fp contract(off)
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbox) return;
+  BoxD& B = boxes[b];
+  if (!B.le) {
+    B.le_shift = 0.0;
+    B.le_next = 0.0;
+    return;
+  }
+  for (int k = 0; k < 2; ++k) {
+    double t = (double)(pos_step + k) * dt;
+    double v = (B.shear * B.L[2]) * t;
+    double sft = fmod(v, B.L[0]);
+    if (sft < 0.0) sft += B.L[0];
+    if (k == 0)
+      B.le_shift = sft;
+    else
+      B.le_next = sft;
+  }
+}
+
+void launch_le_shift(BoxD* boxes, int nbox, int64_t pos_step, double dt, hipStream_t st) {
+  k_le_shift<<<(nbox + 63) / 64, 64, 0, st>>>(boxes, nbox, pos_step, dt);
 }
 
 static constexpr int SCAN_ITEMS = 8;
@@ -261,16 +293,11 @@ __device__ __forceinline__ int wave_sum_i(int v) {
   return v;
 }
 
-// cells within reach of a sphere of radius H around a cell coordinate
-__device__ __forceinline__ void reach(const Grid& g, int a, int c, double H, int& lo, int& cnt) {
-  int k = (int)ceil(H * g.inv_cs[a] * (1.0 + 1e-9));
-  if (g.per[a] && 2 * k + 1 >= g.nc[a]) {
-    lo = 0;
-    cnt = g.nc[a];
-    return;
-  }
-  lo = c - k;
-  cnt = 2 * k + 1;
+// cells to search around a point for partners within H (largest over the axes)
+__device__ __forceinline__ int reach_cells(const Grid& g, double H) {
+  int k = 1;
+  for (int a = 0; a < 3; ++a) k = max(k, (int)ceil(H * g.inv_cs[a] * (1.0 + 1e-9)));
+  return k;
 }
 
 __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
@@ -278,47 +305,51 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
   const int lane = threadIdx.x & 63;
   if (wave >= d.nr) return;
   // spheres in rigid-grid cell order: neighbouring waves share cache lines
-  const int s = d.ritems[wave];
+  const int s = __builtin_amdgcn_readfirstlane(d.ritems[wave]);
   const int si = d.rig_sorted[s];
+  const BoxD& B = d.boxes[__builtin_amdgcn_readfirstlane(d.rbox[s])];
+  const Geo G = geo_of(B);
+  const Grid gr = B.g;
+  const int coff = B.cell_off;
   const D4 ps = d.pos[si];
   const double R = ps.w, H = R + d.h, H2 = H * H;
   int oob = 0;
-  int c[3] = {cell_coord(ps.x, d.g, 0, &oob), cell_coord(ps.y, d.g, 1, &oob),
-              cell_coord(ps.z, d.g, 2, &oob)};
-  int lo[3], cnt[3];
-  for (int a = 0; a < 3; ++a) reach(d.g, a, c[a], H, lo[a], cnt[a]);
-  const int nbox = cnt[0] * cnt[1] * cnt[2];
+  const int cc[3] = {cell_coord(ps.x, gr, 0, &oob), cell_coord(ps.y, gr, 1, &oob),
+                     cell_coord(ps.z, gr, 2, &oob)};
+  const int kr = reach_cells(gr, H);
   const size_t np = (size_t)d.npad;
-  double om = 0, v0 = 0, v1 = 0, v2 = 0, f0 = 0, f1 = 0, f2 = 0;
+  double om = 0, v0 = 0, v1 = 0, v2 = 0, f0 = 0, f1 = 0, f2 = 0, l0 = 0, l1 = 0, l2 = 0;
   int nrig = 0;
-  for (int cb = 0; cb < nbox; cb += 64) {
-    // lane r describes cell cb + r of the search box: one contiguous slice
-    int s0 = 0, l0 = 0;
-    int cidx = cb + lane;
-    if (cidx < nbox) {
-      int x = lo[0] + cidx % cnt[0];
-      int y = lo[1] + (cidx / cnt[0]) % cnt[1];
-      int z = lo[2] + cidx / (cnt[0] * cnt[1]);
-      if (wrap_axis(x, d.g.nc[0], d.g.per[0]) && wrap_axis(y, d.g.nc[1], d.g.per[1]) &&
-          wrap_axis(z, d.g.nc[2], d.g.per[2])) {
-        int key = cell_index(d.g, x, y, z);
-        s0 = d.cstart[key];
-        l0 = d.cstart[key + 1] - s0;
-      }
+  // the search box as runs of consecutive cells; lane r takes run r of each
+  // batch of 64 runs (every lane enumerates the same runs)
+  int nruns = 0;
+  for_stencil(G, gr, coff, ps.x, cc, kr, [&](int, int) { ++nruns; });
+  for (int rb = 0; rb < nruns; rb += 64) {
+    int s0 = 0, len = 0;
+    {
+      int r = 0;
+      const int want = rb + lane;
+      for_stencil(G, gr, coff, ps.x, cc, kr, [&](int k0, int k1) {
+        if (r == want) {
+          s0 = d.cstart[k0];
+          len = d.cstart[k1] - s0;
+        }
+        ++r;
+      });
     }
-    int inc = l0;
+    int inc = len;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       int t = __shfl_up(inc, o, 64);
       if (lane >= o) inc += t;
     }
     const int total = __shfl(inc, 63, 64);
-    const int off = inc - l0;
-    // every lane takes one candidate of the concatenated slices per round;
+    const int off = inc - len;
+    // every lane takes one candidate of the concatenated runs per round;
     // all lanes stay active through the shuffles
     for (int base = 0; base < total; base += 64) {
       const int t = base + lane;
-      int r = 0;  // last cell whose offset is <= t
+      int r = 0;  // last run whose offset is <= t
 #pragma unroll
       for (int stp = 32; stp > 0; stp >>= 1) {
         int cand = r + stp;
@@ -333,9 +364,8 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
       uint8_t tj = d.type[j];
       if (tj != T_FLUID && tj != T_RIGID) continue;
       D4 pj = d.pos[j];
-      double ex = min_img(ps.x - pj.x, d.per[0], d.L[0], d.halfL[0]);
-      double ey = min_img(ps.y - pj.y, d.per[1], d.L[1], d.halfL[1]);
-      double ez = min_img(ps.z - pj.z, d.per[2], d.L[2], d.halfL[2]);
+      double ex = ps.x - pj.x, ey = ps.y - pj.y, ez = ps.z - pj.z;
+      const int kz = min_img_box(G, ex, ey, ez);
       double r2 = r2_exact(ex, ey, ez);
       if (!(r2 < H2)) continue;
       if (tj == T_RIGID) {
@@ -345,12 +375,15 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
       double w = lucy_w(sqrt(r2), H);
       D4 vj = d.vel[j];
       om += w;
-      v0 += w * vj.x;
+      v0 += w * (vj.x + (double)kz * G.le_jump);  // image velocity (Lees-Edwards)
       v1 += w * vj.y;
       v2 += w * vj.z;
       f0 += w * (double)d.fout[6 * np + j];
       f1 += w * (double)d.fout[7 * np + j];
       f2 += w * (double)d.fout[8 * np + j];
+      l0 += w * ex;
+      l1 += w * ey;
+      l2 += w * ez;
       d.cstamp[j] = d.stamp;
     }
   }
@@ -361,6 +394,11 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
   f0 = wave_sum(f0);
   f1 = wave_sum(f1);
   f2 = wave_sum(f2);
+  if (d.stress) {
+    l0 = wave_sum(l0);
+    l1 = wave_sum(l1);
+    l2 = wave_sum(l2);
+  }
   nrig = wave_sum_i(nrig);
   if (lane != 0) return;
   const double Vs = 4.0 / 3.0 * PI * R * R * R;
@@ -374,9 +412,9 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
     const D4 vs = d.vel[si];
     double dv[3] = {vs.x - v0 / om, vs.y - v1 / om, vs.z - v2 / om};
     double dva = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-    double B = drag_b(eps, dva, 2.0 * R, d.rho0, d.eta);
+    double B_ = drag_b(eps, dva, 2.0 * R, d.rho0, d.eta);
     double kp = d.rho0 * Vs / d.m_f;
-    for (int a = 0; a < 3; ++a) dg[a] = -B * Vs * dv[a];
+    for (int a = 0; a < 3; ++a) dg[a] = -B_ * Vs * dv[a];
     pg[0] = kp * (f0 / om);
     pg[1] = kp * (f1 / om);
     pg[2] = kp * (f2 / om);
@@ -385,6 +423,9 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
     d.f_dg[3 * s + a] = dg[a];
     d.f_pg[3 * s + a] = pg[a];
   }
+  // virial of the coupling: lever (sum_j w_sj r_sj / Omega_s)_z times the
+  // x force; the contacts add theirs later in the pass
+  if (d.stress) d.wzx_r[s] = om > 0.0 ? (l2 / om) * (dg[0] + pg[0]) : 0.0;
   // F^DG / Omega beside the sphere's cell-ordered record, for the reaction
   D4 rc;
   rc.x = om > 0.0 ? dg[0] / om : 0.0;
@@ -400,64 +441,33 @@ void launch_fpi_action(const Dev& d, hipStream_t st) {
   k_fpi_action<<<(d.nr + waves_per_block - 1) / waves_per_block, BS, 0, st>>>(d);
 }
 
-// cells of the rigid grid (linear keys) within `k` cells of a coordinate
-// (each at most once on a periodic axis shorter than 2k+1 cells)
-template <class Fn>
-__device__ __forceinline__ void for_rigid_stencil(const Grid& G, const int cc[3], int k, Fn&& fn) {
-  int lo[3], cnt[3];
-  for (int a = 0; a < 3; ++a) {
-    if (G.per[a] && G.nc[a] < 2 * k + 1) {
-      lo[a] = 0;
-      cnt[a] = G.nc[a];
-    } else {
-      lo[a] = cc[a] - k;
-      cnt[a] = 2 * k + 1;
-    }
-  }
-  for (int kz = 0; kz < cnt[2]; ++kz) {
-    int z = lo[2] + kz;
-    if (!wrap_axis(z, G.nc[2], G.per[2])) continue;
-    for (int ky = 0; ky < cnt[1]; ++ky) {
-      int y = lo[1] + ky;
-      if (!wrap_axis(y, G.nc[1], G.per[1])) continue;
-      int x0 = lo[0], x1 = lo[0] + cnt[0] - 1;
-      if (!G.per[0]) {
-        x0 = max(x0, 0);
-        x1 = min(x1, G.nc[0] - 1);
-        if (x0 <= x1) fn(cell_index(G, x0, y, z), cell_index(G, x1, y, z) + 1);
-      } else {
-        for (int kx = 0; kx < cnt[0]; ++kx) {
-          int x = lo[0] + kx;
-          wrap_axis(x, G.nc[0], 1);
-          fn(cell_index(G, x, y, z), cell_index(G, x, y, z) + 1);
-        }
-      }
-    }
-  }
-}
-
 // (a7) reaction on the stamped fluid particles, Eq. F_fpi_DG_reac
 // normalised per rigid particle: -sum_s F^DG_s w_sj / Omega_s over the
 // rigid s with j in C_s.  The rigid grid's cells are at least H_max wide.
 __global__ __launch_bounds__(BS) void k_fpi_reaction(Dev d) {
-  int i = xcd_tid();
-  if (i >= d.n) return;
+  int i;
+  const int b = blk_box(d, i);
+  if (b < 0) return;
+  const BoxD& B = d.boxes[b];
+  if (i >= B.first + B.count) return;
   if (d.cstamp[i] != d.stamp || d.type[i] != T_FLUID) return;
   D4 pi = d.pos[i];
+  const Geo G = geo_of(B);
+  const Grid gr = B.rg;
+  const int coff = B.rcell_off;
   int oob = 0;
-  int cc[3] = {cell_coord(pi.x, d.rg, 0, &oob), cell_coord(pi.y, d.rg, 1, &oob),
-               cell_coord(pi.z, d.rg, 2, &oob)};
+  int cc[3] = {cell_coord(pi.x, gr, 0, &oob), cell_coord(pi.y, gr, 1, &oob),
+               cell_coord(pi.z, gr, 2, &oob)};
   double a0 = 0, a1 = 0, a2 = 0;
-  for_rigid_stencil(d.rg, cc, 1, [&](int cb, int ce) {
+  for_stencil(G, gr, coff, pi.x, cc, 1, [&](int cb, int ce) {
     int tb = d.rstart[cb], te = d.rstart[ce];
     for (int t = tb; t < te; ++t) {
       D4 g = d.rdg_c[t];
       if (g.w == 0.0) continue;
       D4 ps = d.rpos_c[t];
       double H = ps.w + d.h;
-      double ex = min_img(ps.x - pi.x, d.per[0], d.L[0], d.halfL[0]);
-      double ey = min_img(ps.y - pi.y, d.per[1], d.L[1], d.halfL[1]);
-      double ez = min_img(ps.z - pi.z, d.per[2], d.L[2], d.halfL[2]);
+      double ex = ps.x - pi.x, ey = ps.y - pi.y, ez = ps.z - pi.z;
+      min_img_box(G, ex, ey, ez);
       double r2 = r2_exact(ex, ey, ez);
       if (!(r2 < H * H)) continue;
       double w = lucy_w(sqrt(r2), H);
@@ -473,7 +483,7 @@ __global__ __launch_bounds__(BS) void k_fpi_reaction(Dev d) {
 }
 
 void launch_fpi_reaction(const Dev& d, hipStream_t st) {
-  k_fpi_reaction<<<nblocks(d.n), BS, 0, st>>>(d);
+  k_fpi_reaction<<<d.nblk, BS, 0, st>>>(d);
 }
 
 // ---------------------------------------------------------------------------
@@ -489,32 +499,37 @@ __global__ __launch_bounds__(DEM_BS) void k_dem(Dev d, int commit, int* nxt_cnt,
                                                int* nxt_partner, double* nxt_dt) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= d.nr) return;
+  const BoxD& B = d.boxes[d.rbox[s]];
+  const Geo G = geo_of(B);
+  const Grid gr = B.rg;
+  const int coff = B.rcell_off, reach = B.dem_reach;
   const int me = d.rslot_pos[s];
   const D4 ps = d.rpos_c[me], vs = d.rvel_c[me], ws = d.rom_c[me];
   const double Rs = ps.w, ms = vs.w;
   const double Di = (1.0 - d.nu * d.nu) / (d.E * PI);
   int oob = 0;
-  int cc[3] = {cell_coord(ps.x, d.rg, 0, &oob), cell_coord(ps.y, d.rg, 1, &oob),
-               cell_coord(ps.z, d.rg, 2, &oob)};
+  int cc[3] = {cell_coord(ps.x, gr, 0, &oob), cell_coord(ps.y, gr, 1, &oob),
+               cell_coord(ps.z, gr, 2, &oob)};
   const int mc = d.maxc;
   const int ocnt = d.ct_cnt[s];
   double F[3] = {0, 0, 0}, FL[3] = {0, 0, 0}, N[3] = {0, 0, 0};
+  double Wzx = 0.0;
   int ncnt = 0;
   int overflow = 0;
-  for_rigid_stencil(d.rg, cc, d.dem_reach, [&](int cb, int ce) {
+  for_stencil(G, gr, coff, ps.x, cc, reach, [&](int cb, int ce) {
     int tb = d.rstart[cb], te = d.rstart[ce];
     for (int t = tb; t < te; ++t) {
       if (t == me) continue;
       D4 pk = d.rpos_c[t];
       double Rk = pk.w;
-      double e0 = min_img(ps.x - pk.x, d.per[0], d.L[0], d.halfL[0]);
-      double e1 = min_img(ps.y - pk.y, d.per[1], d.L[1], d.halfL[1]);
-      double e2 = min_img(ps.z - pk.z, d.per[2], d.L[2], d.halfL[2]);
+      double e0 = ps.x - pk.x, e1 = ps.y - pk.y, e2 = ps.z - pk.z;
+      const int kz = min_img_box(G, e0, e1, e2);
       double L2 = r2_exact(e0, e1, e2);
       double reachk = Rs + Rk + d.h;
       if (!(L2 < reachk * reachk)) continue;
       double L = sqrt(L2);
       D4 vk = d.rvel_c[t];
+      vk.x += (double)kz * G.le_jump;  // image velocity (Lees-Edwards)
       if (L < Rs + Rk) {
         D4 wk = d.rom_c[t];
         int gk = d.rig_gid[d.ritems[t]];
@@ -577,6 +592,7 @@ __global__ __launch_bounds__(DEM_BS) void k_dem(Dev d, int commit, int* nxt_cnt,
         F[0] += fn0 + ft0;
         F[1] += fn1 + ft1;
         F[2] += fn2 + ft2;
+        Wzx += 0.5 * e2 * (fn0 + ft0);
         // torque R_s (-n) x F_t
         N[0] += -Rs * (n1 * ft2 - n2 * ft1);
         N[1] += -Rs * (n2 * ft0 - n0 * ft2);
@@ -601,6 +617,7 @@ __global__ __launch_bounds__(DEM_BS) void k_dem(Dev d, int commit, int* nxt_cnt,
           FL[0] += c * (vk.x - vs.x);
           FL[1] += c * (vk.y - vs.y);
           FL[2] += c * (vk.z - vs.z);
+          Wzx += 0.5 * e2 * (c * (vk.x - vs.x));
         }
       }
     }
@@ -610,6 +627,7 @@ __global__ __launch_bounds__(DEM_BS) void k_dem(Dev d, int commit, int* nxt_cnt,
     d.f_lub[3 * s + a] = FL[a];
     d.n_dem[3 * s + a] = N[a];
   }
+  if (d.stress) d.wzx_r[s] += Wzx;
   if (commit) {
     nxt_cnt[s] = ncnt;
     if (overflow) atomicOr(d.status, ST_CONTACT_OVERFLOW);
@@ -625,12 +643,13 @@ void launch_dem(const Dev& d, int commit, int* nxt_cnt, int* nxt_partner, double
 // ---------------------------------------------------------------------------
 // (a9) velocity Verlet (Alg. 1, update) with the boundary treatment.
 
-__device__ __forceinline__ void total_force(const Dev& d, int i, uint8_t t, const D4& p,
-                                            int rigid_active, double F[3], double N[3]) {
+__device__ __forceinline__ void total_force(const Dev& d, const BoxD& B, int i, uint8_t t,
+                                            const D4& p, int rigid_active, double F[3],
+                                            double N[3]) {
   double sg = 1.0;
   if (d.gtype == 1) {
     double x = d.gaxis == 0 ? p.x : (d.gaxis == 1 ? p.y : p.z);
-    sg = (x - d.org[d.gaxis] >= 0.5 * d.L[d.gaxis]) ? 1.0 : -1.0;
+    sg = (x - B.org[d.gaxis] >= 0.5 * B.L[d.gaxis]) ? 1.0 : -1.0;
   }
   const size_t np = (size_t)d.npad;
   double m = d.vel[i].w;
@@ -656,14 +675,17 @@ __device__ __forceinline__ void total_force(const Dev& d, int i, uint8_t t, cons
 }
 
 __global__ __launch_bounds__(BS) void k_integrate(Dev d, int velver, int rigid_active) {
-  int i = xcd_tid();
-  if (i >= d.n) return;
+  int i;
+  const int b = blk_box(d, i);
+  if (b < 0) return;
+  const BoxD& B = d.boxes[b];
+  if (i >= B.first + B.count) return;
   uint8_t t = d.type[i];
   if (t == T_OUTER) return;
   if (t == T_RIGID && !rigid_active) return;
   D4 p = d.pos[i], v = d.vel[i], w = d.om[i];
   double F[3], N[3];
-  total_force(d, i, t, p, rigid_active, F, N);
+  total_force(d, B, i, t, p, rigid_active, F, N);
   const double hdt = 0.5 * d.dt;
   v.x += hdt * F[0] / v.w;
   v.y += hdt * F[1] / v.w;
@@ -675,13 +697,29 @@ __global__ __launch_bounds__(BS) void k_integrate(Dev d, int velver, int rigid_a
   if (velver == 1 && (t == T_FLUID || t == T_RIGID)) {
     double x[3] = {p.x + d.dt * v.x, p.y + d.dt * v.y, p.z + d.dt * v.z};
     double vv[3] = {v.x, v.y, v.z};
+    if (B.le) {
+      // through a sheared z face: re-enter as the image of the next box
+      if (x[2] < B.org[2]) {
+        x[2] += B.L[2];
+        x[0] += B.le_next;
+        vv[0] += B.le_jump;
+      } else if (x[2] >= B.org[2] + B.L[2]) {
+        x[2] -= B.L[2];
+        x[0] -= B.le_next;
+        vv[0] -= B.le_jump;
+      }
+      if (x[0] < B.org[0])
+        x[0] += B.L[0];
+      else if (x[0] >= B.org[0] + B.L[0])
+        x[0] -= B.L[0];
+    }
     for (int a = 0; a < 3; ++a) {
-      double lo = d.org[a], hi = d.org[a] + d.L[a];
-      if (d.per[a]) {
+      double lo = B.org[a], hi = B.org[a] + B.L[a];
+      if (B.per[a]) {
         if (x[a] < lo)
-          x[a] += d.L[a];
+          x[a] += B.L[a];
         else if (x[a] >= hi)
-          x[a] -= d.L[a];
+          x[a] -= B.L[a];
       } else if (x[a] < lo || x[a] > hi) {
         x[a] = x[a] < lo ? 2.0 * lo - x[a] : 2.0 * hi - x[a];
         if (d.noslip) {
@@ -721,7 +759,50 @@ __global__ __launch_bounds__(BS) void k_integrate(Dev d, int velver, int rigid_a
 }
 
 void launch_integrate(const Dev& d, int velver, int rigid_active, hipStream_t st) {
-  k_integrate<<<nblocks(d.n), BS, 0, st>>>(d, velver, rigid_active);
+  k_integrate<<<d.nblk, BS, 0, st>>>(d, velver, rigid_active);
+}
+
+// ---------------------------------------------------------------------------
+// Per-box pressure tensor component P_zx after a step: kinetic part
+// m v'_z v'_x with v' the velocity less the shear profile, plus the virial of
+// the last force evaluation (pair kernel plane 12 for fluid and inner walls,
+// wzx_r for rigid particles), over the box volume.  One block per box sums
+// its fixed particle range in a fixed order, so the result is repeatable.
+
+__global__ __launch_bounds__(BS) void k_box_stress(Dev d, int rigid_active, int accumulate) {
+  __shared__ double sh[BS];
+  const int b = blockIdx.x;
+  const BoxD& B = d.boxes[b];
+  const size_t np = (size_t)d.npad;
+  const double zmid = B.org[2] + 0.5 * B.L[2];
+  double acc = 0.0;
+  for (int i = B.first + (int)threadIdx.x; i < B.first + B.count; i += BS) {
+    const uint8_t t = d.type[i];
+    if (t == T_OUTER) continue;
+    const D4 p = d.pos[i], v = d.vel[i];
+    const double vx = v.x - B.shear * (p.z - zmid);
+    double q = v.w * v.z * vx;
+    if (t == T_FLUID || t == T_INNER)
+      q += (double)d.fout[12 * np + i];
+    else if (t == T_RIGID && rigid_active)
+      q += d.wzx_r[d.gid2slot[d.gid[i]]];
+    acc += q;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = BS / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double pzx = sh[0] / B.vol;
+    d.st_inst[b] = pzx;
+    if (accumulate) d.st_sum[b] += pzx;
+  }
+}
+
+void launch_box_stress(const Dev& d, int accumulate, hipStream_t st) {
+  k_box_stress<<<d.nbox, BS, 0, st>>>(d, d.have_rxn, accumulate);
 }
 
 // ---------------------------------------------------------------------------
@@ -792,7 +873,16 @@ __global__ __launch_bounds__(BS) void k_read_field(Dev d, int field, int rigid_a
     case SDPDEM_F_TOTAL:
     case SDPDEM_N_TOTAL: {
       double F[3], N[3];
-      total_force(d, i, t, d.pos[i], rigid_active, F, N);
+      // the box whose fixed sorted range holds i
+      int lo = 0, hi = d.nbox - 1;
+      while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (d.boxes[mid].first <= i)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      total_force(d, d.boxes[lo], i, t, d.pos[i], rigid_active, F, N);
       for (int a = 0; a < 3; ++a) v[a] = field == SDPDEM_F_TOTAL ? F[a] : N[a];
     } break;
     default:

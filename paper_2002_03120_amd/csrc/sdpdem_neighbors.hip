@@ -14,8 +14,11 @@ namespace sdpdem {
 // contiguous slice of the sorted arrays unless the row wraps.
 
 __global__ __launch_bounds__(BS) void k_build_density(Dev d) {
-  int i = xcd_tid();
-  if (i >= d.n) return;
+  int i;
+  const int b = blk_box(d, i);
+  if (b < 0) return;
+  const BoxD& B = d.boxes[b];
+  if (i >= B.first + B.count) return;
   uint8_t ti = d.type[i];
   if (ti == T_OUTER) {
     d.nbr_cnt[i] = 0;
@@ -24,55 +27,34 @@ __global__ __launch_bounds__(BS) void k_build_density(Dev d) {
     return;
   }
   const D4 pi = d.pos[i];
+  const Geo G = geo_of(B);
+  const Grid gr = B.g;
+  const int coff = B.cell_off;
   int oob = 0;
-  const int cx = cell_coord(pi.x, d.g, 0, &oob);
-  const int cy = cell_coord(pi.y, d.g, 1, &oob);
-  const int cz = cell_coord(pi.z, d.g, 2, &oob);
+  const int cc[3] = {cell_coord(pi.x, gr, 0, &oob), cell_coord(pi.y, gr, 1, &oob),
+                     cell_coord(pi.z, gr, 2, &oob)};
   const double h2 = d.h2, inv_h = d.inv_h;
   double acc = d.W0;
   int cnt = 0;
   const size_t npad = (size_t)d.npad;
   int* const nb = d.nbr + i;
-  for (int dz = -1; dz <= 1; ++dz) {
-    int z = cz + dz;
-    if (!wrap_axis(z, d.g.nc[2], d.g.per[2])) continue;
-    for (int dy = -1; dy <= 1; ++dy) {
-      int y = cy + dy;
-      if (!wrap_axis(y, d.g.nc[1], d.g.per[1])) continue;
-      int xs[3];
-      int nx = 0;
-      for (int dxx = -1; dxx <= 1; ++dxx) {
-        int x = cx + dxx;
-        if (wrap_axis(x, d.g.nc[0], d.g.per[0])) xs[nx++] = x;
-      }
-      int k = 0;
-      while (k < nx) {  // maximal runs of consecutive cells
-        int x0 = xs[k], x1 = xs[k];
-        while (k + 1 < nx && xs[k + 1] == x1 + 1) {
-          ++k;
-          x1 = xs[k];
-        }
-        ++k;
-        const int jb = d.cstart[cell_index(d.g, x0, y, z)];
-        const int je = d.cstart[cell_index(d.g, x1, y, z) + 1];
-        for (int j = jb; j < je; ++j) {
-          const D4 pj = d.pos[j];
-          const double ex = min_img(pi.x - pj.x, d.per[0], d.L[0], d.halfL[0]);
-          const double ey = min_img(pi.y - pj.y, d.per[1], d.L[1], d.halfL[1]);
-          const double ez = min_img(pi.z - pj.z, d.per[2], d.L[2], d.halfL[2]);
-          const double r2 = r2_exact(ex, ey, ez);
-          if (r2 < h2 && j != i) {
-            const double q = sqrt_nr(r2) * inv_h;
-            const double om = 1.0 - q;
-            const double w = d.w_norm * (1.0 + 3.0 * q) * om * om * om;
-            if (cnt < d.maxn) nb[(size_t)cnt * npad] = j;
-            ++cnt;
-            acc += w;
-          }
-        }
+  for_stencil(G, gr, coff, pi.x, cc, 1, [&](int k0, int k1) {
+    const int jb = d.cstart[k0];
+    const int je = d.cstart[k1];
+    for (int j = jb; j < je; ++j) {
+      const D4 pj = d.pos[j];
+      double ex = pi.x - pj.x, ey = pi.y - pj.y, ez = pi.z - pj.z;
+      min_img_box(G, ex, ey, ez);
+      const double r2 = r2_exact(ex, ey, ez);
+      if (r2 < h2 && j != i) {
+        const double q = sqrt_nr(r2) * inv_h;
+        const double om = 1.0 - q;
+        if (cnt < d.maxn) nb[(size_t)cnt * npad] = j;
+        ++cnt;
+        acc += d.w_norm * (1.0 + 3.0 * q) * om * om * om;
       }
     }
-  }
+  });
   if (cnt > d.maxn) {
     atomicOr(d.status, ST_NBR_OVERFLOW);
     cnt = d.maxn;
@@ -86,7 +68,7 @@ __global__ __launch_bounds__(BS) void k_build_density(Dev d) {
 }
 
 void launch_build_density(const Dev& d, hipStream_t st) {
-  k_build_density<<<nblocks(d.n), BS, 0, st>>>(d);
+  k_build_density<<<d.nblk, BS, 0, st>>>(d);
 }
 
 // ---------------------------------------------------------------------------
@@ -94,11 +76,15 @@ void launch_build_density(const Dev& d, hipStream_t st) {
 // positions) and the pair records of the force pass.
 
 __global__ __launch_bounds__(BS) void k_smooth(Dev d) {
-  int i = xcd_tid();
-  if (i >= d.n) return;
+  int i;
+  const int b = blk_box(d, i);
+  if (b < 0) return;
+  const BoxD& B = d.boxes[b];
+  if (i >= B.first + B.count) return;
   const uint8_t ti = d.type[i];
   const double pi = d.p[i];
   const D4 x = d.pos[i];
+  const Geo G = geo_of(B);
   double ps = pi;
   if (d.smooth && ti != T_OUTER) {
     double num = pi * d.W0, den = d.W0;
@@ -109,9 +95,8 @@ __global__ __launch_bounds__(BS) void k_smooth(Dev d) {
     for (int k = 0; k < cnt; ++k) {
       const int j = nb[(size_t)k * npad];
       const D4 xj = d.pos[j];
-      const double ex = min_img(x.x - xj.x, d.per[0], d.L[0], d.halfL[0]);
-      const double ey = min_img(x.y - xj.y, d.per[1], d.L[1], d.halfL[1]);
-      const double ez = min_img(x.z - xj.z, d.per[2], d.L[2], d.halfL[2]);
+      double ex = x.x - xj.x, ey = x.y - xj.y, ez = x.z - xj.z;
+      min_img_box(G, ex, ey, ez);
       const double q = sqrt_nr(r2_exact(ex, ey, ez)) * inv_h;
       const double om = fmax(1.0 - q, 0.0);
       const double w = d.w_norm * (1.0 + 3.0 * q) * om * om * om;
@@ -136,12 +121,12 @@ __global__ __launch_bounds__(BS) void k_smooth(Dev d) {
   r.wz = (float)w.z;
   r.invd = (float)(1.0 / di);
   r.gid = d.gid[i];
-  r.pad = 0;
+  r.type = ti;
   d.prec[i] = r;
 }
 
 void launch_smooth(const Dev& d, hipStream_t st) {
-  k_smooth<<<nblocks(d.n), BS, 0, st>>>(d);
+  k_smooth<<<d.nblk, BS, 0, st>>>(d);
 }
 
 // ---------------------------------------------------------------------------
@@ -149,18 +134,28 @@ void launch_smooth(const Dev& d, hipStream_t st) {
 // inner-wall particles: FP32 math on FP64-differenced separations, FP32
 // per-particle sums; outputs F^SDPD, its torque and the F^C + F^D sum.
 
-template <bool NOISE>
+template <bool NOISE, bool STRESS>
 __global__ __launch_bounds__(BS) void k_fluid_forces(Dev d, uint32_t step) {
-  const int i = xcd_tid();
-  if (i >= d.n) return;
+  int i;
+  const int b = blk_box(d, i);
+  if (b < 0) return;
+  const BoxD& B = d.boxes[b];
+  if (i >= B.first + B.count) return;
   const uint8_t ti = d.type[i];
   float F0 = 0.f, F1 = 0.f, F2 = 0.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, N0 = 0.f, N1 = 0.f, N2 = 0.f;
+  float Wzx = 0.f;
   if (ti == T_FLUID || ti == T_INNER) {
     const PR ri = load_pr(d.prec, i);
     const uint32_t gi = (uint32_t)ri.gid;
     const int cnt = d.nbr_cnt[i];
     const int* nb = d.nbr + i;
     const size_t npad = (size_t)d.npad;
+    const Geo G = geo_of(B);
+    const bool le = G.le;
+    const float jump = (float)G.le_jump;
+    const bool noise = NOISE && B.noise;
+    const float kT = B.kTf;
+    const uint32_t key0 = B.key0, key1 = B.key1;
     // software-pipelined: the record of slot k+1 and the index of slot k+2
     // are in flight while slot k is evaluated
     int jn = cnt > 0 ? nb[0] : i;
@@ -170,9 +165,8 @@ __global__ __launch_bounds__(BS) void k_fluid_forces(Dev d, uint32_t step) {
       const PR rj = rn;
       rn = load_pr(d.prec, jn);
       jn = k + 2 < cnt ? nb[(size_t)(k + 2) * npad] : i;
-      const double dx_ = min_img(ri.x - rj.x, d.per[0], d.L[0], d.halfL[0]);
-      const double dy_ = min_img(ri.y - rj.y, d.per[1], d.L[1], d.halfL[1]);
-      const double dz_ = min_img(ri.z - rj.z, d.per[2], d.L[2], d.halfL[2]);
+      double dx_ = ri.x - rj.x, dy_ = ri.y - rj.y, dz_ = ri.z - rj.z;
+      const int kz = min_img_box(G, dx_, dy_, dz_);
       const double r2d = dx_ * dx_ + dy_ * dy_ + dz_ * dz_;
       const float rx = (float)dx_, ry = (float)dy_, rz = (float)dz_;
       const float inv_r = __builtin_amdgcn_rsqf((float)r2d);
@@ -191,8 +185,11 @@ __global__ __launch_bounds__(BS) void k_fluid_forces(Dev d, uint32_t step) {
       // F / (d_i d_j): the two inverse densities multiply symmetrically so
       // that F_ji = -F_ij holds bit for bit
       const float fdd = Fk * (ri.invd * rj.invd);
-      // dissipative force, Eq. FijD: -ga v_ij - (ga + 2 gb)/3 (e.v_ij) e
-      const float vx = ri.vx - rj.vx, vy = ri.vy - rj.vy, vz = ri.vz - rj.vz;
+      // dissipative force, Eq. FijD: -ga v_ij - (ga + 2 gb)/3 (e.v_ij) e; a
+      // partner seen through a sheared z face moves with its image velocity
+      float vx = ri.vx - rj.vx;
+      if (le) vx = vx - (float)kz * jump;
+      const float vy = ri.vy - rj.vy, vz = ri.vz - rj.vz;
       const float ev = ex * vx + ey * vy + ez * vz;
       const float cde = d.kBf * fdd * ev;
       const float cdv = d.kAf * fdd;
@@ -213,12 +210,12 @@ __global__ __launch_bounds__(BS) void k_fluid_forces(Dev d, uint32_t step) {
       tx += rrx;
       ty += rry;
       tz += rrz;
-      if (NOISE) {
+      if (noise) {
         // thermal force, Eq. FijT with dW^S = sym(dW) - tr(dW)/3
         float z[9];
-        pair_normals(gi, (uint32_t)rj.gid, step, d.key0, d.key1, z);
-        const float sa = 2.0f * sqrtf(d.kTf * d.CAf * fdd);
-        const float sb = 2.0f * sqrtf(d.kTf * d.CBf * fdd);
+        pair_normals(gi, (uint32_t)rj.gid, step, key0, key1, z);
+        const float sa = 2.0f * sqrtf(kT * d.CAf * fdd);
+        const float sb = 2.0f * sqrtf(kT * d.CBf * fdd);
         const float tr3 = (z[0] + z[4] + z[8]) * (1.0f / 3.0f);
         const float s01 = 0.5f * (z[1] + z[3]), s02 = 0.5f * (z[2] + z[6]),
                     s12 = 0.5f * (z[5] + z[7]);
@@ -241,6 +238,12 @@ __global__ __launch_bounds__(BS) void k_fluid_forces(Dev d, uint32_t step) {
       N0 += ey * tz - ez * ty;
       N1 += ez * tx - ex * tz;
       N2 += ex * ty - ey * tx;
+      if (STRESS) {
+        // virial r_z F_x: half of a pair that j evaluates too, all of a
+        // pair with a rigid or outer-wall partner (it does not)
+        const float c = (rj.type == T_FLUID || rj.type == T_INNER) ? 0.5f : 1.0f;
+        Wzx += c * rz * fx;
+      }
     }
     N0 *= -d.leverf;
     N1 *= -d.leverf;
@@ -257,13 +260,21 @@ __global__ __launch_bounds__(BS) void k_fluid_forces(Dev d, uint32_t step) {
   o[6 * np + i] = C0;
   o[7 * np + i] = C1;
   o[8 * np + i] = C2;
+  if (STRESS) o[12 * np + i] = Wzx;
 }
 
 void launch_fluid_forces(const Dev& d, uint32_t step, bool noise, hipStream_t st) {
-  if (noise)
-    k_fluid_forces<true><<<nblocks(d.n), BS, 0, st>>>(d, step);
-  else
-    k_fluid_forces<false><<<nblocks(d.n), BS, 0, st>>>(d, step);
+  if (noise) {
+    if (d.stress)
+      k_fluid_forces<true, true><<<d.nblk, BS, 0, st>>>(d, step);
+    else
+      k_fluid_forces<true, false><<<d.nblk, BS, 0, st>>>(d, step);
+  } else {
+    if (d.stress)
+      k_fluid_forces<false, true><<<d.nblk, BS, 0, st>>>(d, step);
+    else
+      k_fluid_forces<false, false><<<d.nblk, BS, 0, st>>>(d, step);
+  }
 }
 
 // neighbour columns k0..k0+kn-1 as ids (-1 past a row's end), for export

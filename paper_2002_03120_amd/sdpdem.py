@@ -62,6 +62,7 @@ class Params(ctypes.Structure):
         ("itr_start", ctypes.c_int64), ("itr_actv_rigid", ctypes.c_int64),
         ("seed", ctypes.c_uint64),
         ("max_neighbors", ctypes.c_int32), ("max_contacts", ctypes.c_int32),
+        ("shear_rate", ctypes.c_double),
     ]
 
 
@@ -71,6 +72,15 @@ class Particles(ctypes.Structure):
         ("n", ctypes.c_int64), ("id", ctypes.c_void_p), ("type", ctypes.c_void_p),
         ("pos", ctypes.c_void_p), ("vel", ctypes.c_void_p), ("angvel", ctypes.c_void_p),
         ("mass", ctypes.c_void_p), ("inertia", ctypes.c_void_p), ("radius", ctypes.c_void_p),
+    ]
+
+
+class Box(ctypes.Structure):
+    """sdpdem_box: one box of a batch."""
+    _fields_ = [
+        ("org", ctypes.c_double * 3), ("L", ctypes.c_double * 3),
+        ("periodic", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32),
+        ("shear_rate", ctypes.c_double), ("kBT", ctypes.c_double), ("seed", ctypes.c_uint64),
     ]
 
 
@@ -90,6 +100,14 @@ def lib():
                                              ctypes.POINTER(sz)]
         L.sdpdem_create.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Particles), vp, sz,
                                     vp, ctypes.POINTER(vp)]
+        L.sdpdem_batch_workspace_bytes.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Box),
+                                                   ctypes.c_int32, ctypes.POINTER(Particles),
+                                                   vp, ctypes.POINTER(sz)]
+        L.sdpdem_create_batch.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Box),
+                                          ctypes.c_int32, ctypes.POINTER(Particles), vp, vp, sz,
+                                          vp, ctypes.POINTER(vp)]
+        L.sdpdem_set_stress.argtypes = [vp, ctypes.c_int, vp]
+        L.sdpdem_box_stress.argtypes = [vp, vp, vp, ctypes.POINTER(i64), vp]
         L.sdpdem_step.argtypes = [vp, i64, vp]
         L.sdpdem_compute_forces.argtypes = [vp, vp]
         L.sdpdem_read_field.argtypes = [vp, ctypes.c_int, vp, sz, vp]
@@ -192,6 +210,63 @@ def sdpdem_create(params: dict, parts: dict, workspace, stream=None) -> ctypes.c
     return h
 
 
+def make_boxes(boxes):
+    """Array of sdpdem_box from a list of dicts (org, L, periodic, shear_rate,
+    kBT, seed)."""
+    arr = (Box * len(boxes))()
+    for b, d in zip(arr, boxes):
+        for a in range(3):
+            b.org[a] = float(d["org"][a])
+            b.L[a] = float(d["L"][a])
+            b.periodic[a] = int(d["periodic"][a])
+        b.reserved = 0
+        b.shear_rate = float(d.get("shear_rate", 0.0))
+        b.kBT = float(d.get("kBT", 0.0))
+        b.seed = int(d.get("seed", 0))
+    return arr
+
+
+def sdpdem_batch_workspace_bytes(params: dict, boxes, parts: dict, box_of) -> int:
+    p = make_params(params)
+    bx = make_boxes(boxes)
+    q, _keep = make_particles(parts)
+    bo = np.ascontiguousarray(box_of, dtype=np.int32)
+    out = ctypes.c_size_t()
+    _check(lib().sdpdem_batch_workspace_bytes(ctypes.byref(p), bx, len(boxes), ctypes.byref(q),
+                                              bo.ctypes.data, ctypes.byref(out)),
+           "sdpdem_batch_workspace_bytes")
+    return int(out.value)
+
+
+def sdpdem_create_batch(params: dict, boxes, parts: dict, box_of, workspace,
+                        stream=None) -> ctypes.c_void_p:
+    p = make_params(params)
+    bx = make_boxes(boxes)
+    q, _keep = make_particles(parts)
+    bo = np.ascontiguousarray(box_of, dtype=np.int32)
+    h = ctypes.c_void_p()
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(lib().sdpdem_create_batch(ctypes.byref(p), bx, len(boxes), ctypes.byref(q),
+                                     bo.ctypes.data, ctypes.c_void_p(workspace.data_ptr()),
+                                     nbytes, _stream(stream), ctypes.byref(h)),
+           "sdpdem_create_batch")
+    return h
+
+
+def sdpdem_set_stress(h, on: bool, stream=None):
+    _check(lib().sdpdem_set_stress(h, 1 if on else 0, _stream(stream)), "sdpdem_set_stress")
+
+
+def sdpdem_box_stress(h, nbox: int, stream=None):
+    """(last P_zx sample per box, running sums per box, number of samples)"""
+    inst = np.zeros(nbox)
+    tot = np.zeros(nbox)
+    m = ctypes.c_int64()
+    _check(lib().sdpdem_box_stress(h, inst.ctypes.data, tot.ctypes.data, ctypes.byref(m),
+                                   _stream(stream)), "sdpdem_box_stress")
+    return inst, tot, int(m.value)
+
+
 def sdpdem_step(h, nsteps: int, stream=None) -> int:
     return lib().sdpdem_step(h, int(nsteps), _stream(stream))
 
@@ -276,14 +351,22 @@ def sdpdem_destroy(h):
 class System:
     """A system plus the device workspace it lives in (torch uint8 tensor)."""
 
-    def __init__(self, params: dict, parts: dict, device="cuda", stream=None):
+    def __init__(self, params: dict, parts: dict, device="cuda", stream=None, boxes=None,
+                 box_of=None):
+        """boxes/box_of: a batch of independent boxes (sdpdem_create_batch)."""
         import torch
         self.n = int(parts["id"].shape[0])
         self.params = dict(params)
         self.stream = stream
-        nbytes = sdpdem_workspace_bytes(params, parts)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
-        self.h = sdpdem_create(params, parts, self.workspace, stream)
+        self.nbox = len(boxes) if boxes is not None else 1
+        if boxes is None:
+            nbytes = sdpdem_workspace_bytes(params, parts)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+            self.h = sdpdem_create(params, parts, self.workspace, stream)
+        else:
+            nbytes = sdpdem_batch_workspace_bytes(params, boxes, parts, box_of)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+            self.h = sdpdem_create_batch(params, boxes, parts, box_of, self.workspace, stream)
 
     def close(self):
         if getattr(self, "h", None):
@@ -332,6 +415,12 @@ class System:
 
     def set_profiling(self, kernel):
         sdpdem_set_profiling(self.h, kernel)
+
+    def set_stress(self, on=True):
+        sdpdem_set_stress(self.h, on, self.stream)
+
+    def box_stress(self):
+        return sdpdem_box_stress(self.h, self.nbox, self.stream)
 
     def kernel_time(self):
         return sdpdem_kernel_time(self.h)

@@ -44,6 +44,7 @@ def base_params(**over) -> dict:
         enable_kernel_norm=1, enable_pres_smooth=1, enable_neg_p_clamp=0,
         enable_lub=1, eps_min=0.2, lub_gap_min=0.01,
         itr_start=0, itr_actv_rigid=0, seed=0, max_neighbors=64, max_contacts=16,
+        shear_rate=0.0,
     )
     p.update(over)
     return p
@@ -219,6 +220,95 @@ def dam_break(tank=(256, 64, 192), column=(128, 64, 128), n_rigid=20000, d=3.0,
         rig = np.zeros((0, 3))
     wp, wt = _walls(tank, (0, 0, 0), layers, dx)
     return _assemble(p, fluid, rig, d, ratio, wp, wt, steps, "dam_break")
+
+
+def shear_cell(n_side=16, phi=0.2, d=4.0, kBT=1e-3, shear_rate=1e-2, ratio=1.0, dt=5e-3,
+               seed=0, steps=5000, **over):
+    """A periodic Lees-Edwards shear cell (the batched viscometer's unit):
+    an n_side^3 fluid lattice with DEM spheres of diameter d on a jittered
+    cubic sub-lattice of spacing (V_s/phi)^(1/3) (dense enough for phi up to
+    0.4, where random sequential addition would jam), each replacing its
+    nearest fluid site.  Velocities follow the linear shear profile
+    v_x = shear_rate (z - L/2) plus Maxwellian noise of variance kBT/m; spins
+    are shear_rate/2 about y (half the vorticity)."""
+    dx = 1.0
+    n = int(n_side)
+    L = float(n)
+    rng = np.random.default_rng(seed)
+    p = base_params(org=[0.0, 0.0, 0.0], L=[L, L, L], periodic=[1, 1, 1], kBT=kBT, dt=dt,
+                    g=[0.0, 0.0, 0.0], shear_rate=shear_rate, seed=seed)
+    p.update(over)
+    fluid = _lattice(n, n, n, dx)
+    rig = np.zeros((0, 3))
+    if phi > 0.0 and d > 0.0:
+        vs = math.pi * d ** 3 / 6.0
+        a = (vs / phi) ** (1.0 / 3.0)
+        m = int(math.floor(L / a))
+        if m >= 1:
+            a = L / m
+            g = (np.stack(np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij"),
+                          axis=-1).reshape(-1, 3) + 0.5) * a
+            jit = 0.45 * max(a - d, 0.0)
+            rig = g + rng.uniform(-jit, jit, size=g.shape)
+            k = np.floor(rig / dx).astype(np.int64) % n
+            sites = (k[:, 2] * n + k[:, 1]) * n + k[:, 0]
+            if np.unique(sites).size != sites.size:
+                raise RuntimeError("two spheres share a lattice site")
+            keep = np.ones(fluid.shape[0], bool)
+            keep[sites] = False
+            fluid = fluid[keep]
+    params, parts, info = _assemble(p, fluid, rig, d, ratio, np.zeros((0, 3)),
+                                    np.zeros(0, np.uint8), steps, "shear_cell")
+    z = parts["pos"][:, 2]
+    m_ = parts["mass"]
+    parts["vel"][:, 0] = shear_rate * (z - 0.5 * L)
+    if kBT > 0.0:
+        parts["vel"] += rng.normal(size=(z.size, 3)) * np.sqrt(kBT / m_)[:, None]
+    parts["angvel"][:, 1] = 0.5 * shear_rate
+    info.update(phi=float(rig.shape[0] * math.pi * d ** 3 / 6.0 / L ** 3), d=float(d),
+                kBT=float(kBT), shear_rate=float(shear_rate), L=L)
+    return params, parts, info
+
+
+def viscometer_batch(n_cells=256, seed=0, side=(16, 40), phi=(0.0, 0.4), d=(2.0, 6.0),
+                     kBT=(5e-4, 5e-3), shear=(1e-3, 1e-1), dt=5e-3, steps=5000, **over):
+    """Independent Lees-Edwards shear cells of uneven size for the batched
+    viscometer: side ~ U{side}, volume fraction ~ U[phi], sphere diameter
+    ~ U[d], kT ~ U[kBT], shear rate log-uniform in [shear].  Returns
+    (params shared by all cells, list of per-cell (params, particles, info))."""
+    rng = np.random.default_rng(seed)
+    cells = []
+    for c in range(n_cells):
+        L = int(rng.integers(side[0], side[1] + 1))
+        ph = float(rng.uniform(*phi))
+        dd = float(rng.uniform(*d))
+        kt = float(rng.uniform(*kBT))
+        gd = float(math.exp(rng.uniform(math.log(shear[0]), math.log(shear[1]))))
+        cells.append(shear_cell(L, ph, dd, kt, gd, dt=dt, seed=seed * 1000003 + c, steps=steps,
+                                **over))
+    shared = dict(cells[0][0]) if cells else base_params(dt=dt)
+    return shared, cells
+
+
+def stack_cells(cells):
+    """Concatenate shear cells into one batch: particles with ids offset per
+    cell, the box list and the per-particle box index."""
+    ids, types, pos, vel, ang, mass, iner, rad, box_of, boxes = ([] for _ in range(10))
+    off = 0
+    for b, (p, parts, info) in enumerate(cells):
+        n = parts["id"].shape[0]
+        ids.append(parts["id"] + off)
+        for lst, k in ((types, "type"), (pos, "pos"), (vel, "vel"), (ang, "angvel"),
+                       (mass, "mass"), (iner, "inertia"), (rad, "radius")):
+            lst.append(parts[k])
+        box_of.append(np.full(n, b, np.int32))
+        boxes.append(dict(org=p["org"], L=p["L"], periodic=p["periodic"],
+                          shear_rate=p["shear_rate"], kBT=p["kBT"], seed=p["seed"]))
+        off += n
+    parts = dict(id=np.concatenate(ids), type=np.concatenate(types), pos=np.concatenate(pos),
+                 vel=np.concatenate(vel), angvel=np.concatenate(ang), mass=np.concatenate(mass),
+                 inertia=np.concatenate(iner), radius=np.concatenate(rad))
+    return parts, boxes, np.concatenate(box_of)
 
 
 def periodic_scale(n_side=(256, 256, 128), **over):
