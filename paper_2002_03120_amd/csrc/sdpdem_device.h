@@ -145,80 +145,105 @@ __device__ __forceinline__ double sqrt_nr(double x) {
 __device__ __forceinline__ PR load_pr(const PR* base, int j) { return base[j]; }
 
 // The cells within k of cell cc (local coordinates, particle x coordinate
-// px) of box B in grid G, as runs of consecutive x cells of one row:
-// fn(first_key, end_key) with global keys (off = the box's cell offset).
-// Rows seen through a Lees-Edwards z face are centred on the shifted x
-// coordinate and widened by one cell on each side; when the stencil wraps
-// onto itself along z under shear, every x cell is taken.
+// px) of a box in grid G, row by row: row r = (iz, iy) of the (2k+1)^2
+// rows (all rows of an axis when the stencil would wrap onto itself) holds
+// at most two runs of consecutive x cells, [a0, a1) and [b0, b1) in global
+// keys (off = the box's cell offset); empty runs have a0 == a1.  Rows seen
+// through a Lees-Edwards z face are centred on the shifted x coordinate and
+// widened by one cell on each side; when the stencil wraps onto itself
+// along z under shear, every x cell is taken.
+struct StencilShape {
+  int zlo, zn, ylo, yn;
+};
+
+__device__ __forceinline__ StencilShape stencil_shape(const Grid& G, const int cc[3], int k) {
+  StencilShape sh;
+  const bool zall = G.per[2] && 2 * k + 1 > G.nc[2];
+  const bool yall = G.per[1] && 2 * k + 1 > G.nc[1];
+  sh.zlo = zall ? 0 : cc[2] - k;
+  sh.zn = zall ? G.nc[2] : 2 * k + 1;
+  sh.ylo = yall ? 0 : cc[1] - k;
+  sh.yn = yall ? G.nc[1] : 2 * k + 1;
+  return sh;
+}
+
+__device__ __forceinline__ void stencil_row(const Geo& B, const Grid& G, int off, double px,
+                                            const int cc[3], int k, const StencilShape& sh,
+                                            int r, int& a0, int& a1, int& b0, int& b1) {
+  a0 = a1 = b0 = b1 = 0;
+  const int nx = G.nc[0], ny = G.nc[1], nz = G.nc[2];
+  int z = sh.zlo + r / sh.yn, y = sh.ylo + r % sh.yn, wz = 0;
+  if (z < 0) {
+    if (!G.per[2]) return;
+    z += nz;
+    wz = -1;
+  } else if (z >= nz) {
+    if (!G.per[2]) return;
+    z -= nz;
+    wz = 1;
+  }
+  if (y < 0) {
+    if (!G.per[1]) return;
+    y += ny;
+  } else if (y >= ny) {
+    if (!G.per[1]) return;
+    y -= ny;
+  }
+  int x0 = cc[0] - k, xn = 2 * k + 1;
+  if (B.le && (sh.zn == nz && G.per[2] && 2 * k + 1 > nz)) {
+    x0 = 0;
+    xn = nx;
+  } else if (B.le && wz != 0) {
+    // candidates sit around x - k_z delta, k_z = wz
+    double xc = px - (double)wz * B.le_shift;
+    double f = floor((xc - G.lo[0]) * G.inv_cs[0]);
+    f = f - (double)nx * floor(f / (double)nx);
+    int c = (int)f;
+    if (c < 0) c = 0;
+    if (c >= nx) c = nx - 1;
+    x0 = c - k - 1;
+    xn = 2 * k + 3;
+  }
+  const int rowkey = off + (z * ny + y) * nx;
+  if (G.per[0] && xn >= nx) {
+    a0 = rowkey;
+    a1 = rowkey + nx;
+  } else if (!G.per[0]) {
+    int lo = max(x0, 0), hi = min(x0 + xn - 1, nx - 1);
+    if (lo <= hi) {
+      a0 = rowkey + lo;
+      a1 = rowkey + hi + 1;
+    }
+  } else {
+    int lo = x0, hi = x0 + xn - 1;  // at most one wrap
+    if (lo < 0) {
+      a0 = rowkey + lo + nx;
+      a1 = rowkey + nx;
+      b0 = rowkey;
+      b1 = rowkey + hi + 1;
+    } else if (hi >= nx) {
+      a0 = rowkey + lo;
+      a1 = rowkey + nx;
+      b0 = rowkey;
+      b1 = rowkey + hi - nx + 1;
+    } else {
+      a0 = rowkey + lo;
+      a1 = rowkey + hi + 1;
+    }
+  }
+}
+
+// the same cells as fn(first_key, end_key) over the runs, in row order
 template <class Fn>
 __device__ __forceinline__ void for_stencil(const Geo& B, const Grid& G, int off, double px,
                                             const int cc[3], int k, Fn&& fn) {
-  const int nx = G.nc[0], ny = G.nc[1], nz = G.nc[2];
-  const bool zall = G.per[2] && 2 * k + 1 > nz;
-  const bool yall = G.per[1] && 2 * k + 1 > ny;
-  const int zlo = zall ? 0 : cc[2] - k, zn = zall ? nz : 2 * k + 1;
-  const int ylo = yall ? 0 : cc[1] - k, yn = yall ? ny : 2 * k + 1;
-  for (int iz = 0; iz < zn; ++iz) {
-    int z = zlo + iz, wz = 0;
-    if (z < 0) {
-      if (!G.per[2]) continue;
-      z += nz;
-      wz = -1;
-    } else if (z >= nz) {
-      if (!G.per[2]) continue;
-      z -= nz;
-      wz = 1;
-    }
-    int x0 = cc[0] - k, xn = 2 * k + 1;
-    if (B.le && (zall || wz != 0)) {
-      if (zall) {
-        x0 = 0;
-        xn = nx;
-      } else {
-        // candidates sit around x - k_z delta, k_z = wz
-        double xc = px - (double)wz * B.le_shift;
-        double f = floor((xc - G.lo[0]) * G.inv_cs[0]);
-        f = f - (double)nx * floor(f / (double)nx);
-        int c = (int)f;
-        if (c < 0) c = 0;
-        if (c >= nx) c = nx - 1;
-        x0 = c - k - 1;
-        xn = 2 * k + 3;
-      }
-    }
-    bool xall = G.per[0] && xn >= nx;
-    if (xall) {
-      x0 = 0;
-      xn = nx;
-    }
-    for (int iy = 0; iy < yn; ++iy) {
-      int y = ylo + iy;
-      if (y < 0) {
-        if (!G.per[1]) continue;
-        y += ny;
-      } else if (y >= ny) {
-        if (!G.per[1]) continue;
-        y -= ny;
-      }
-      const int rowkey = off + (z * ny + y) * nx;
-      if (xall) {
-        fn(rowkey, rowkey + nx);
-      } else if (!G.per[0]) {
-        int a = max(x0, 0), b = min(x0 + xn - 1, nx - 1);
-        if (a <= b) fn(rowkey + a, rowkey + b + 1);
-      } else {
-        int a = x0, b = x0 + xn - 1;  // at most one wrap
-        if (a < 0) {
-          fn(rowkey + a + nx, rowkey + nx);
-          fn(rowkey, rowkey + b + 1);
-        } else if (b >= nx) {
-          fn(rowkey + a, rowkey + nx);
-          fn(rowkey, rowkey + b - nx + 1);
-        } else {
-          fn(rowkey + a, rowkey + b + 1);
-        }
-      }
-    }
+  const StencilShape sh = stencil_shape(G, cc, k);
+  const int nrows = sh.zn * sh.yn;
+  for (int r = 0; r < nrows; ++r) {
+    int a0, a1, b0, b1;
+    stencil_row(B, G, off, px, cc, k, sh, r, a0, a1, b0, b1);
+    if (a1 > a0) fn(a0, a1);
+    if (b1 > b0) fn(b0, b1);
   }
 }
 

@@ -320,23 +320,25 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
   const size_t np = (size_t)d.npad;
   double om = 0, v0 = 0, v1 = 0, v2 = 0, f0 = 0, f1 = 0, f2 = 0, l0 = 0, l1 = 0, l2 = 0;
   int nrig = 0;
-  // the search box as runs of consecutive cells; lane r takes run r of each
-  // batch of 64 runs (every lane enumerates the same runs)
-  int nruns = 0;
-  for_stencil(G, gr, coff, ps.x, cc, kr, [&](int, int) { ++nruns; });
-  for (int rb = 0; rb < nruns; rb += 64) {
-    int s0 = 0, len = 0;
-    {
-      int r = 0;
-      const int want = rb + lane;
-      for_stencil(G, gr, coff, ps.x, cc, kr, [&](int k0, int k1) {
-        if (r == want) {
-          s0 = d.cstart[k0];
-          len = d.cstart[k1] - s0;
-        }
-        ++r;
-      });
+  // the search box row by row: lane r takes row r of each batch of 64 rows
+  // (at most two runs of consecutive cells per row)
+  const StencilShape sh = stencil_shape(gr, cc, kr);
+  const int nrows = sh.zn * sh.yn;
+  for (int rb = 0; rb < nrows; rb += 64) {
+    int sa = 0, la = 0, sb = 0, lb = 0;
+    if (rb + lane < nrows) {
+      int a0, a1, b0, b1;
+      stencil_row(G, gr, coff, ps.x, cc, kr, sh, rb + lane, a0, a1, b0, b1);
+      if (a1 > a0) {
+        sa = d.cstart[a0];
+        la = d.cstart[a1] - sa;
+      }
+      if (b1 > b0) {
+        sb = d.cstart[b0];
+        lb = d.cstart[b1] - sb;
+      }
     }
+    const int len = la + lb;
     int inc = len;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -357,9 +359,12 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
         if (cand < 64 && v <= t) r = cand;
       }
       const int offr = __shfl(off, r, 64);
-      const int s0r = __shfl(s0, r, 64);
+      const int sar = __shfl(sa, r, 64);
+      const int lar = __shfl(la, r, 64);
+      const int sbr = __shfl(sb, r, 64);
       if (t >= total) continue;
-      const int j = s0r + (t - offr);
+      const int q = t - offr;
+      const int j = q < lar ? sar + q : sbr + (q - lar);
       if (j == si) continue;
       uint8_t tj = d.type[j];
       if (tj != T_FLUID && tj != T_RIGID) continue;
@@ -487,157 +492,228 @@ void launch_fpi_reaction(const Dev& d, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// (a8) DEM contacts (Sec. 2.2) and lubrication (Sec. 2.3), one thread per
-// rigid particle, FP64, over the cell-ordered rigid records.  The contact
-// table row of a particle holds partner ids and tangential displacements;
-// commit (second pass) writes the next table: the updated history of
-// every pair still in contact.
+// (a8) DEM contacts (Sec. 2.2) and lubrication (Sec. 2.3), FP64, over the
+// cell-ordered rigid records: one wavefront per rigid particle, one
+// candidate partner per lane.  The contact table row of a particle holds
+// partner ids and tangential displacements; commit (second pass) writes the
+// next table: the updated history of every pair still in contact, in
+// candidate order (ballot + prefix count, so the order is deterministic).
 
-static constexpr int DEM_BS = 64;
+struct DemAcc {
+  double F[3], FL[3], N[3], Wzx;
+};
 
-__global__ __launch_bounds__(DEM_BS) void k_dem(Dev d, int commit, int* nxt_cnt,
-                                               int* nxt_partner, double* nxt_dt) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= d.nr) return;
-  const BoxD& B = d.boxes[d.rbox[s]];
+// one candidate partner t of sphere s; returns 1 if it is a contact, with
+// its partner id and committed tangential displacement
+__device__ __forceinline__ int dem_pair_eval(const Dev& d, const Geo& G, int s, const D4& ps,
+                                             const D4& vs, const D4& ws, int t, int ocnt,
+                                             DemAcc& acc, int& gk, double nd[3]) {
+  const double Rs = ps.w, ms = vs.w;
+  const double Di = (1.0 - d.nu * d.nu) / (d.E * PI);
+  const int mc = d.maxc;
+  D4 pk = d.rpos_c[t];
+  double Rk = pk.w;
+  double e0 = ps.x - pk.x, e1 = ps.y - pk.y, e2 = ps.z - pk.z;
+  const int kz = min_img_box(G, e0, e1, e2);
+  double L2 = r2_exact(e0, e1, e2);
+  double reachk = Rs + Rk + d.h;
+  if (!(L2 < reachk * reachk)) return 0;
+  double L = sqrt(L2);
+  D4 vk = d.rvel_c[t];
+  vk.x += (double)kz * G.le_jump;  // image velocity (Lees-Edwards)
+  if (L < Rs + Rk) {
+    D4 wk = d.rom_c[t];
+    gk = d.rig_gid[d.ritems[t]];
+    double dt0 = 0, dt1 = 0, dt2 = 0;
+    for (int q = 0; q < ocnt; ++q) {
+      if (d.ct_partner[s * mc + q] == gk) {
+        dt0 = d.ct_dt[(size_t)(s * mc + q) * 3 + 0];
+        dt1 = d.ct_dt[(size_t)(s * mc + q) * 3 + 1];
+        dt2 = d.ct_dt[(size_t)(s * mc + q) * 3 + 2];
+        break;
+      }
+    }
+    double n0 = e0 / L, n1 = e1 / L, n2 = e2 / L;
+    double ov = L - (Rs + Rk);  // delta_n = ov * n
+    double u0 = vs.x - vk.x, u1 = vs.y - vk.y, u2 = vs.z - vk.z;
+    double un = u0 * n0 + u1 * n1 + u2 * n2;
+    double rw0 = Rs * ws.x + Rk * wk.x, rw1 = Rs * ws.y + Rk * wk.y, rw2 = Rs * ws.z + Rk * wk.z;
+    double t0 = u0 - un * n0 + (rw1 * n2 - rw2 * n1);
+    double t1 = u1 - un * n1 + (rw2 * n0 - rw0 * n2);
+    double t2 = u2 - un * n2 + (rw0 * n1 - rw1 * n0);
+    double kn = 4.0 / (3.0 * PI) * (1.0 / (Di + Di)) * sqrt(Rs * Rk / (Rs + Rk));
+    double kt = kn / (2.0 * (1.0 + d.nu));
+    double mk = vk.w;
+    double mm = 2.0 * ms * mk / (ms + mk);
+    double cn = d.damp * 2.0 * sqrt(mm * kn), ct = d.damp * 2.0 * sqrt(mm * kt);
+    double fn0 = -kn * ov * n0 - cn * un * n0;
+    double fn1 = -kn * ov * n1 - cn * un * n1;
+    double fn2 = -kn * ov * n2 - cn * un * n2;
+    double ft0 = -kt * dt0 - ct * t0, ft1 = -kt * dt1 - ct * t1, ft2 = -kt * dt2 - ct * t2;
+    double vta = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+    double dta = sqrt(dt0 * dt0 + dt1 * dt1 + dt2 * dt2);
+    double d0 = 0, d1 = 0, d2 = 0;
+    if (vta > 0.0) {
+      d0 = t0 / vta;
+      d1 = t1 / vta;
+      d2 = t2 / vta;
+    } else if (dta > 0.0) {
+      d0 = dt0 / dta;
+      d1 = dt1 / dta;
+      d2 = dt2 / dta;
+    }
+    double fna = sqrt(fn0 * fn0 + fn1 * fn1 + fn2 * fn2);
+    double fta = sqrt(ft0 * ft0 + ft1 * ft1 + ft2 * ft2);
+    double lim = d.mu * fna;
+    if (fta >= lim) {  // Coulomb slider, Eq. slideref
+      ft0 = -lim * d0;
+      ft1 = -lim * d1;
+      ft2 = -lim * d2;
+      double m = lim / kt;
+      nd[0] = m * d0;
+      nd[1] = m * d1;
+      nd[2] = m * d2;
+    } else {  // Eq. tandispn
+      nd[0] = dta * d0 + t0 * d.dt;
+      nd[1] = dta * d1 + t1 * d.dt;
+      nd[2] = dta * d2 + t2 * d.dt;
+    }
+    acc.F[0] += fn0 + ft0;
+    acc.F[1] += fn1 + ft1;
+    acc.F[2] += fn2 + ft2;
+    acc.Wzx += 0.5 * e2 * (fn0 + ft0);
+    // torque R_s (-n) x F_t
+    acc.N[0] += -Rs * (n1 * ft2 - n2 * ft1);
+    acc.N[1] += -Rs * (n2 * ft0 - n0 * ft2);
+    acc.N[2] += -Rs * (n0 * ft1 - n1 * ft0);
+    return 1;
+  }
+  if (d.lub) {
+    double gap = L - (Rs + Rk);
+    if (gap > 0.0 && gap < d.h) {
+      double db = Rs + Rk;
+      double gg = gap > d.lub_gap_min ? gap : d.lub_gap_min;
+      double c = 3.0 * PI * d.eta * db * db / (8.0 * gg);
+      acc.FL[0] += c * (vk.x - vs.x);
+      acc.FL[1] += c * (vk.y - vs.y);
+      acc.FL[2] += c * (vk.z - vs.z);
+      acc.Wzx += 0.5 * e2 * (c * (vk.x - vs.x));
+    }
+  }
+  return 0;
+}
+
+__global__ __launch_bounds__(BS) void k_dem(Dev d, int commit, int* nxt_cnt, int* nxt_partner,
+                                           double* nxt_dt) {
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (wave >= d.nr) return;
+  // spheres in rigid-grid cell order: neighbouring waves share cache lines
+  const int me = wave;
+  const int s = __builtin_amdgcn_readfirstlane(d.ritems[me]);
+  const BoxD& B = d.boxes[__builtin_amdgcn_readfirstlane(d.rbox[s])];
   const Geo G = geo_of(B);
   const Grid gr = B.rg;
   const int coff = B.rcell_off, reach = B.dem_reach;
-  const int me = d.rslot_pos[s];
   const D4 ps = d.rpos_c[me], vs = d.rvel_c[me], ws = d.rom_c[me];
-  const double Rs = ps.w, ms = vs.w;
-  const double Di = (1.0 - d.nu * d.nu) / (d.E * PI);
   int oob = 0;
   int cc[3] = {cell_coord(ps.x, gr, 0, &oob), cell_coord(ps.y, gr, 1, &oob),
                cell_coord(ps.z, gr, 2, &oob)};
   const int mc = d.maxc;
   const int ocnt = d.ct_cnt[s];
-  double F[3] = {0, 0, 0}, FL[3] = {0, 0, 0}, N[3] = {0, 0, 0};
-  double Wzx = 0.0;
+  DemAcc acc = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, 0.0};
   int ncnt = 0;
   int overflow = 0;
-  for_stencil(G, gr, coff, ps.x, cc, reach, [&](int cb, int ce) {
-    int tb = d.rstart[cb], te = d.rstart[ce];
-    for (int t = tb; t < te; ++t) {
-      if (t == me) continue;
-      D4 pk = d.rpos_c[t];
-      double Rk = pk.w;
-      double e0 = ps.x - pk.x, e1 = ps.y - pk.y, e2 = ps.z - pk.z;
-      const int kz = min_img_box(G, e0, e1, e2);
-      double L2 = r2_exact(e0, e1, e2);
-      double reachk = Rs + Rk + d.h;
-      if (!(L2 < reachk * reachk)) continue;
-      double L = sqrt(L2);
-      D4 vk = d.rvel_c[t];
-      vk.x += (double)kz * G.le_jump;  // image velocity (Lees-Edwards)
-      if (L < Rs + Rk) {
-        D4 wk = d.rom_c[t];
-        int gk = d.rig_gid[d.ritems[t]];
-        double dt0 = 0, dt1 = 0, dt2 = 0;
-        for (int q = 0; q < ocnt; ++q) {
-          if (d.ct_partner[s * mc + q] == gk) {
-            dt0 = d.ct_dt[(size_t)(s * mc + q) * 3 + 0];
-            dt1 = d.ct_dt[(size_t)(s * mc + q) * 3 + 1];
-            dt2 = d.ct_dt[(size_t)(s * mc + q) * 3 + 2];
-            break;
-          }
-        }
-        double n0 = e0 / L, n1 = e1 / L, n2 = e2 / L;
-        double ov = L - (Rs + Rk);  // delta_n = ov * n
-        double u0 = vs.x - vk.x, u1 = vs.y - vk.y, u2 = vs.z - vk.z;
-        double un = u0 * n0 + u1 * n1 + u2 * n2;
-        double rw0 = Rs * ws.x + Rk * wk.x, rw1 = Rs * ws.y + Rk * wk.y,
-               rw2 = Rs * ws.z + Rk * wk.z;
-        double t0 = u0 - un * n0 + (rw1 * n2 - rw2 * n1);
-        double t1 = u1 - un * n1 + (rw2 * n0 - rw0 * n2);
-        double t2 = u2 - un * n2 + (rw0 * n1 - rw1 * n0);
-        double kn = 4.0 / (3.0 * PI) * (1.0 / (Di + Di)) * sqrt(Rs * Rk / (Rs + Rk));
-        double kt = kn / (2.0 * (1.0 + d.nu));
-        double mk = vk.w;
-        double mm = 2.0 * ms * mk / (ms + mk);
-        double cn = d.damp * 2.0 * sqrt(mm * kn), ct = d.damp * 2.0 * sqrt(mm * kt);
-        double fn0 = -kn * ov * n0 - cn * un * n0;
-        double fn1 = -kn * ov * n1 - cn * un * n1;
-        double fn2 = -kn * ov * n2 - cn * un * n2;
-        double ft0 = -kt * dt0 - ct * t0, ft1 = -kt * dt1 - ct * t1, ft2 = -kt * dt2 - ct * t2;
-        double vta = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
-        double dta = sqrt(dt0 * dt0 + dt1 * dt1 + dt2 * dt2);
-        double d0 = 0, d1 = 0, d2 = 0;
-        if (vta > 0.0) {
-          d0 = t0 / vta;
-          d1 = t1 / vta;
-          d2 = t2 / vta;
-        } else if (dta > 0.0) {
-          d0 = dt0 / dta;
-          d1 = dt1 / dta;
-          d2 = dt2 / dta;
-        }
-        double fna = sqrt(fn0 * fn0 + fn1 * fn1 + fn2 * fn2);
-        double fta = sqrt(ft0 * ft0 + ft1 * ft1 + ft2 * ft2);
-        double lim = d.mu * fna;
-        double nd0, nd1, nd2;
-        if (fta >= lim) {  // Coulomb slider, Eq. slideref
-          ft0 = -lim * d0;
-          ft1 = -lim * d1;
-          ft2 = -lim * d2;
-          double m = lim / kt;
-          nd0 = m * d0;
-          nd1 = m * d1;
-          nd2 = m * d2;
-        } else {  // Eq. tandispn
-          nd0 = dta * d0 + t0 * d.dt;
-          nd1 = dta * d1 + t1 * d.dt;
-          nd2 = dta * d2 + t2 * d.dt;
-        }
-        F[0] += fn0 + ft0;
-        F[1] += fn1 + ft1;
-        F[2] += fn2 + ft2;
-        Wzx += 0.5 * e2 * (fn0 + ft0);
-        // torque R_s (-n) x F_t
-        N[0] += -Rs * (n1 * ft2 - n2 * ft1);
-        N[1] += -Rs * (n2 * ft0 - n0 * ft2);
-        N[2] += -Rs * (n0 * ft1 - n1 * ft0);
-        if (commit) {
-          if (ncnt < mc) {
-            nxt_partner[s * mc + ncnt] = gk;
-            nxt_dt[(size_t)(s * mc + ncnt) * 3 + 0] = nd0;
-            nxt_dt[(size_t)(s * mc + ncnt) * 3 + 1] = nd1;
-            nxt_dt[(size_t)(s * mc + ncnt) * 3 + 2] = nd2;
-            ++ncnt;
+  const StencilShape sh = stencil_shape(gr, cc, reach);
+  const int nrows = sh.zn * sh.yn;
+  for (int rb = 0; rb < nrows; rb += 64) {
+    int sa = 0, la = 0, sb = 0, lb = 0;
+    if (rb + lane < nrows) {
+      int a0, a1, b0, b1;
+      stencil_row(G, gr, coff, ps.x, cc, reach, sh, rb + lane, a0, a1, b0, b1);
+      if (a1 > a0) {
+        sa = d.rstart[a0];
+        la = d.rstart[a1] - sa;
+      }
+      if (b1 > b0) {
+        sb = d.rstart[b0];
+        lb = d.rstart[b1] - sb;
+      }
+    }
+    const int len = la + lb;
+    int inc = len;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      int t = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += t;
+    }
+    const int total = __shfl(inc, 63, 64);
+    const int off = inc - len;
+    for (int base = 0; base < total; base += 64) {
+      const int t = base + lane;
+      int r = 0;  // last row whose offset is <= t
+#pragma unroll
+      for (int stp = 32; stp > 0; stp >>= 1) {
+        int cand = r + stp;
+        int v = __shfl(off, cand & 63, 64);
+        if (cand < 64 && v <= t) r = cand;
+      }
+      const int offr = __shfl(off, r, 64);
+      const int sar = __shfl(sa, r, 64);
+      const int lar = __shfl(la, r, 64);
+      const int sbr = __shfl(sb, r, 64);
+      int contact = 0, gk = -1;
+      double nd[3] = {0, 0, 0};
+      if (t < total) {
+        const int q = t - offr;
+        const int tt = q < lar ? sar + q : sbr + (q - lar);
+        if (tt != me) contact = dem_pair_eval(d, G, s, ps, vs, ws, tt, ocnt, acc, gk, nd);
+      }
+      if (commit) {
+        // contacts of this round in candidate order
+        const uint64_t m = __ballot(contact);
+        const int before = __popcll(m & ((1ull << lane) - 1ull));
+        const int slot = ncnt + before;
+        if (contact) {
+          if (slot < mc) {
+            nxt_partner[s * mc + slot] = gk;
+            nxt_dt[(size_t)(s * mc + slot) * 3 + 0] = nd[0];
+            nxt_dt[(size_t)(s * mc + slot) * 3 + 1] = nd[1];
+            nxt_dt[(size_t)(s * mc + slot) * 3 + 2] = nd[2];
           } else {
             overflow = 1;
           }
         }
-      } else if (d.lub) {
-        double gap = L - (Rs + Rk);
-        if (gap > 0.0 && gap < d.h) {
-          double db = Rs + Rk;
-          double gg = gap > d.lub_gap_min ? gap : d.lub_gap_min;
-          double c = 3.0 * PI * d.eta * db * db / (8.0 * gg);
-          FL[0] += c * (vk.x - vs.x);
-          FL[1] += c * (vk.y - vs.y);
-          FL[2] += c * (vk.z - vs.z);
-          Wzx += 0.5 * e2 * (c * (vk.x - vs.x));
-        }
+        ncnt += __popcll(m);
       }
     }
-  });
-  for (int a = 0; a < 3; ++a) {
-    d.f_dem[3 * s + a] = F[a];
-    d.f_lub[3 * s + a] = FL[a];
-    d.n_dem[3 * s + a] = N[a];
   }
-  if (d.stress) d.wzx_r[s] += Wzx;
+  for (int a = 0; a < 3; ++a) {
+    acc.F[a] = wave_sum(acc.F[a]);
+    acc.FL[a] = wave_sum(acc.FL[a]);
+    acc.N[a] = wave_sum(acc.N[a]);
+  }
+  if (d.stress) acc.Wzx = wave_sum(acc.Wzx);
+  overflow = __any(overflow);
+  if (lane != 0) return;
+  for (int a = 0; a < 3; ++a) {
+    d.f_dem[3 * s + a] = acc.F[a];
+    d.f_lub[3 * s + a] = acc.FL[a];
+    d.n_dem[3 * s + a] = acc.N[a];
+  }
+  if (d.stress) d.wzx_r[s] += acc.Wzx;
   if (commit) {
-    nxt_cnt[s] = ncnt;
-    if (overflow) atomicOr(d.status, ST_CONTACT_OVERFLOW);
+    nxt_cnt[s] = ncnt < mc ? ncnt : mc;
+    if (overflow || ncnt > mc) atomicOr(d.status, ST_CONTACT_OVERFLOW);
   }
 }
 
 void launch_dem(const Dev& d, int commit, int* nxt_cnt, int* nxt_partner, double* nxt_dt,
                 hipStream_t st) {
   if (d.nr == 0) return;
-  k_dem<<<(d.nr + DEM_BS - 1) / DEM_BS, DEM_BS, 0, st>>>(d, commit, nxt_cnt, nxt_partner, nxt_dt);
+  const int waves_per_block = BS / 64;
+  k_dem<<<(d.nr + waves_per_block - 1) / waves_per_block, BS, 0, st>>>(d, commit, nxt_cnt,
+                                                                      nxt_partner, nxt_dt);
 }
 
 // ---------------------------------------------------------------------------
