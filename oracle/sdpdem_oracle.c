@@ -50,14 +50,14 @@
  *      (all components for no-slip, the normal one for slip).
  *  R15 The neighbour test is r^2 < h^2, strict, with
  *      r^2 = (dx*dx + dy*dy) + dz*dz in double precision.
- *  R16 Lees-Edwards shear (not in the paper; for the viscometer): flow
+ *  R19 Lees-Edwards shear (not in the paper; for the viscometer): flow
  *      along x, gradient along z.  The image of the box above sits at
  *      x + delta(t), delta = fmod(shear_rate L_z t, L_x) with t the time of
  *      the current positions, and moves with +shear_rate L_z in x.  The
  *      minimum image takes the z image first, then wraps x and y; pair
  *      terms see the image's velocity.  A particle leaving through a z face
  *      re-enters shifted by -/+ delta in x with v_x -/+ shear_rate L_z.
- *  R17 Pressure tensor of the box: P_ab = (sum_i m v'_a v'_b + W_ab) / V
+ *  R20 Pressure tensor of the box: P_ab = (sum_i m v'_a v'_b + W_ab) / V
  *      with v' = v - shear_rate (z - z_mid) e_x over fluid, rigid and
  *      inner-wall particles, and W the virial of the pair forces of the
  *      last evaluation: sum over pairs of r_ij,a F_ij,b, a pair computed
@@ -107,7 +107,7 @@ struct oracle_system {
   double* ct_dt;
   int64_t step;
   int64_t pos_step;  /* step index of the time of the current positions */
-  double le_shift;   /* Lees-Edwards offset at that time (R16) */
+  double le_shift;   /* Lees-Edwards offset at that time (R19) */
   double* vir;       /* per-particle virial W_ab of the last evaluation */
   /* background grid with linked lists (Sec. 3.2) */
   double glo[3], gcs[3];
@@ -334,7 +334,7 @@ void oracle_dem_pair(const oracle_params* P, const double dij[3],
 /* ------------------------------------------------------------------------ */
 /* geometry helpers                                                        */
 
-/* Lees-Edwards offset delta(t) of the image above (R16) */
+/* Lees-Edwards offset delta(t) of the image above (R19) */
 static double le_shift_at(const oracle_params* P, int64_t pstep) {
   if (P->shear_rate == 0.0) return 0.0;
   double t = (double)pstep * P->dt;
@@ -349,7 +349,7 @@ static void set_pos_step(oracle_system* s, int64_t pstep) {
   s->le_shift = le_shift_at(&s->P, pstep);
 }
 
-/* minimum-image separation x_i - x_j' (R14, R16); returns k_z, the number
+/* minimum-image separation x_i - x_j' (R14, R19); returns k_z, the number
  * of boxes (in z) by which the image j' is displaced, so that j' moves with
  * v_j + k_z shear_rate L_z e_x */
 static int min_image(const oracle_system* s, const double* xi,
@@ -369,7 +369,7 @@ static int min_image(const oracle_system* s, const double* xi,
   return 0;
 }
 
-/* velocity of the image of j displaced by kz boxes (R16) */
+/* velocity of the image of j displaced by kz boxes (R19) */
 static void image_vel(const oracle_system* s, const double* vj, int kz,
                       double out[3]) {
   out[0] = vj[0] + (double)kz * (s->P.shear_rate * s->P.L[2]);
@@ -633,7 +633,7 @@ static void compute_fluid(oracle_system* s) {
           Fcd[a] += cd[a];
           N[a] += tq[a];
         }
-        /* virial (R17): half of a pair that j also evaluates */
+        /* virial (R20): half of a pair that j also evaluates */
         double c = (s->type[j] == O_FLUID || s->type[j] == O_INNER_WALL) ? 0.5 : 1.0;
         for (int a = 0; a < 3; ++a)
           for (int b = 0; b < 3; ++b) W[3 * a + b] += c * rij[a] * f[b];
@@ -727,7 +727,7 @@ static int compute_fpi_action(oracle_system* s) {
         s->f_dg[3 * si + a] = -B * Vs * dv[a];
         s->f_pg[3 * si + a] = P->rho0 * Vs / P->mass_fluid * (fcd[a] / omega);
       }
-      /* virial of the coupling (R17), lever M_s = sum_j w_sj r_sj / Omega_s */
+      /* virial of the coupling (R20), lever M_s = sum_j w_sj r_sj / Omega_s */
       for (int a = 0; a < 3; ++a)
         for (int c = 0; c < 3; ++c)
           s->vir[9 * si + 3 * a + c] +=
@@ -924,7 +924,7 @@ static int update(oracle_system* s, int velver) {
   const oracle_params* P = &s->P;
   int bad = 0, out = 0;
   int act = rigid_active(s);
-  /* Lees-Edwards offset at the time the drift moves to (R16) */
+  /* Lees-Edwards offset at the time the drift moves to (R19) */
   const int le = P->shear_rate != 0.0;
   const double le_new = le_shift_at(P, s->step + 1);
   const double le_dv = P->shear_rate * P->L[2];
@@ -1338,7 +1338,7 @@ int oracle_totals(oracle_system* s, double out[16]) {
 
 int64_t oracle_get_step(const oracle_system* s) { return s ? s->step : -1; }
 
-/* pressure tensor of the box (R17): kinetic part from the current
+/* pressure tensor of the box (R20): kinetic part from the current
  * velocities, virial from the last force evaluation */
 int oracle_stress(oracle_system* s, double out[9]) {
   if (!s || !out) return ORACLE_E_INVALID_ARG;

@@ -21,6 +21,14 @@ __device__ __forceinline__ int xcd_tid() {
   return (int)(lb * blockDim.x + threadIdx.x);
 }
 
+// Global wavefront index with blocks taken in XCD order: consecutive
+// wavefronts (neighbouring spheres in cell order) share an XCD and its L2.
+__device__ __forceinline__ int xcd_wave() {
+  unsigned nb = gridDim.x, b = blockIdx.x;
+  unsigned lb = (nb % 8u == 0u) ? (b % 8u) * (nb / 8u) + (b / 8u) : b;
+  return (int)((lb * blockDim.x + threadIdx.x) >> 6);
+}
+
 // Launch block -> (box, first sorted particle): the box is uniform over a
 // block, so its constants are scalar loads.  Blocks are taken in XCD order
 // (block b runs on XCD b % 8; each XCD gets a contiguous run of the table).

@@ -301,7 +301,7 @@ __device__ __forceinline__ int reach_cells(const Grid& g, double H) {
 }
 
 __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
-  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int wave = xcd_wave();
   const int lane = threadIdx.x & 63;
   if (wave >= d.nr) return;
   // spheres in rigid-grid cell order: neighbouring waves share cache lines
@@ -442,8 +442,7 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
 
 void launch_fpi_action(const Dev& d, hipStream_t st) {
   if (d.nr == 0) return;
-  int waves_per_block = BS / 64;
-  k_fpi_action<<<(d.nr + waves_per_block - 1) / waves_per_block, BS, 0, st>>>(d);
+  k_fpi_action<<<nblocks((size_t)d.nr * 64), BS, 0, st>>>(d);
 }
 
 // (a7) reaction on the stamped fluid particles, Eq. F_fpi_DG_reac
@@ -605,7 +604,7 @@ __device__ __forceinline__ int dem_pair_eval(const Dev& d, const Geo& G, int s, 
 
 __global__ __launch_bounds__(BS) void k_dem(Dev d, int commit, int* nxt_cnt, int* nxt_partner,
                                            double* nxt_dt) {
-  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int wave = xcd_wave();
   const int lane = threadIdx.x & 63;
   if (wave >= d.nr) return;
   // spheres in rigid-grid cell order: neighbouring waves share cache lines
@@ -711,9 +710,7 @@ __global__ __launch_bounds__(BS) void k_dem(Dev d, int commit, int* nxt_cnt, int
 void launch_dem(const Dev& d, int commit, int* nxt_cnt, int* nxt_partner, double* nxt_dt,
                 hipStream_t st) {
   if (d.nr == 0) return;
-  const int waves_per_block = BS / 64;
-  k_dem<<<(d.nr + waves_per_block - 1) / waves_per_block, BS, 0, st>>>(d, commit, nxt_cnt,
-                                                                      nxt_partner, nxt_dt);
+  k_dem<<<nblocks((size_t)d.nr * 64), BS, 0, st>>>(d, commit, nxt_cnt, nxt_partner, nxt_dt);
 }
 
 // ---------------------------------------------------------------------------
