@@ -7,7 +7,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("sdpdem_kernels.hip", "sdpdem_neighbors.hip", "sdpdem_api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("sdpdem_kernels.hip", "sdpdem_neighbors.hip",
+                                                   "sdpdem_api.hip", "sdpdem_mlp.hip")]
 LIB = os.path.join(HERE, "libsdpdem.so")
 
 FLAGS = [

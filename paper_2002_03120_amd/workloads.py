@@ -311,6 +311,41 @@ def stack_cells(cells):
     return parts, boxes, np.concatenate(box_of)
 
 
+# ---- the viscosity surrogate's inputs -------------------------------------
+
+MLP_LAYERS = (4, 64, 64, 64, 1)
+
+
+def mlp_param_count(layers=MLP_LAYERS):
+    return sum(a * b + b for a, b in zip(layers[:-1], layers[1:]))
+
+
+def mlp_init(seed=0, layers=MLP_LAYERS):
+    """Initial parameters of the surrogate MLP as one flat float32 array in
+    the order W1 [in x out] row-major, b1, W2, b2, ...: weights uniform in
+    +-sqrt(6 / (fan_in + fan_out)) (Glorot), biases zero.  Seeded random
+    numbers only; no arithmetic of the network."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for a, b in zip(layers[:-1], layers[1:]):
+        lim = math.sqrt(6.0 / (a + b))
+        parts.append(rng.uniform(-lim, lim, size=a * b))
+        parts.append(np.zeros(b))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def mlp_queries(n, seed=0, phi=(0.0, 0.4), d=(2.0, 6.0), kBT=(5e-4, 5e-3), shear=(1e-3, 1e-1)):
+    """Query points (phi, d/dx, kT, log shear rate) uniform over the
+    viscometer's sampling box (log-uniform in the shear rate)."""
+    rng = np.random.default_rng(seed)
+    q = np.empty((n, 4), np.float32)
+    q[:, 0] = rng.uniform(*phi, size=n)
+    q[:, 1] = rng.uniform(*d, size=n)
+    q[:, 2] = rng.uniform(*kBT, size=n)
+    q[:, 3] = rng.uniform(math.log(shear[0]), math.log(shear[1]), size=n)
+    return q
+
+
 def periodic_scale(n_side=(256, 256, 128), **over):
     """Scale run: a fully periodic SDPD lattice at density 1 with the
     reverse-Poiseuille constants (2^23 particles at the default size)."""

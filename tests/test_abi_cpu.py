@@ -1,5 +1,5 @@
 """Host-side checks of the C-ABI library that need no GPU: it loads,
-exports every symbol of include/sdpdem.h, sizes workspaces and rejects bad
+exports every symbol declared in include/*.h, sizes workspaces and rejects bad
 arguments before touching a device."""
 import ctypes
 import os
@@ -15,7 +15,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared_symbols():
-    src = open(os.path.join(ROOT, "include", "sdpdem.h")).read()
+    import glob
+    src = "".join(open(f).read() for f in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))))
     return sorted(set(re.findall(r"\b(sdpdem_[a-z_]+)\s*\(", src)))
 
 
