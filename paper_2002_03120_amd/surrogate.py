@@ -1,0 +1,219 @@
+"""The viscometer workflow: effective viscosities measured by batched
+Lees-Edwards shear cells, a surrogate MLP trained on them on the GPU, and
+queries answered by the network inside its training box and by the plain
+simulation (the batched viscometer) outside it.
+
+Every number comes from the HIP library (libsdpdem.so): the cells run on
+sdpdem_create_batch / sdpdem_step / sdpdem_box_stress, the network on the
+sdpdem_mlp_* kernels; this module only arranges inputs and averages the
+per-box stress samples the library returns.
+
+Viscosity: eta_eff = -<P_zx> / shear_rate over the second half of a run,
+<.> the mean of the per-step samples; its standard error from block means
+(blocks of `block` steps).  The network's target is log(eta_eff / eta).
+
+    python -m paper_2002_03120_amd.surrogate --cells 4096 --steps 2000
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import mlp as MLP
+from . import sdpdem as S
+from . import workloads as W
+
+# the sampling box of the viscometer (phi, d/dx, kT, log shear rate)
+BOX_LO = np.array([0.0, 2.0, 5e-4, math.log(1e-3)])
+BOX_HI = np.array([0.4, 6.0, 5e-3, math.log(1e-1)])
+
+
+def features(infos):
+    """(phi, d/dx, kT, log shear rate) of measured cells (the achieved phi)."""
+    return np.array([[i["phi"], i["d"], i["kBT"], math.log(i["shear_rate"])] for i in infos],
+                    np.float32)
+
+
+def measure(cells, steps, block=50, chunk_particles=4_000_000, log=None):
+    """Run the cells as batches of at most chunk_particles particles.
+    Returns (eta_eff / eta, standard error of it) per cell."""
+    import torch
+    eta_rel = np.empty(len(cells))
+    se_rel = np.empty(len(cells))
+    start = 0
+    while start < len(cells):
+        stop, n = start, 0
+        while stop < len(cells) and (stop == start or n + cells[stop][2]["n"] <= chunk_particles):
+            n += cells[stop][2]["n"]
+            stop += 1
+        part = cells[start:stop]
+        parts, boxes, box_of = W.stack_cells(part)
+        g = S.System(part[0][0], parts, boxes=boxes, box_of=box_of)
+        g.set_stress(True)
+        nb = len(part)
+        sums = []
+        prev = np.zeros(nb)
+        for _ in range(steps // block):
+            g.step(block)
+            _, tot, _ = g.box_stress()
+            sums.append(tot - prev)
+            prev = tot
+        del g
+        torch.cuda.empty_cache()
+        blocks = np.array(sums) / block  # block means of P_zx, [nblocks, nb]
+        half = blocks[blocks.shape[0] // 2:]
+        gd = np.array([c[2]["shear_rate"] for c in part])
+        eta0 = np.array([c[0]["eta"] for c in part])
+        mean = half.mean(axis=0)
+        se = half.std(axis=0, ddof=1) / math.sqrt(max(half.shape[0], 2))
+        eta_rel[start:stop] = -mean / gd / eta0
+        se_rel[start:stop] = se / np.abs(gd) / eta0
+        if log:
+            log(f"measured cells {start}..{stop - 1} ({n} particles)")
+        start = stop
+    return eta_rel, se_rel
+
+
+def normalisation(lo=BOX_LO, hi=BOX_HI):
+    """Mean and standard deviation of the uniform sampling box (the inputs'
+    fixed normalisation)."""
+    mean = 0.5 * (lo + hi)
+    std = (hi - lo) / math.sqrt(12.0)
+    return np.concatenate([mean, std]).astype(np.float32)
+
+
+class Surrogate:
+    """The trained network plus the plain simulation as its fallback."""
+
+    def __init__(self, net, lo, hi, cell_kw=None, fallback_steps=2000):
+        self.net = net
+        self.lo = np.asarray(lo, np.float32)
+        self.hi = np.asarray(hi, np.float32)
+        self.cell_kw = dict(cell_kw or {})
+        self.fallback_steps = fallback_steps
+
+    def inside(self, q):
+        q = np.asarray(q, np.float32)
+        return np.all((q >= self.lo) & (q <= self.hi), axis=1)
+
+    def predict(self, q):
+        """eta_eff / eta by the network (inputs as features())."""
+        import torch
+        x = torch.from_numpy(np.ascontiguousarray(q, np.float32)).cuda()
+        return np.exp(self.net.predict(x).cpu().numpy().astype(np.float64))
+
+    def query(self, q, seed=12345):
+        """Answers inside the training box from the network, the others by
+        running the plain simulation for them.  Returns (eta_eff / eta,
+        mask of the answers that came from the simulation)."""
+        q = np.asarray(q, np.float32)
+        ins = self.inside(q)
+        out = np.empty(q.shape[0])
+        if ins.any():
+            out[ins] = self.predict(q[ins])
+        if (~ins).any():
+            cells = []
+            for k, row in enumerate(q[~ins]):
+                cells.append(W.shear_cell(phi=float(row[0]), d=float(row[1]), kBT=float(row[2]),
+                                          shear_rate=float(math.exp(row[3])),
+                                          seed=seed + k, **self.cell_kw))
+            out[~ins] = measure(cells, self.fallback_steps)[0]
+        return out, ~ins
+
+
+def train(x, y, epochs=300, batch=256, lr=3e-3, seed=0, log=None):
+    """Adam on the GPU over shuffled mini-batches; returns the network and
+    the per-epoch mean training loss."""
+    import torch
+    net = MLP.Mlp(W.mlp_init(seed), normalisation(), lr=lr)
+    xd = torch.from_numpy(np.ascontiguousarray(x, np.float32)).cuda()
+    yd = torch.from_numpy(np.ascontiguousarray(y, np.float32)).cuda()
+    rng = np.random.default_rng(seed)
+    hist = []
+    n = x.shape[0]
+    for ep in range(epochs):
+        order = torch.from_numpy(rng.permutation(n)).cuda()
+        tot = 0.0
+        nb = 0
+        for b0 in range(0, n, batch):
+            idx = order[b0:b0 + batch]
+            net.train_step(xd[idx], yd[idx], update=True)
+            if ep == epochs - 1 or ep % 50 == 0:
+                tot += net.read()[3]
+                nb += 1
+        if nb:
+            hist.append((ep, tot / nb))
+            if log:
+                log(f"epoch {ep} loss {tot / nb:.5f}")
+    return net, hist
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--cells", type=int, default=4096, help="training cells")
+    ap.add_argument("--eval-cells", type=int, default=64, help="fresh plain runs for the error")
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--side", type=int, nargs=2, default=[12, 16])
+    ap.add_argument("--epochs", type=int, default=400)
+    ap.add_argument("--queries", type=int, default=1 << 20)
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args(argv)
+    log = lambda m: print(f"# {m}", file=sys.stderr, flush=True)
+    import torch
+    torch.cuda.set_device(0)
+    kw = dict(side=tuple(args.side), steps=args.steps)
+    t0 = time.perf_counter()
+    _, cells = W.viscometer_batch(args.cells, seed=args.seed, **kw)
+    eta, se = measure(cells, args.steps, log=log)
+    torch.cuda.synchronize()
+    t_meas = time.perf_counter() - t0
+    x = features([c[2] for c in cells])
+    ok = eta > 0
+    y = np.log(np.where(ok, eta, 1.0)).astype(np.float32)
+    t0 = time.perf_counter()
+    net, hist = train(x[ok], y[ok], epochs=args.epochs, seed=args.seed, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    # fresh plain runs, never seen in training
+    _, fresh = W.viscometer_batch(args.eval_cells, seed=args.seed + 999, **kw)
+    eta_f, se_f = measure(fresh, args.steps, log=log)
+    sur = Surrogate(net, BOX_LO, BOX_HI)
+    pred = sur.predict(features([c[2] for c in fresh]))
+    rel = np.abs(pred / eta_f - 1.0)
+    rel_se = se_f / np.abs(eta_f)
+    quiet = rel_se < 0.02
+    q = W.mlp_queries(args.queries, seed=args.seed + 7)
+    qd = torch.from_numpy(q).cuda()
+    net.predict(qd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        net.predict(qd)
+    torch.cuda.synchronize()
+    t_q = (time.perf_counter() - t0) / 10
+    res = {
+        "train_cells": args.cells, "steps_per_run": args.steps, "side": args.side,
+        "measure_s": round(t_meas, 2), "train_s": round(t_train, 2),
+        "final_train_loss": hist[-1][1],
+        "eval_cells": args.eval_cells,
+        "median_rel_error": float(np.median(rel)),
+        "mean_rel_error": float(rel.mean()),
+        "median_plain_rel_se": float(np.median(rel_se)),
+        "cells_with_plain_se_below_2pct": int(quiet.sum()),
+        "mean_rel_error_where_plain_se_below_2pct": float(rel[quiet].mean()) if quiet.any() else None,
+        "frac_within_5pct_where_plain_se_below_2pct":
+            float((rel[quiet] <= 0.05).mean()) if quiet.any() else None,
+        "queries": args.queries, "query_s": t_q, "queries_per_s": args.queries / t_q,
+        "plain_runs_per_s": args.cells / t_meas,
+    }
+    print(json.dumps(res), flush=True)
+    return res
+
+
+if __name__ == "__main__":
+    main()
