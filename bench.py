@@ -63,41 +63,41 @@ def profiled_counters():
             "lane_use": float(kv["lane_use"])}
 
 
-def viscometer_leg(k_steps, n_cells=256, run_steps=5000):
+def viscometer_leg(k_steps, n_cells=256, run_steps=5000, graph_steps=10):
     """Batched viscometer: the 256 Lees-Edwards shear cells of uneven size
     advanced together (one launch per kernel for all cells) against the same
-    cells run one after another as plain systems.  Each configuration is
-    timed over k_steps steps after 3 warm-up steps; runs/hr extrapolates to
-    run_steps steps per run."""
+    cells run one after another as plain systems.  Both run on a side stream
+    with the step loop replayed from captured HIP graphs (graph_steps steps
+    per graph) and stress sampling on; each configuration is timed over
+    k_steps steps after a warm-up that includes the capture; runs/hr
+    extrapolates to run_steps steps per run."""
     import torch
 
     from paper_2002_03120_amd import sdpdem as S
     from paper_2002_03120_amd import workloads as W
 
+    k_steps = max(graph_steps, (k_steps // graph_steps) * graph_steps)
+    st = torch.cuda.Stream()
+
+    def timed(p, parts, **kw):
+        g = S.System(p, parts, stream=st, **kw)
+        g.set_stress(True)
+        g.set_graph(graph_steps)
+        g.step(1 + graph_steps)  # first build, capture, one replay
+        st.synchronize()
+        t0 = time.perf_counter()
+        g.step(k_steps)
+        st.synchronize()
+        t = (time.perf_counter() - t0) / k_steps
+        del g
+        return t
+
     shared, cells = W.viscometer_batch(n_cells, seed=0, steps=run_steps)
     parts, boxes, box_of = W.stack_cells(cells)
     n_all = int(parts["id"].shape[0])
-    g = S.System(shared, parts, boxes=boxes, box_of=box_of)
-    g.set_stress(True)
-    g.step(3)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    g.step(k_steps)
-    torch.cuda.synchronize()
-    t_batch = (time.perf_counter() - t0) / k_steps
-    del g
+    t_batch = timed(shared, parts, boxes=boxes, box_of=box_of)
     torch.cuda.empty_cache()
-    t_plain = 0.0
-    for p, pp, info in cells:
-        c = S.System(p, pp)
-        c.set_stress(True)
-        c.step(3)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        c.step(k_steps)
-        torch.cuda.synchronize()
-        t_plain += (time.perf_counter() - t0) / k_steps
-        del c
+    t_plain = sum(timed(p, pp) for p, pp, _info in cells)
     torch.cuda.empty_cache()
     rb = n_cells / (t_batch * run_steps) * 3600.0
     rp = n_cells / (t_plain * run_steps) * 3600.0
@@ -108,9 +108,32 @@ def viscometer_leg(k_steps, n_cells=256, run_steps=5000):
         "batched_ms_per_step": round(t_batch * 1e3, 3),
         "plain_ms_per_step_all_cells": round(t_plain * 1e3, 3),
         "batched_particle_steps_per_s": round(n_all / t_batch, 1),
-        "sample": f"{k_steps} timed steps per configuration after 3 warm-up steps, "
-                  f"extrapolated to {run_steps} steps per run",
+        "graph_steps": graph_steps,
+        "sample": f"{k_steps} timed steps per configuration after a warm-up of "
+                  f"{1 + graph_steps} steps (graph capture included), extrapolated to "
+                  f"{run_steps} steps per run",
     }
+
+
+def graph_ms_per_step(p, parts, steps, graph_steps=10):
+    """The same workload with its step loop replayed from captured graphs
+    (same results bit for bit); reported beside the eager figure."""
+    import torch
+
+    from paper_2002_03120_amd import sdpdem as S
+
+    st = torch.cuda.Stream()
+    g = S.System(p, parts, stream=st)
+    g.set_graph(graph_steps)
+    g.step(1 + graph_steps)
+    st.synchronize()
+    steps = max(graph_steps, (steps // graph_steps) * graph_steps)
+    t0 = time.perf_counter()
+    g.step(steps)
+    st.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    del g
+    return t * 1e3
 
 
 def main():
@@ -124,6 +147,8 @@ def main():
     ap.add_argument("--small", action="store_true", help="a small tank, for quick checks")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration)")
+    ap.add_argument("--graph-steps", type=int, default=10,
+                    help="steps per captured graph for the graph-replay figure (0: skip)")
     ap.add_argument("--viscometer-steps", type=int, default=20,
                     help="timed steps per configuration of the batched-viscometer leg (0: skip)")
     args = ap.parse_args()
@@ -225,9 +250,12 @@ def main():
                          "rho_max": float(tot[10])},
     }
 
+    del sysm
+    torch.cuda.empty_cache()
+    if args.graph_steps > 0:
+        result["ms_per_step_graph"] = round(graph_ms_per_step(p, parts, args.steps,
+                                                              args.graph_steps), 4)
     if args.viscometer_steps > 0:
-        del sysm
-        torch.cuda.empty_cache()
         result["viscometer"] = viscometer_leg(args.viscometer_steps)
 
     if args.cpu_seconds > 0:

@@ -181,6 +181,15 @@ int sdpdem_create_batch(const sdpdem_params* params, const sdpdem_box* boxes, in
  * device status (overflow, non-finite, out of domain) seen at the end. */
 int sdpdem_step(sdpdem_system* sys, int64_t nsteps, void* hip_stream);
 
+/* Replay the step loop from a captured HIP graph of steps_per_graph steps
+ * (an even number; 0 switches it off, the default).  sdpdem_step then runs
+ * whole graphs where it can and single steps otherwise; results are the
+ * same bits as without graphs.  Capture needs a stream other than the null
+ * stream; where capture fails the calls stay eager.  The graph is
+ * re-captured after profiling, stress sampling or the rigid activation
+ * (itr_actv_rigid) change the launch sequence. */
+int sdpdem_set_graph(sdpdem_system* sys, int steps_per_graph);
+
 /* One evaluation of every force at the current state (Alg. 2), no update. */
 int sdpdem_compute_forces(sdpdem_system* sys, void* hip_stream);
 

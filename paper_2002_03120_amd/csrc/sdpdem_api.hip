@@ -36,6 +36,11 @@ struct sdpdem_system {
   bool noise = false;
   bool stress = false;
   int64_t stress_samples = 0;
+  // captured step loop (graph_steps steps, an even number, per launch)
+  int graph_steps = 0;
+  hipGraphExec_t gexec = nullptr;
+  bool g_act = false, g_stress = false;
+  int g_cur = 0, g_ct = 0;  // buffer parity the graph was captured with
   BoxD* boxes = nullptr;  // device copy of the box table
   std::vector<BoxD> h_boxes;
   std::vector<int> h_gid2slot;
@@ -230,6 +235,8 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
   D4* rdg_c = b.take<D4>(nr);
   int* rslot_pos = b.take<int>(nr);
   int* cstamp = b.take<int>(np);
+  int64_t* dstep = b.take<int64_t>(1);
+  int* dstamp = b.take<int>(1);
   int *ctc0 = b.take<int>(nr), *ctc1 = b.take<int>(nr);
   int *ctp0 = b.take<int>(nr * z.maxc), *ctp1 = b.take<int>(nr * z.maxc);
   double *ctd0 = b.take<double>(3 * nr * z.maxc), *ctd1 = b.take<double>(3 * nr * z.maxc);
@@ -302,6 +309,8 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
     d.rdg_c = rdg_c;
     d.rslot_pos = rslot_pos;
     d.cstamp = cstamp;
+    d.dstep = dstep;
+    d.dstamp = dstamp;
   }
   return total;
 }
@@ -469,7 +478,6 @@ void fill_constants(sdpdem_system* s, const Sizes& z) {
   d.cR = (float)P.coeff_r;
   d.cT = (float)P.coeff_t;
   d.leverf = (float)(0.5 * P.dx);
-  d.stamp = 0;
   s->noise = false;
   for (const BoxD& B : z.boxes) s->noise = s->noise || B.noise;
   s->h_boxes = z.boxes;
@@ -584,13 +592,14 @@ bool rigid_active(const sdpdem_system* s) {
 // (a5)-(a9): one force evaluation (Alg. 2) and, if asked, the update.
 void run_pass(sdpdem_system* s, int velver, int commit, bool integrate, hipStream_t st) {
   Dev& d = s->d;
+  // the pass's stamp marks the fluid particles coupled in it
+  launch_pass_begin(d, integrate ? velver : 0, st);
   {
     Prof pr(s, SDPDEM_K_FLUID_FORCES, st);
-    launch_fluid_forces(d, (uint32_t)s->step, s->noise, st);
+    launch_fluid_forces(d, s->noise, st);
   }
   const bool act = rigid_active(s);
   if (act) {
-    d.stamp += 1;  // marks the fluid particles coupled in this pass
     {
       Prof pr(s, SDPDEM_K_RIGID_GRID, st);
       launch_rigid_gather(d, st);
@@ -705,6 +714,12 @@ int create_impl(const sdpdem_params* params, const sdpdem_box* boxes, int nbox,
   ok &= hipMemcpyAsync(s->boxes, z.boxes.data(), sizeof(BoxD) * z.nbox, hipMemcpyHostToDevice, st) == hipSuccess;
   ok &= hipMemcpyAsync(const_cast<int2*>(d.blk), z.blk.data(), sizeof(int2) * z.blk.size(),
                        hipMemcpyHostToDevice, st) == hipSuccess;
+  {
+    const int64_t step0 = params->itr_start;
+    const int stamp0 = 0;
+    ok &= hipMemcpyAsync(d.dstep, &step0, sizeof(int64_t), hipMemcpyHostToDevice, st) == hipSuccess;
+    ok &= hipMemcpyAsync(d.dstamp, &stamp0, sizeof(int), hipMemcpyHostToDevice, st) == hipSuccess;
+  }
   if (z.nr) {
     ok &= hipMemcpyAsync(d.rig_gid, hrg.data(), sizeof(int) * z.nr, hipMemcpyHostToDevice, st) == hipSuccess;
     ok &= hipMemcpyAsync(d.rig_sorted, hsort.data(), sizeof(int) * z.nr, hipMemcpyHostToDevice, st) == hipSuccess;
@@ -798,34 +813,113 @@ int sdpdem_create_batch(const sdpdem_params* params, const sdpdem_box* boxes, in
                      hip_stream, out);
 }
 
+namespace {
+
+// One iteration of Algorithm 1 (enqueue only).
+void step_body(sdpdem_system* s, hipStream_t st) {
+  Dev& d = s->d;
+  // Lees-Edwards offsets for positions at this step and after the drift
+  launch_le_shift(s->boxes, d.nbox, d.dstep, 0, d.dt, st);
+  if (!s->cache_valid) run_build(s, st);
+  run_pass(s, 1, 0, true, st);
+  // positions moved: sort, neighbours, density and smoothing at x(n+1);
+  // they stay valid for the first pass of the next step
+  launch_le_shift(s->boxes, d.nbox, d.dstep, 1, d.dt, st);
+  run_build(s, st);
+  run_pass(s, 2, 1, true, st);
+  if (s->stress) {
+    launch_box_stress(d, 1, st);
+    s->stress_samples += 1;
+  }
+  launch_step_end(d, st);
+  s->cache_valid = true;
+  s->step += 1;
+}
+
+void drop_graph(sdpdem_system* s) {
+  if (s->gexec) hipGraphExecDestroy(s->gexec);
+  s->gexec = nullptr;
+}
+
+// Capture graph_steps steps into one executable graph.  Every per-step
+// value the kernels need (step number, pass stamps, Lees-Edwards offsets)
+// lives in device memory, and the host-side buffer swaps repeat with
+// period two, so an even number of captured steps replays correctly.
+bool capture(sdpdem_system* s, hipStream_t st) {
+  drop_graph(s);
+  const int64_t step0 = s->step, samples0 = s->stress_samples;
+  const int cur0 = s->cur, ct0 = s->ct_cur;
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+  for (int k = 0; k < s->graph_steps; ++k) step_body(s, st);
+  const bool ok = hipStreamEndCapture(st, &g) == hipSuccess && g;
+  // nothing ran yet: restore the host mirror of the device state
+  s->step = step0;
+  s->stress_samples = samples0;
+  if (s->cur != cur0 || s->ct_cur != ct0) {
+    if (g) hipGraphDestroy(g);
+    return false;
+  }
+  if (!ok) return false;
+  hipGraphExec_t ex = nullptr;
+  const bool inst = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
+  hipGraphDestroy(g);
+  if (!inst) return false;
+  s->gexec = ex;
+  s->g_act = rigid_active(s);
+  s->g_stress = s->stress;
+  s->g_cur = s->cur;
+  s->g_ct = s->ct_cur;
+  return true;
+}
+
+}  // namespace
+
 int sdpdem_step(sdpdem_system* s, int64_t nsteps, void* hip_stream) {
   if (!s || nsteps < 0) return SDPDEM_E_INVALID_ARG;
   hipStream_t st = (hipStream_t)hip_stream;
-  Dev& d = s->d;
-  for (int64_t it = 0; it < nsteps; ++it) {
-    // Lees-Edwards offsets for positions at this step and after the drift
-    launch_le_shift(s->boxes, d.nbox, s->step, d.dt, st);
-    if (!s->cache_valid) run_build(s, st);
-    run_pass(s, 1, 0, true, st);
-    // positions moved: sort, neighbours, density and smoothing at x(n+1);
-    // they stay valid for the first pass of the next step
-    launch_le_shift(s->boxes, d.nbox, s->step + 1, d.dt, st);
-    run_build(s, st);
-    run_pass(s, 2, 1, true, st);
-    if (s->stress) {
-      launch_box_stress(d, 1, st);
-      s->stress_samples += 1;
+  int64_t left = nsteps;
+  const int K = s->graph_steps;
+  while (left > 0) {
+    // replay whole graphs while nothing that shapes the launch sequence
+    // changes inside them (first build done, no timing, rigid activation
+    // not crossed)
+    const bool act_now = rigid_active(s);
+    const bool act_stable =
+        s->d.nr == 0 || s->step >= s->P.itr_actv_rigid || s->step + K <= s->P.itr_actv_rigid;
+    if (K > 0 && left >= K && s->cache_valid && s->prof_kernel == SDPDEM_K_NONE && act_stable) {
+      // the graph bakes in the double buffers' roles: an odd number of
+      // eager steps since the capture swaps them, so capture again
+      if (!s->gexec || s->g_act != act_now || s->g_stress != s->stress || s->g_cur != s->cur ||
+          s->g_ct != s->ct_cur) {
+        if (!capture(s, st)) {
+          s->graph_steps = 0;  // capture unavailable: stay eager
+          continue;
+        }
+      }
+      if (hipGraphLaunch(s->gexec, st) != hipSuccess) return SDPDEM_E_HIP;
+      s->step += K;
+      if (s->stress) s->stress_samples += K;
+      left -= K;
+    } else {
+      step_body(s, st);
+      left -= 1;
     }
-    s->cache_valid = true;
-    s->step += 1;
   }
   return sync_status(s, st);
+}
+
+int sdpdem_set_graph(sdpdem_system* s, int steps_per_graph) {
+  if (!s || steps_per_graph < 0 || steps_per_graph % 2) return SDPDEM_E_INVALID_ARG;
+  drop_graph(s);
+  s->graph_steps = steps_per_graph;
+  return SDPDEM_OK;
 }
 
 int sdpdem_compute_forces(sdpdem_system* s, void* hip_stream) {
   if (!s) return SDPDEM_E_INVALID_ARG;
   hipStream_t st = (hipStream_t)hip_stream;
-  launch_le_shift(s->boxes, s->d.nbox, s->step, s->d.dt, st);
+  launch_le_shift(s->boxes, s->d.nbox, s->d.dstep, 0, s->d.dt, st);
   if (!s->cache_valid) {
     run_build(s, st);
     s->cache_valid = true;
@@ -1061,6 +1155,7 @@ int sdpdem_info(sdpdem_system* s, int64_t out[16], void* hip_stream) {
 
 int sdpdem_set_profiling(sdpdem_system* s, int kernel) {
   if (!s || kernel < 0 || kernel >= SDPDEM_NUM_KERNELS) return SDPDEM_E_INVALID_ARG;
+  drop_graph(s);
   prof_flush(s);
   s->prof_kernel = kernel;
   s->prof_ms = 0.0;
@@ -1080,6 +1175,7 @@ int sdpdem_kernel_time(sdpdem_system* s, double* total_ms, int64_t* launches) {
 
 void sdpdem_destroy(sdpdem_system* s) {
   if (!s) return;
+  drop_graph(s);
   prof_flush(s);
   for (auto& e : s->ev) {
     hipEventDestroy(e.first);

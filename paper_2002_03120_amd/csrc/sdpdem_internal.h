@@ -162,7 +162,10 @@ struct Dev {
   int* rslot_pos;  // slot -> t
   // fluid particles coupled to a sphere in the current pass carry the stamp
   int* cstamp;
-  int stamp;
+  // device-resident counters (so that a captured graph replays correctly):
+  // the step number and the stamp of the current pass
+  int64_t* dstep;
+  int* dstamp;
   int* ct_cnt;      // current contact table
   int* ct_partner;  // partner id
   double* ct_dt;
@@ -188,12 +191,17 @@ void launch_cell_sort(const int* start, int ncells, int* perm, const int* sortke
 void launch_permute(const Dev& d, const D4* spos, const D4* svel, const D4* som,
                     const uint8_t* stype, const int* sgid, hipStream_t st);
 void launch_build_density(const Dev& d, hipStream_t st);
-// Lees-Edwards offsets of every box for positions at step pos_step
-void launch_le_shift(BoxD* boxes, int nbox, int64_t pos_step, double dt, hipStream_t st);
+// Lees-Edwards offsets of every box for positions at step *dstep + add
+void launch_le_shift(BoxD* boxes, int nbox, const int64_t* dstep, int add, double dt,
+                     hipStream_t st);
+// stamp of a pass: 4 step + code + 1 (code 1, 2: passes of a step; 0: a
+// force evaluation without update); the step counter's increment
+void launch_pass_begin(const Dev& d, int code, hipStream_t st);
+void launch_step_end(const Dev& d, hipStream_t st);
 // per-box sample of P_zx; with accumulate, also added to the running sums
 void launch_box_stress(const Dev& d, int accumulate, hipStream_t st);
 void launch_smooth(const Dev& d, hipStream_t st);
-void launch_fluid_forces(const Dev& d, uint32_t step, bool noise, hipStream_t st);
+void launch_fluid_forces(const Dev& d, bool noise, hipStream_t st);
 void launch_rigid_gather(const Dev& d, hipStream_t st);
 void launch_fpi_action(const Dev& d, hipStream_t st);
 void launch_fpi_reaction(const Dev& d, hipStream_t st);

@@ -84,10 +84,11 @@ void launch_bin_rigid(const Dev& d, hipStream_t st) {
 
 // Lees-Edwards offsets delta(t) = fmod(shear L_z t, L_x) of every box for
 // positions at step pos_step and at the step after
-__global__ void k_le_shift(BoxD* boxes, int nbox, int64_t pos_step, double dt) {
+__global__ void k_le_shift(BoxD* boxes, int nbox, const int64_t* dstep, int add, double dt) {
 #pragma clang fp contract(off)
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nbox) return;
+  const int64_t pos_step = dstep[0] + add;
   BoxD& B = boxes[b];
   if (!B.le) {
     B.le_shift = 0.0;
@@ -106,8 +107,23 @@ __global__ void k_le_shift(BoxD* boxes, int nbox, int64_t pos_step, double dt) {
   }
 }
 
-void launch_le_shift(BoxD* boxes, int nbox, int64_t pos_step, double dt, hipStream_t st) {
-  k_le_shift<<<(nbox + 63) / 64, 64, 0, st>>>(boxes, nbox, pos_step, dt);
+void launch_le_shift(BoxD* boxes, int nbox, const int64_t* dstep, int add, double dt,
+                     hipStream_t st) {
+  k_le_shift<<<(nbox + 63) / 64, 64, 0, st>>>(boxes, nbox, dstep, add, dt);
+}
+
+__global__ void k_pass_begin(const int64_t* dstep, int* dstamp, int code) {
+  if (threadIdx.x == 0) dstamp[0] = (int)(4 * dstep[0] + code + 1);
+}
+__global__ void k_step_end(int64_t* dstep) {
+  if (threadIdx.x == 0) dstep[0] += 1;
+}
+
+void launch_pass_begin(const Dev& d, int code, hipStream_t st) {
+  k_pass_begin<<<1, 64, 0, st>>>(d.dstep, d.dstamp, code);
+}
+void launch_step_end(const Dev& d, hipStream_t st) {
+  k_step_end<<<1, 64, 0, st>>>(d.dstep);
 }
 
 static constexpr int SCAN_ITEMS = 8;
@@ -318,6 +334,7 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
                      cell_coord(ps.z, gr, 2, &oob)};
   const int kr = reach_cells(gr, H);
   const size_t np = (size_t)d.npad;
+  const int stamp = d.dstamp[0];
   double om = 0, v0 = 0, v1 = 0, v2 = 0, f0 = 0, f1 = 0, f2 = 0, l0 = 0, l1 = 0, l2 = 0;
   int nrig = 0;
   // the search box row by row: lane r takes row r of each batch of 64 rows
@@ -389,7 +406,7 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
       l0 += w * ex;
       l1 += w * ey;
       l2 += w * ez;
-      d.cstamp[j] = d.stamp;
+      d.cstamp[j] = stamp;
     }
   }
   om = wave_sum(om);
@@ -454,7 +471,7 @@ __global__ __launch_bounds__(BS) void k_fpi_reaction(Dev d) {
   if (b < 0) return;
   const BoxD& B = d.boxes[b];
   if (i >= B.first + B.count) return;
-  if (d.cstamp[i] != d.stamp || d.type[i] != T_FLUID) return;
+  if (d.cstamp[i] != d.dstamp[0] || d.type[i] != T_FLUID) return;
   D4 pi = d.pos[i];
   const Geo G = geo_of(B);
   const Grid gr = B.rg;
@@ -729,7 +746,8 @@ __device__ __forceinline__ void total_force(const Dev& d, const BoxD& B, int i, 
   for (int a = 0; a < 3; ++a) {
     double body = m * d.body[a] * sg;
     if (t == T_FLUID) {
-      double rx = (d.have_rxn && d.cstamp[i] == d.stamp) ? (double)d.fout[(9 + a) * np + i] : 0.0;
+      double rx = (d.have_rxn && d.cstamp[i] == d.dstamp[0]) ? (double)d.fout[(9 + a) * np + i]
+                                                              : 0.0;
       F[a] = (double)d.fout[a * np + i] + rx + body;
       N[a] = (double)d.fout[(3 + a) * np + i];
     } else if (t == T_INNER) {
@@ -925,7 +943,7 @@ __global__ __launch_bounds__(BS) void k_read_field(Dev d, int field, int rigid_a
     case SDPDEM_F_CD:
     case SDPDEM_F_RXN: {
       int base = field == SDPDEM_F_SDPD ? 0 : field == SDPDEM_N_SDPD ? 3 : field == SDPDEM_F_CD ? 6 : 9;
-      if (field != SDPDEM_F_RXN || (d.have_rxn && d.cstamp[i] == d.stamp))
+      if (field != SDPDEM_F_RXN || (d.have_rxn && d.cstamp[i] == d.dstamp[0]))
         for (int a = 0; a < 3; ++a) v[a] = (double)d.fout[(base + a) * np + i];
     } break;
     case SDPDEM_F_DG:

@@ -135,7 +135,7 @@ void launch_smooth(const Dev& d, hipStream_t st) {
 // per-particle sums; outputs F^SDPD, its torque and the F^C + F^D sum.
 
 template <bool NOISE, bool STRESS>
-__global__ __launch_bounds__(BS) void k_fluid_forces(Dev d, uint32_t step) {
+__global__ __launch_bounds__(BS) void k_fluid_forces(Dev d) {
   int i;
   const int b = blk_box(d, i);
   if (b < 0) return;
@@ -156,6 +156,7 @@ __global__ __launch_bounds__(BS) void k_fluid_forces(Dev d, uint32_t step) {
     const bool noise = NOISE && B.noise;
     const float kT = B.kTf;
     const uint32_t key0 = B.key0, key1 = B.key1;
+    const uint32_t step = NOISE ? (uint32_t)d.dstep[0] : 0u;  // noise counter
     // software-pipelined: the record of slot k+1 and the index of slot k+2
     // are in flight while slot k is evaluated
     int jn = cnt > 0 ? nb[0] : i;
@@ -263,17 +264,17 @@ __global__ __launch_bounds__(BS) void k_fluid_forces(Dev d, uint32_t step) {
   if (STRESS) o[12 * np + i] = Wzx;
 }
 
-void launch_fluid_forces(const Dev& d, uint32_t step, bool noise, hipStream_t st) {
+void launch_fluid_forces(const Dev& d, bool noise, hipStream_t st) {
   if (noise) {
     if (d.stress)
-      k_fluid_forces<true, true><<<d.nblk, BS, 0, st>>>(d, step);
+      k_fluid_forces<true, true><<<d.nblk, BS, 0, st>>>(d);
     else
-      k_fluid_forces<true, false><<<d.nblk, BS, 0, st>>>(d, step);
+      k_fluid_forces<true, false><<<d.nblk, BS, 0, st>>>(d);
   } else {
     if (d.stress)
-      k_fluid_forces<false, true><<<d.nblk, BS, 0, st>>>(d, step);
+      k_fluid_forces<false, true><<<d.nblk, BS, 0, st>>>(d);
     else
-      k_fluid_forces<false, false><<<d.nblk, BS, 0, st>>>(d, step);
+      k_fluid_forces<false, false><<<d.nblk, BS, 0, st>>>(d);
   }
 }
 

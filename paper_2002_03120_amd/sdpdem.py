@@ -107,6 +107,7 @@ def lib():
                                           ctypes.c_int32, ctypes.POINTER(Particles), vp, vp, sz,
                                           vp, ctypes.POINTER(vp)]
         L.sdpdem_set_stress.argtypes = [vp, ctypes.c_int, vp]
+        L.sdpdem_set_graph.argtypes = [vp, ctypes.c_int]
         L.sdpdem_box_stress.argtypes = [vp, vp, vp, ctypes.POINTER(i64), vp]
         L.sdpdem_step.argtypes = [vp, i64, vp]
         L.sdpdem_compute_forces.argtypes = [vp, vp]
@@ -415,6 +416,10 @@ class System:
 
     def set_profiling(self, kernel):
         sdpdem_set_profiling(self.h, kernel)
+
+    def set_graph(self, steps_per_graph):
+        """Replay steps from a captured graph (needs a non-null stream)."""
+        _check(lib().sdpdem_set_graph(self.h, int(steps_per_graph)), "sdpdem_set_graph")
 
     def set_stress(self, on=True):
         sdpdem_set_stress(self.h, on, self.stream)

@@ -40,9 +40,11 @@ def features(infos):
 
 
 def measure(cells, steps, block=50, chunk_particles=4_000_000, log=None):
-    """Run the cells as batches of at most chunk_particles particles.
+    """Run the cells as batches of at most chunk_particles particles (on a
+    side stream, the step loop replayed from captured graphs of 10 steps).
     Returns (eta_eff / eta, standard error of it) per cell."""
     import torch
+    stream = torch.cuda.Stream()
     eta_rel = np.empty(len(cells))
     se_rel = np.empty(len(cells))
     start = 0
@@ -53,8 +55,9 @@ def measure(cells, steps, block=50, chunk_particles=4_000_000, log=None):
             stop += 1
         part = cells[start:stop]
         parts, boxes, box_of = W.stack_cells(part)
-        g = S.System(part[0][0], parts, boxes=boxes, box_of=box_of)
+        g = S.System(part[0][0], parts, boxes=boxes, box_of=box_of, stream=stream)
         g.set_stress(True)
+        g.set_graph(10)
         nb = len(part)
         sums = []
         prev = np.zeros(nb)
