@@ -377,6 +377,8 @@ bool plan(const sdpdem_params* P, const sdpdem_box* boxes, int nbox,
     // DEM partners lie within R_s + R_k + h <= 2 R_max + h
     double mincs = std::min(B.rg.cs[0], std::min(B.rg.cs[1], B.rg.cs[2]));
     B.dem_reach = std::max(1, (int)std::ceil((2.0 * rmax + P->h) / mincs * (1.0 + 1e-9)));
+    B.couple_R = rmax + P->h;
+    B.dem_R = 2.0 * rmax + P->h;
     B.cell_off = (int)coff;
     B.rcell_off = (int)rcoff;
     coff += B.g.ncells;

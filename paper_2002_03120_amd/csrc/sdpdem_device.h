@@ -152,35 +152,48 @@ __device__ __forceinline__ double sqrt_nr(double x) {
 // one 64-byte pair record (four 16-byte loads from one cache line)
 __device__ __forceinline__ PR load_pr(const PR* base, int j) { return base[j]; }
 
-// The cells within k of cell cc (local coordinates, particle x coordinate
-// px) of a box in grid G, row by row: row r = (iz, iy) of the (2k+1)^2
-// rows (all rows of an axis when the stencil would wrap onto itself) holds
-// at most two runs of consecutive x cells, [a0, a1) and [b0, b1) in global
-// keys (off = the box's cell offset); empty runs have a0 == a1.  Rows seen
-// through a Lees-Edwards z face are centred on the shifted x coordinate and
-// widened by one cell on each side; when the stencil wraps onto itself
-// along z under shear, every x cell is taken.
+// The cells that can hold partners within R of a point (px, py, pz) in
+// cell cc of a box's grid G, searched over the (2k+1)^2 rows (z, y) around
+// cc (all rows of an axis when the stencil would wrap onto itself).  A row
+// whose slab lies R or more away from the point in y and z is empty; in
+// the others only the x cells within sqrt(R^2 - d^2) of the point's x (d
+// its distance to the slab) are taken, at most the 2k+1 cells around cc.
+// Rows seen through a Lees-Edwards z face are centred on the shifted x
+// coordinate; when the stencil wraps onto itself along z under shear every
+// x cell is taken.  Row r holds at most two runs of consecutive x cells,
+// [a0, a1) and [b0, b1) in global keys (off = the box's cell offset);
+// empty runs have a0 == a1.  The x range carries a relative margin of 1e-9
+// so that the distance test, not the range, decides.
 struct StencilShape {
   int zlo, zn, ylo, yn;
+  bool zall, yall;
 };
 
 __device__ __forceinline__ StencilShape stencil_shape(const Grid& G, const int cc[3], int k) {
   StencilShape sh;
-  const bool zall = G.per[2] && 2 * k + 1 > G.nc[2];
-  const bool yall = G.per[1] && 2 * k + 1 > G.nc[1];
-  sh.zlo = zall ? 0 : cc[2] - k;
-  sh.zn = zall ? G.nc[2] : 2 * k + 1;
-  sh.ylo = yall ? 0 : cc[1] - k;
-  sh.yn = yall ? G.nc[1] : 2 * k + 1;
+  sh.zall = G.per[2] && 2 * k + 1 > G.nc[2];
+  sh.yall = G.per[1] && 2 * k + 1 > G.nc[1];
+  sh.zlo = sh.zall ? 0 : cc[2] - k;
+  sh.zn = sh.zall ? G.nc[2] : 2 * k + 1;
+  sh.ylo = sh.yall ? 0 : cc[1] - k;
+  sh.yn = sh.yall ? G.nc[1] : 2 * k + 1;
   return sh;
 }
 
+// distance of x to the slab [lo, lo + cs)
+__device__ __forceinline__ double slab_dist(double x, double lo, double cs) {
+  return fmax(0.0, fmax(lo - x, x - (lo + cs)));
+}
+
+template <bool PRUNE>
 __device__ __forceinline__ void stencil_row(const Geo& B, const Grid& G, int off, double px,
-                                            const int cc[3], int k, const StencilShape& sh,
-                                            int r, int& a0, int& a1, int& b0, int& b1) {
+                                            double py, double pz, double R, const int cc[3],
+                                            int k, const StencilShape& sh, int r, int& a0,
+                                            int& a1, int& b0, int& b1) {
   a0 = a1 = b0 = b1 = 0;
   const int nx = G.nc[0], ny = G.nc[1], nz = G.nc[2];
-  int z = sh.zlo + r / sh.yn, y = sh.ylo + r % sh.yn, wz = 0;
+  const int zu = sh.zlo + r / sh.yn, yu = sh.ylo + r % sh.yn;  // unwrapped rows
+  int z = zu, y = yu, wz = 0;
   if (z < 0) {
     if (!G.per[2]) return;
     z += nz;
@@ -197,20 +210,49 @@ __device__ __forceinline__ void stencil_row(const Geo& B, const Grid& G, int off
     if (!G.per[1]) return;
     y -= ny;
   }
-  int x0 = cc[0] - k, xn = 2 * k + 1;
-  if (B.le && (sh.zn == nz && G.per[2] && 2 * k + 1 > nz)) {
+  // reach in x from the distance to the row's slab (unwrapped coordinates)
+  double d2 = 0.0;
+  if (PRUNE && !sh.zall) {
+    const double dz = slab_dist(pz, G.lo[2] + (double)zu * G.cs[2], G.cs[2]);
+    d2 += dz * dz;
+  }
+  if (PRUNE && !sh.yall) {
+    const double dy = slab_dist(py, G.lo[1] + (double)yu * G.cs[1], G.cs[1]);
+    d2 += dy * dy;
+  }
+  if (PRUNE && d2 >= R * R) return;
+  const double rx = PRUNE ? sqrt(R * R - d2) * (1.0 + 1e-9) + 1e-9 * G.cs[0]
+                          : (double)(k + 1) * G.cs[0];
+  int x0, xn;
+  if (B.le && sh.zall) {
     x0 = 0;
     xn = nx;
-  } else if (B.le && wz != 0) {
-    // candidates sit around x - k_z delta, k_z = wz
-    double xc = px - (double)wz * B.le_shift;
-    double f = floor((xc - G.lo[0]) * G.inv_cs[0]);
-    f = f - (double)nx * floor(f / (double)nx);
-    int c = (int)f;
-    if (c < 0) c = 0;
-    if (c >= nx) c = nx - 1;
-    x0 = c - k - 1;
-    xn = 2 * k + 3;
+  } else {
+    // candidates sit around x - k_z delta (k_z = wz, 0 off the sheared faces)
+    const double xc = (B.le && wz != 0) ? px - (double)wz * B.le_shift : px;
+    int xa, xb;
+    if (!PRUNE && !(B.le && wz != 0)) {  // the plain stencil
+      xa = cc[0] - k;
+      xb = cc[0] + k;
+    } else {
+      xa = (int)floor((xc - rx - G.lo[0]) * G.inv_cs[0]);
+      xb = (int)floor((xc + rx - G.lo[0]) * G.inv_cs[0]);
+      if (!(B.le && wz != 0)) {  // never beyond the plain stencil
+        xa = max(xa, cc[0] - k);
+        xb = min(xb, cc[0] + k);
+      }
+    }
+    x0 = xa;
+    xn = xb - xa + 1;
+    if (xn <= 0) return;
+    if (G.per[0]) {
+      if (xn >= nx) {
+        x0 = 0;
+        xn = nx;
+      } else {
+        x0 = ((x0 % nx) + nx) % nx;
+      }
+    }
   }
   const int rowkey = off + (z * ny + y) * nx;
   if (G.per[0] && xn >= nx) {
@@ -223,13 +265,8 @@ __device__ __forceinline__ void stencil_row(const Geo& B, const Grid& G, int off
       a1 = rowkey + hi + 1;
     }
   } else {
-    int lo = x0, hi = x0 + xn - 1;  // at most one wrap
-    if (lo < 0) {
-      a0 = rowkey + lo + nx;
-      a1 = rowkey + nx;
-      b0 = rowkey;
-      b1 = rowkey + hi + 1;
-    } else if (hi >= nx) {
+    int lo = x0, hi = x0 + xn - 1;  // 0 <= lo < nx: at most one wrap
+    if (hi >= nx) {
       a0 = rowkey + lo;
       a1 = rowkey + nx;
       b0 = rowkey;
@@ -241,15 +278,18 @@ __device__ __forceinline__ void stencil_row(const Geo& B, const Grid& G, int off
   }
 }
 
-// the same cells as fn(first_key, end_key) over the runs, in row order
-template <class Fn>
+// the same cells as fn(first_key, end_key) over the runs, in row order;
+// PRUNE = false keeps the whole 2k+1 cells of every row (one thread per
+// particle: lanes of a cell then walk the same runs in step)
+template <bool PRUNE, class Fn>
 __device__ __forceinline__ void for_stencil(const Geo& B, const Grid& G, int off, double px,
-                                            const int cc[3], int k, Fn&& fn) {
+                                            double py, double pz, double R, const int cc[3],
+                                            int k, Fn&& fn) {
   const StencilShape sh = stencil_shape(G, cc, k);
   const int nrows = sh.zn * sh.yn;
   for (int r = 0; r < nrows; ++r) {
     int a0, a1, b0, b1;
-    stencil_row(B, G, off, px, cc, k, sh, r, a0, a1, b0, b1);
+    stencil_row<PRUNE>(B, G, off, px, py, pz, R, cc, k, sh, r, a0, a1, b0, b1);
     if (a1 > a0) fn(a0, a1);
     if (b1 > b0) fn(b0, b1);
   }

@@ -73,6 +73,8 @@ struct BoxD {
   int cell_off, rcell_off;
   int first, count;   // sorted particle range
   int dem_reach;      // rigid-grid cells to search for DEM partners
+  double couple_R;    // R_max + h: coupling partners lie within it
+  double dem_R;       // 2 R_max + h: DEM and lubrication partners lie within it
   int noise;          // thermal forces on
   float kTf;
   uint32_t key0, key1;

@@ -345,7 +345,8 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
     int sa = 0, la = 0, sb = 0, lb = 0;
     if (rb + lane < nrows) {
       int a0, a1, b0, b1;
-      stencil_row(G, gr, coff, ps.x, cc, kr, sh, rb + lane, a0, a1, b0, b1);
+      stencil_row<true>(G, gr, coff, ps.x, ps.y, ps.z, H, cc, kr, sh, rb + lane, a0, a1, b0,
+                        b1);
       if (a1 > a0) {
         sa = d.cstart[a0];
         la = d.cstart[a1] - sa;
@@ -480,7 +481,7 @@ __global__ __launch_bounds__(BS) void k_fpi_reaction(Dev d) {
   int cc[3] = {cell_coord(pi.x, gr, 0, &oob), cell_coord(pi.y, gr, 1, &oob),
                cell_coord(pi.z, gr, 2, &oob)};
   double a0 = 0, a1 = 0, a2 = 0;
-  for_stencil(G, gr, coff, pi.x, cc, 1, [&](int cb, int ce) {
+  for_stencil<false>(G, gr, coff, pi.x, pi.y, pi.z, B.couple_R, cc, 1, [&](int cb, int ce) {
     int tb = d.rstart[cb], te = d.rstart[ce];
     for (int t = tb; t < te; ++t) {
       D4 g = d.rdg_c[t];
@@ -631,6 +632,8 @@ __global__ __launch_bounds__(BS) void k_dem(Dev d, int commit, int* nxt_cnt, int
   const Geo G = geo_of(B);
   const Grid gr = B.rg;
   const int coff = B.rcell_off, reach = B.dem_reach;
+  // partners k lie within R_s + R_k + h <= R_s + (R_max + h)
+  const double dem_Rk = B.couple_R;
   const D4 ps = d.rpos_c[me], vs = d.rvel_c[me], ws = d.rom_c[me];
   int oob = 0;
   int cc[3] = {cell_coord(ps.x, gr, 0, &oob), cell_coord(ps.y, gr, 1, &oob),
@@ -646,7 +649,8 @@ __global__ __launch_bounds__(BS) void k_dem(Dev d, int commit, int* nxt_cnt, int
     int sa = 0, la = 0, sb = 0, lb = 0;
     if (rb + lane < nrows) {
       int a0, a1, b0, b1;
-      stencil_row(G, gr, coff, ps.x, cc, reach, sh, rb + lane, a0, a1, b0, b1);
+      stencil_row<true>(G, gr, coff, ps.x, ps.y, ps.z, ps.w + dem_Rk, cc, reach, sh, rb + lane,
+                        a0, a1, b0, b1);
       if (a1 > a0) {
         sa = d.rstart[a0];
         la = d.rstart[a1] - sa;

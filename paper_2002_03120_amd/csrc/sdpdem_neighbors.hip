@@ -38,7 +38,7 @@ __global__ __launch_bounds__(BS) void k_build_density(Dev d) {
   int cnt = 0;
   const size_t npad = (size_t)d.npad;
   int* const nb = d.nbr + i;
-  for_stencil(G, gr, coff, pi.x, cc, 1, [&](int k0, int k1) {
+  for_stencil<false>(G, gr, coff, pi.x, pi.y, pi.z, d.h, cc, 1, [&](int k0, int k1) {
     const int jb = d.cstart[k0];
     const int je = d.cstart[k1];
     for (int j = jb; j < je; ++j) {
