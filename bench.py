@@ -63,45 +63,64 @@ def profiled_counters():
             "lane_use": float(kv["lane_use"])}
 
 
-def viscometer_leg(k_steps, n_cells=256, run_steps=5000, graph_steps=10):
+def viscometer_leg(k_steps, n_cells=256, run_steps=5000, graph_steps=10, tune=True):
     """Batched viscometer: the 256 Lees-Edwards shear cells of uneven size
-    advanced together (one launch per kernel for all cells) against the same
-    cells run one after another as plain systems.  Both run on a side stream
-    with the step loop replayed from captured HIP graphs (graph_steps steps
-    per graph) and stress sampling on; each configuration is timed over
-    k_steps steps after a warm-up that includes the capture; runs/hr
-    extrapolates to run_steps steps per run."""
+    advanced together (one launch per kernel for all cells of a batch)
+    against the same cells run one after another as plain systems.  All run
+    on a side stream with the step loop replayed from captured HIP graphs and
+    stress sampling on; each system is timed over k_steps steps after a
+    warm-up that includes the capture; runs/hr extrapolates to run_steps
+    steps per run.  The batched figure is taken twice: at the default launch
+    shape (cell = h, graph_steps steps per graph, all cells in one batch) and
+    at the shape the autotuner picks (its own trials are not timed here)."""
     import torch
 
+    from paper_2002_03120_amd import autotune as AT
     from paper_2002_03120_amd import sdpdem as S
     from paper_2002_03120_amd import workloads as W
 
-    k_steps = max(graph_steps, (k_steps // graph_steps) * graph_steps)
     st = torch.cuda.Stream()
 
-    def timed(p, parts, **kw):
+    def timed(p, parts, cell_factor=1.0, gs=graph_steps, **kw):
+        k = max(gs, (k_steps // gs) * gs)
+        p = dict(p, cell_factor=float(cell_factor))
         g = S.System(p, parts, stream=st, **kw)
         g.set_stress(True)
-        g.set_graph(graph_steps)
-        g.step(1 + graph_steps)  # first build, capture, one replay
+        g.set_graph(gs)
+        g.step(1 + gs)  # first build, capture, one replay
         st.synchronize()
         t0 = time.perf_counter()
-        g.step(k_steps)
+        g.step(k)
         st.synchronize()
-        t = (time.perf_counter() - t0) / k_steps
+        t = (time.perf_counter() - t0) / k
+        g.close()
         del g
+        torch.cuda.empty_cache()
         return t
 
+    def batched(cs, cell_factor=1.0, gs=graph_steps):
+        parts, boxes, box_of = W.stack_cells(cs)
+        return timed(cs[0][0], parts, cell_factor, gs, boxes=boxes, box_of=box_of)
+
     shared, cells = W.viscometer_batch(n_cells, seed=0, steps=run_steps)
-    parts, boxes, box_of = W.stack_cells(cells)
-    n_all = int(parts["id"].shape[0])
-    t_batch = timed(shared, parts, boxes=boxes, box_of=box_of)
-    torch.cuda.empty_cache()
+    n_all = sum(c[2]["n"] for c in cells)
+    t_batch = batched(cells)
+    out = {}
+    if tune:
+        tun = AT.tune(cells, run_steps)
+        t_tuned = sum(batched(cells[a:b], tun["cell_factor"], tun["graph_steps"])
+                      for a, b, _n in AT.split(cells, tun["tile"]))
+        out["autotuned"] = {
+            "cell_factor": tun["cell_factor"], "graph_steps": tun["graph_steps"],
+            "tile_particles": tun["tile"], "tune_s": round(tun["tune_s"], 2),
+            "trials": len(tun["trials"]),
+            "batched_ms_per_step": round(t_tuned * 1e3, 3),
+            "batched_runs_per_hour": round(n_cells / (t_tuned * run_steps) * 3600.0, 1),
+        }
     t_plain = sum(timed(p, pp) for p, pp, _info in cells)
-    torch.cuda.empty_cache()
     rb = n_cells / (t_batch * run_steps) * 3600.0
     rp = n_cells / (t_plain * run_steps) * 3600.0
-    return {
+    res = {
         "cells": n_cells, "particles": n_all, "steps_per_run": run_steps,
         "batched_runs_per_hour": round(rb, 1), "plain_runs_per_hour": round(rp, 1),
         "speedup": round(rb / rp, 2),
@@ -109,10 +128,13 @@ def viscometer_leg(k_steps, n_cells=256, run_steps=5000, graph_steps=10):
         "plain_ms_per_step_all_cells": round(t_plain * 1e3, 3),
         "batched_particle_steps_per_s": round(n_all / t_batch, 1),
         "graph_steps": graph_steps,
-        "sample": f"{k_steps} timed steps per configuration after a warm-up of "
-                  f"{1 + graph_steps} steps (graph capture included), extrapolated to "
-                  f"{run_steps} steps per run",
+        "sample": f"{k_steps} timed steps per system after a warm-up of 1 + graph length "
+                  f"steps (graph capture included), extrapolated to {run_steps} steps per run",
     }
+    if "autotuned" in out:
+        res["autotuned"] = out["autotuned"]
+        res["autotuned"]["speedup_vs_plain"] = round(out["autotuned"]["batched_runs_per_hour"] / rp, 2)
+    return res
 
 
 def graph_ms_per_step(p, parts, steps, graph_steps=10):

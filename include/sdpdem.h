@@ -88,6 +88,9 @@ typedef struct sdpdem_params {
                               non-zero needs all axes periodic: flow along x,
                               gradient along z, the image above shifted by
                               shear_rate L_z t in x and moving at +shear_rate L_z */
+  double cell_factor;      /* fluid cell size = max(1, cell_factor) h, at most
+                              16 h: a tuning knob (0 = 1); neighbour sets do not
+                              depend on it, FP32 sums only through their order  */
 } sdpdem_params;
 
 /* Particles, host memory, n rows in any order (ids must cover 0..n-1).
@@ -167,6 +170,10 @@ int sdpdem_create(const sdpdem_params* params, const sdpdem_particles* particles
  * launch covering all of them (the batched viscometer).  box_of[k] gives
  * the box of particle row k; ids run over 0..n-1 across all boxes.  No
  * pair, contact or coupling ever joins particles of different boxes.
+ * The thermal noise of a pair is keyed by its box's seed and the two ids
+ * less the smallest id in the box, so a box whose ids are a contiguous
+ * range runs bit for bit as the same box alone (ids from 0) would, whatever
+ * the other boxes of the batch.
  * Rejects what sdpdem_create rejects, per box, and box_of entries outside
  * 0..nbox-1; a box with shear_rate != 0 must be periodic on all axes. */
 int sdpdem_batch_workspace_bytes(const sdpdem_params* params, const sdpdem_box* boxes,

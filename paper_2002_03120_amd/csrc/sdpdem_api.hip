@@ -76,6 +76,7 @@ bool valid_params(const sdpdem_params* P) {
   if (P->max_neighbors < 1 || P->max_contacts < 1) return false;
   if (P->xi < 40.0 * P->eta / 51.0 || P->xi > 5.0 * P->eta / 3.0) return false;
   if (P->gravity_axis < 0 || P->gravity_axis > 2) return false;
+  if (!(P->cell_factor >= 0.0) || P->cell_factor > 16.0) return false;
   return true;
 }
 
@@ -368,7 +369,8 @@ bool plan(const sdpdem_params* P, const sdpdem_box* boxes, int nbox,
     B.le_shift = 0.0;
     B.le_next = 0.0;
     B.vol = hb.L[0] * hb.L[1] * hb.L[2];
-    if (!make_grid(hb, *q, r, P->h * (1.0 + 1e-6), B.g)) return false;
+    const double cf = P->cell_factor > 1.0 ? P->cell_factor : 1.0;
+    if (!make_grid(hb, *q, r, cf * P->h * (1.0 + 1e-6), B.g)) return false;
     for (int a = 0; a < 3; ++a)
       if (B.per[a] && B.g.nc[a] < 3) return false;
     // rigid grid: cells at least H_max = R_max + h wide, so that the fluid
@@ -391,6 +393,9 @@ bool plan(const sdpdem_params* P, const sdpdem_box* boxes, int nbox,
     B.kTf = (float)hb.kBT;
     B.key0 = (uint32_t)(hb.seed & 0xffffffffu);
     B.key1 = (uint32_t)(hb.seed >> 32);
+    int64_t id0 = r.empty() ? 0 : q->id[r[0]];
+    for (int64_t k : r) id0 = std::min(id0, q->id[k]);
+    B.id_base = (uint32_t)id0;
     for (int c = 0; c < (B.count + BS - 1) / BS; ++c)
       z.blk.push_back(make_int2(b, B.first + c * BS));
     for (int64_t k : r) z.order.push_back(k);

@@ -78,6 +78,7 @@ struct BoxD {
   int noise;          // thermal forces on
   float kTf;
   uint32_t key0, key1;
+  uint32_t id_base;   // smallest id in the box: noise counters use ids above it
 };
 
 // The part of a box the pair loops need, copied into registers once per

@@ -146,7 +146,8 @@ __global__ __launch_bounds__(BS) void k_fluid_forces(Dev d) {
   float Wzx = 0.f;
   if (ti == T_FLUID || ti == T_INNER) {
     const PR ri = load_pr(d.prec, i);
-    const uint32_t gi = (uint32_t)ri.gid;
+    const uint32_t ib = B.id_base;
+    const uint32_t gi = (uint32_t)ri.gid - ib;  // box-local noise index
     const int cnt = d.nbr_cnt[i];
     const int* nb = d.nbr + i;
     const size_t npad = (size_t)d.npad;
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(BS) void k_fluid_forces(Dev d) {
       if (noise) {
         // thermal force, Eq. FijT with dW^S = sym(dW) - tr(dW)/3
         float z[9];
-        pair_normals(gi, (uint32_t)rj.gid, step, key0, key1, z);
+        pair_normals(gi, (uint32_t)rj.gid - ib, step, key0, key1, z);
         const float sa = 2.0f * sqrtf(kT * d.CAf * fdd);
         const float sb = 2.0f * sqrtf(kT * d.CBf * fdd);
         const float tr3 = (z[0] + z[4] + z[8]) * (1.0f / 3.0f);

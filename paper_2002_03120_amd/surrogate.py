@@ -24,6 +24,7 @@ import time
 
 import numpy as np
 
+from . import autotune as AT
 from . import mlp as MLP
 from . import sdpdem as S
 from . import workloads as W
@@ -39,25 +40,29 @@ def features(infos):
                     np.float32)
 
 
-def measure(cells, steps, block=50, chunk_particles=4_000_000, log=None):
+def measure(cells, steps, block=50, chunk_particles=4_000_000, tuning=None, log=None):
     """Run the cells as batches of at most chunk_particles particles (on a
     side stream, the step loop replayed from captured graphs of 10 steps).
-    Returns (eta_eff / eta, standard error of it) per cell."""
+    A `tuning` from autotune.tune replaces the batch tile, the graph length
+    and the cell size by its choice.  Returns (eta_eff / eta, standard error
+    of it) per cell."""
     import torch
+    cell_factor, graph_steps = 1.0, 10
+    if tuning is not None:
+        cell_factor, graph_steps = tuning["cell_factor"], tuning["graph_steps"]
+        chunk_particles = tuning["tile"]
+    # stress is read every `block` steps: a whole number of graphs
+    block = max(graph_steps, (block // graph_steps) * graph_steps)
     stream = torch.cuda.Stream()
     eta_rel = np.empty(len(cells))
     se_rel = np.empty(len(cells))
-    start = 0
-    while start < len(cells):
-        stop, n = start, 0
-        while stop < len(cells) and (stop == start or n + cells[stop][2]["n"] <= chunk_particles):
-            n += cells[stop][2]["n"]
-            stop += 1
+    for start, stop, n in AT.split(cells, chunk_particles):
         part = cells[start:stop]
         parts, boxes, box_of = W.stack_cells(part)
-        g = S.System(part[0][0], parts, boxes=boxes, box_of=box_of, stream=stream)
+        p = dict(part[0][0], cell_factor=float(cell_factor))
+        g = S.System(p, parts, boxes=boxes, box_of=box_of, stream=stream)
         g.set_stress(True)
-        g.set_graph(10)
+        g.set_graph(graph_steps)
         nb = len(part)
         sums = []
         prev = np.zeros(nb)
@@ -78,7 +83,6 @@ def measure(cells, steps, block=50, chunk_particles=4_000_000, log=None):
         se_rel[start:stop] = se / np.abs(gd) / eta0
         if log:
             log(f"measured cells {start}..{stop - 1} ({n} particles)")
-        start = stop
     return eta_rel, se_rel
 
 
@@ -165,6 +169,8 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=400)
     ap.add_argument("--queries", type=int, default=1 << 20)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shape (cell = h, 10-step graphs, 4M-particle batches)")
     args = ap.parse_args(argv)
     log = lambda m: print(f"# {m}", file=sys.stderr, flush=True)
     import torch
@@ -172,7 +178,8 @@ def main(argv=None):
     kw = dict(side=tuple(args.side), steps=args.steps)
     t0 = time.perf_counter()
     _, cells = W.viscometer_batch(args.cells, seed=args.seed, **kw)
-    eta, se = measure(cells, args.steps, log=log)
+    tuning = None if args.no_autotune else AT.tune(cells, args.steps, log=log)
+    eta, se = measure(cells, args.steps, tuning=tuning, log=log)
     torch.cuda.synchronize()
     t_meas = time.perf_counter() - t0
     x = features([c[2] for c in cells])
@@ -184,7 +191,7 @@ def main(argv=None):
     t_train = time.perf_counter() - t0
     # fresh plain runs, never seen in training
     _, fresh = W.viscometer_batch(args.eval_cells, seed=args.seed + 999, **kw)
-    eta_f, se_f = measure(fresh, args.steps, log=log)
+    eta_f, se_f = measure(fresh, args.steps, tuning=tuning, log=log)
     sur = Surrogate(net, BOX_LO, BOX_HI)
     pred = sur.predict(features([c[2] for c in fresh]))
     rel = np.abs(pred / eta_f - 1.0)
@@ -202,6 +209,8 @@ def main(argv=None):
     res = {
         "train_cells": args.cells, "steps_per_run": args.steps, "side": args.side,
         "measure_s": round(t_meas, 2), "train_s": round(t_train, 2),
+        "launch_shape": None if tuning is None else
+            {k: tuning[k] for k in ("cell_factor", "graph_steps", "tile", "tune_s")},
         "final_train_loss": hist[-1][1],
         "eval_cells": args.eval_cells,
         "median_rel_error": float(np.median(rel)),

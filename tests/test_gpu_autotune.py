@@ -1,0 +1,46 @@
+"""The viscometer autotuner on the GPU: its trials, its choice, and the
+launch shapes it chooses between leaving the measured viscosities alone."""
+import numpy as np
+import pytest
+
+from paper_2002_03120_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def AT():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2002_03120_amd import autotune
+    return autotune
+
+
+def test_tuner_picks_the_fastest_predicted_shape(AT):
+    _, cells = W.viscometer_batch(12, seed=4, side=(12, 20), steps=100)
+    n = sum(c[2]["n"] for c in cells)
+    print(f"[case] tune {len(cells)} cells, {n} particles", flush=True)
+    res = AT.tune(cells, 1000, sample_steps=10, cell_factors=(1.0, 1.3),
+                  graph_steps=(2, 10), tiles=(n // 3, 1 << 22))
+    timed = [t for t in res["trials"] if "predicted_s" in t]
+    assert len(timed) == 2 * 2 + 1
+    assert res["predicted_s"] == min(t["predicted_s"] for t in timed)
+    assert res["cell_factor"] in (1.0, 1.3) and res["graph_steps"] in (2, 10)
+    assert res["tile"] in (n // 3, 1 << 22)
+    assert all(t["step_ms"] > 0 and t["create_s"] > 0 for t in timed)
+
+
+def test_batch_tile_and_graph_length_do_not_change_results(AT):
+    """Each cell owns its particle range, noise key and stress sums, so how
+    the cells are packed into batches and how many steps a graph holds
+    leave every measured value bit for bit the same."""
+    from paper_2002_03120_amd import surrogate as SG
+    _, cells = W.viscometer_batch(6, seed=5, side=(10, 14), steps=80)
+    n = sum(c[2]["n"] for c in cells)
+    print(f"[case] measure {len(cells)} cells two ways", flush=True)
+    a = SG.measure(cells, 80, block=20)
+    b = SG.measure(cells, 80, block=20,
+                   tuning=dict(cell_factor=1.0, graph_steps=2, tile=n // 3))
+    assert np.all(np.isfinite(a[1]))
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])

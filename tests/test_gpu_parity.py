@@ -94,3 +94,23 @@ def test_ragged_and_tiny_sizes(S, oracle_lib):
         parts = W.perturb(parts, p, jitter=0.0, kT=1e-3, seed=n, spin=True)
         g, o = _pair(S, oracle_lib, p, parts, f"ragged n={n}")
         _check_all(g, o, p, fields=["F_SDPD", "F_CD", "N_SDPD"])
+
+
+@pytest.mark.parametrize("cf", [1.37, 2.0])
+def test_cell_size_leaves_neighbors_and_forces_unchanged(S, oracle_lib, cf):
+    """The autotuner's cell-size knob: cells of cf x h change only the
+    candidate rows, so the neighbour sets stay bit-exact and the forces stay
+    within the same tolerance of the oracle (which has no such knob)."""
+    p, parts, _ = W.dam_break(tank=(40, 16, 30), column=(20, 16, 20), n_rigid=60, seed=6,
+                              kBT=1e-4)
+    parts = W.perturb(parts, p, jitter=0.1, kT=1e-4, seed=5, spin=True)
+    print(f"[case] dam break 40x16x30 cell_factor={cf}", flush=True)
+    g = S.System(dict(p, cell_factor=cf), parts)
+    o = oracle_lib.Oracle(p, parts)
+    _check_all(g, o, p)
+    q, qparts, _ = W.random_box(900, (9.5, 9.2, 9.6), (1, 1, 1), h=1.5, seed=8)
+    qparts = W.perturb(qparts, q, jitter=0.0, kT=1e-3, seed=18, spin=True)
+    q["kBT"] = 1e-3
+    g = S.System(dict(q, cell_factor=cf), qparts)
+    o = oracle_lib.Oracle(q, qparts)
+    _check_all(g, o, q, fields=["F_SDPD", "F_CD", "N_SDPD"])

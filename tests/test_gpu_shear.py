@@ -181,16 +181,18 @@ def _run(S, p, parts, steps, boxes=None, box_of=None):
     return out
 
 
-def test_batch_equals_separate_boxes(S):
+@pytest.mark.parametrize("kT", [0.0, 1e-3])
+def test_batch_equals_separate_boxes(S, kT):
     """Three cells of different sizes, shear rates and sphere loads, run
     as one batch and one by one: every particle's state and every box's
-    stress sum agree bit for bit (kT = 0: the noise counter uses global ids)."""
-    cells = [W.shear_cell(12, 0.3, 2.5, kBT=0.0, shear_rate=0.05, seed=1, itr_start=10),
-             W.shear_cell(10, 0.0, 0.0, kBT=0.0, shear_rate=-0.02, seed=2, itr_start=10),
-             W.shear_cell(16, 0.2, 4.0, kBT=0.0, shear_rate=0.1, seed=3, itr_start=10)]
+    stress sum agree bit for bit (with noise too: its counters use ids
+    relative to the box's smallest id)."""
+    cells = [W.shear_cell(12, 0.3, 2.5, kBT=kT, shear_rate=0.05, seed=1, itr_start=10),
+             W.shear_cell(10, 0.0, 0.0, kBT=kT, shear_rate=-0.02, seed=2, itr_start=10),
+             W.shear_cell(16, 0.2, 4.0, kBT=kT, shear_rate=0.1, seed=3, itr_start=10)]
     steps = 25
     parts, boxes, box_of = W.stack_cells(cells)
-    print(f"[case] batch of {len(cells)} boxes, n={parts['id'].shape[0]}", flush=True)
+    print(f"[case] batch of {len(cells)} boxes, n={parts['id'].shape[0]}, kT={kT}", flush=True)
     batch = _run(S, cells[0][0], parts, steps, boxes=boxes, box_of=box_of)
     off = 0
     for b, (p, pp, info) in enumerate(cells):
