@@ -169,6 +169,9 @@ def main():
     ap.add_argument("--small", action="store_true", help="a small tank, for quick checks")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration)")
+    ap.add_argument("--cell-factor", type=float, default=0.5,
+                    help="fluid cell size in units of h; the default is the autotuner's "
+                         "pick for the dam break, 0 runs the tuner before the timed region")
     ap.add_argument("--graph-steps", type=int, default=10,
                     help="steps per captured graph for the graph-replay figure (0: skip)")
     ap.add_argument("--viscometer-steps", type=int, default=20,
@@ -203,7 +206,13 @@ def main():
     else:
         p, parts, info = W.dam_break(kBT=args.kT)
     print(f"# workload {info}", file=sys.stderr, flush=True)
-    sysm = S.System(p, parts)
+    tuned = None
+    if args.cell_factor <= 0.0:
+        from paper_2002_03120_amd import autotune as AT
+        tuned = AT.tune_system(p, parts, log=lambda m: print(f"# {m}", file=sys.stderr, flush=True))
+        args.cell_factor = tuned["cell_factor"]
+    pg = dict(p, cell_factor=args.cell_factor)  # the GPU system's parameters
+    sysm = S.System(pg, parts)
     sysm.step(args.warmup)
     torch.cuda.synchronize()
     noise = args.kT > 0
@@ -264,9 +273,11 @@ def main():
             "workload": "dam break with rigid particles" + (" (small)" if args.small else ""),
             "n_fluid": info["n_fluid"], "n_rigid": info["n_rigid"],
             "n_wall": info["n_inner_wall"] + info["n_outer_wall"], "n_total": n,
-            "kT": args.kT, "dt": p["dt"], "h": p["h"],
+            "kT": args.kT, "dt": p["dt"], "h": p["h"], "cell_factor": args.cell_factor,
         },
         "pair_interactions_per_s": round(pair_rate, 1),
+        "cell_size_trials": None if tuned is None else
+            {f"{t['cell_factor']}h": round(t["step_ms"], 4) for t in tuned["trials"] if "step_ms" in t},
         "roofline": roof,
         "status_after": {"max_speed": float(tot[8]), "rho_min": float(tot[9]),
                          "rho_max": float(tot[10])},
@@ -275,7 +286,7 @@ def main():
     del sysm
     torch.cuda.empty_cache()
     if args.graph_steps > 0:
-        result["ms_per_step_graph"] = round(graph_ms_per_step(p, parts, args.steps,
+        result["ms_per_step_graph"] = round(graph_ms_per_step(pg, parts, args.steps,
                                                               args.graph_steps), 4)
     if args.viscometer_steps > 0:
         result["viscometer"] = viscometer_leg(args.viscometer_steps)

@@ -88,9 +88,12 @@ typedef struct sdpdem_params {
                               non-zero needs all axes periodic: flow along x,
                               gradient along z, the image above shifted by
                               shear_rate L_z t in x and moving at +shear_rate L_z */
-  double cell_factor;      /* fluid cell size = max(1, cell_factor) h, at most
-                              16 h: a tuning knob (0 = 1); neighbour sets do not
-                              depend on it, FP32 sums only through their order  */
+  double cell_factor;      /* fluid cell size = cell_factor h, 0.25 <= cell_factor
+                              <= 16 (0 means 1): a tuning knob.  Below 1 the
+                              neighbour search reaches ceil(1/cell_factor) cells
+                              each way and skips cells out of range.  Neighbour
+                              sets do not depend on it; sums only through their
+                              order                                              */
 } sdpdem_params;
 
 /* Particles, host memory, n rows in any order (ids must cover 0..n-1).

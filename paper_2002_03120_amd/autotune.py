@@ -4,9 +4,10 @@ Three knobs decide how fast a set of Lees-Edwards shear cells runs on the
 GPU; none of them changes what is computed (the neighbour sets are fixed by
 the cut-off h, so results move only by FP32 summation order):
 
-* the fluid cell size, cell_factor x h (cell_factor >= 1): larger cells mean
-  fewer, longer stencil rows (fewer bin and row-setup costs) and more
-  candidate pairs outside the cut-off;
+* the fluid cell size, cell_factor x h: cells of h or more are searched as
+  the 27-cell stencil, smaller ones as the rows and x cells within h of the
+  particle (fewer candidate pairs outside the cut-off, more cells to bin and
+  more row set-ups);
 * the batch tile, the number of particles advanced together by one batched
   system (cells are packed in order up to it): one big batch fills the chip
   best, smaller ones keep the working set in the L2 caches;
@@ -16,8 +17,8 @@ Every candidate is created and timed on the GPU itself over a short sample
 of the same cells (graph capture in the warm-up, `sample_steps` timed
 steps); the choice minimises the predicted wall time of the whole run,
   sum over batches of (create time + run_steps x step time).
-The search is coordinate-wise: cell size and graph length on the first
-batch of the largest tile, then the tile at the chosen pair.
+The search is coordinate-wise: the cell size, then the graph length, on the
+first batch of the largest tile, then the tile at the chosen pair.
 
     python -m paper_2002_03120_amd.autotune --cells 256
 """
@@ -31,8 +32,8 @@ import time
 from . import sdpdem as S
 from . import workloads as W
 
-CELL_FACTORS = (1.0, 1.1, 1.2, 1.35, 1.5)
-GRAPH_STEPS = (2, 10, 20)
+CELL_FACTORS = (0.34, 0.5, 0.75, 1.0, 1.25)
+GRAPH_STEPS = (10, 2, 20)  # the first is used while the cell size is tuned
 TILES = (1 << 20, 1 << 21, 1 << 22, 1 << 23)
 
 
@@ -92,53 +93,50 @@ def time_batch(cells, cell_factor, graph_steps, sample_steps, stream):
 def tune(cells, run_steps, sample_steps=40, cell_factors=CELL_FACTORS,
          graph_steps=GRAPH_STEPS, tiles=TILES, log=None):
     """Pick (cell_factor, graph_steps, tile) for running `cells` for
-    `run_steps` steps each.  Returns a dict with the choice, the predicted
-    and default wall times and every trial."""
+    `run_steps` steps each, one knob at a time in that order, the others at
+    their current choice (graph_steps[0], the largest tile to begin with).
+    Returns a dict with the choice, its predicted wall time, that of the
+    default shape (cell = h, 10-step graphs, largest tile) when it was among
+    the trials, and every trial."""
     import torch
     stream = torch.cuda.Stream()
     t_start = time.perf_counter()
     trials = []
     n_all = sum(c[2]["n"] for c in cells)
     big = max(tiles)
-    b0 = split(cells, big)[0]
-    first = cells[b0[0]:b0[1]]
 
-    def predict(tc, ts, tile):
-        # the first batch's per-particle rate stands for every batch of that tile
-        nb = len(split(cells, tile))
-        n_first = split(cells, tile)[0][2]
-        return nb * tc + run_steps * ts * n_all / n_first
+    def trial(cf, gs, tile):
+        a, b, n = split(cells, tile)[0]
+        tc, ts = time_batch(cells[a:b], cf, gs, sample_steps, stream)
+        # the first batch's per-particle rate stands for every batch of the tile
+        tw = len(split(cells, tile)) * tc + run_steps * ts * n_all / n
+        trials.append(dict(cell_factor=cf, graph_steps=gs, tile=tile, particles=n,
+                           create_s=tc, step_ms=ts * 1e3, predicted_s=tw))
+        if log:
+            log(f"cell {cf:.2f}h graph {gs:2d} tile {tile} ({n} particles): "
+                f"{ts * 1e3:.3f} ms/step, predicted {tw:.1f} s")
+        return tw
 
     best = None
+    gs0 = graph_steps[0]
     for cf in cell_factors:
         if not fits(cells, cf):
             trials.append(dict(cell_factor=cf, skipped="fewer than 3 cells on a periodic axis"))
             continue
-        for gs in graph_steps:
-            tc, ts = time_batch(first, cf, gs, sample_steps, stream)
-            tw = predict(tc, ts, big)
-            trials.append(dict(cell_factor=cf, graph_steps=gs, tile=big, particles=b0[2],
-                               create_s=tc, step_ms=ts * 1e3, predicted_s=tw))
-            if log:
-                log(f"cell {cf:.2f}h graph {gs:2d} tile {big}: {ts * 1e3:.3f} ms/step")
-            if best is None or tw < best[0]:
-                best = (tw, cf, gs, big)
+        tw = trial(cf, gs0, big)
+        if best is None or tw < best[0]:
+            best = (tw, cf, gs0, big)
     if best is None:
         raise ValueError("no cell size fits the cells")
-    _, cf, gs, _ = best
-    for tile in sorted(tiles):
-        if tile == big:
-            continue
-        bt = split(cells, tile)[0]
-        tc, ts = time_batch(cells[bt[0]:bt[1]], cf, gs, sample_steps, stream)
-        tw = predict(tc, ts, tile)
-        trials.append(dict(cell_factor=cf, graph_steps=gs, tile=tile, particles=bt[2],
-                           create_s=tc, step_ms=ts * 1e3, predicted_s=tw))
-        if log:
-            log(f"cell {cf:.2f}h graph {gs:2d} tile {tile}: {ts * 1e3:.3f} ms/step "
-                f"({bt[2]} particles)")
+    for gs in graph_steps[1:]:
+        tw = trial(best[1], gs, big)
         if tw < best[0]:
-            best = (tw, cf, gs, tile)
+            best = (tw, best[1], gs, big)
+    for tile in sorted(tiles):
+        if tile != big:
+            tw = trial(best[1], best[2], tile)
+            if tw < best[0]:
+                best = (tw, best[1], best[2], tile)
     default = next((t["predicted_s"] for t in trials if t.get("cell_factor") == 1.0
                     and t.get("graph_steps") == 10 and t.get("tile") == big), None)
     return {
@@ -146,6 +144,38 @@ def tune(cells, run_steps, sample_steps=40, cell_factors=CELL_FACTORS,
         "predicted_s": best[0], "default_predicted_s": default,
         "tune_s": time.perf_counter() - t_start, "trials": trials,
     }
+
+
+def tune_system(p, parts, sample_steps=20, cell_factors=CELL_FACTORS, log=None):
+    """The cell size of one plain system (the dam break, say): each
+    candidate is created and run for sample_steps steps after one warm-up
+    step, eager on the default stream; the fastest step wins.  Returns a
+    dict with the choice and the trials."""
+    import torch
+    trials = []
+    best = None
+    for cf in cell_factors:
+        if not fits([(p, None, None)], cf):
+            trials.append(dict(cell_factor=cf, skipped="fewer than 3 cells on a periodic axis"))
+            continue
+        g = S.System(dict(p, cell_factor=float(cf)), parts)
+        g.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(sample_steps)
+        torch.cuda.synchronize()
+        ts = (time.perf_counter() - t0) / sample_steps
+        g.close()
+        del g
+        torch.cuda.empty_cache()
+        trials.append(dict(cell_factor=cf, step_ms=ts * 1e3))
+        if log:
+            log(f"cell {cf:.2f}h: {ts * 1e3:.3f} ms/step")
+        if best is None or ts < best[0]:
+            best = (ts, cf)
+    if best is None:
+        raise ValueError("no cell size fits the box")
+    return {"cell_factor": best[1], "step_ms": best[0] * 1e3, "trials": trials}
 
 
 def main(argv=None):

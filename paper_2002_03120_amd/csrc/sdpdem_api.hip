@@ -76,7 +76,7 @@ bool valid_params(const sdpdem_params* P) {
   if (P->max_neighbors < 1 || P->max_contacts < 1) return false;
   if (P->xi < 40.0 * P->eta / 51.0 || P->xi > 5.0 * P->eta / 3.0) return false;
   if (P->gravity_axis < 0 || P->gravity_axis > 2) return false;
-  if (!(P->cell_factor >= 0.0) || P->cell_factor > 16.0) return false;
+  if (P->cell_factor != 0.0 && !(P->cell_factor >= 0.25 && P->cell_factor <= 16.0)) return false;
   return true;
 }
 
@@ -369,7 +369,7 @@ bool plan(const sdpdem_params* P, const sdpdem_box* boxes, int nbox,
     B.le_shift = 0.0;
     B.le_next = 0.0;
     B.vol = hb.L[0] * hb.L[1] * hb.L[2];
-    const double cf = P->cell_factor > 1.0 ? P->cell_factor : 1.0;
+    const double cf = P->cell_factor > 0.0 ? P->cell_factor : 1.0;
     if (!make_grid(hb, *q, r, cf * P->h * (1.0 + 1e-6), B.g)) return false;
     for (int a = 0; a < 3; ++a)
       if (B.per[a] && B.g.nc[a] < 3) return false;

@@ -180,6 +180,13 @@ __device__ __forceinline__ StencilShape stencil_shape(const Grid& G, const int c
   return sh;
 }
 
+// cells each way that hold every point within H of a cell's points
+__device__ __forceinline__ int reach_cells(const Grid& g, double H) {
+  int k = 1;
+  for (int a = 0; a < 3; ++a) k = max(k, (int)ceil(H * g.inv_cs[a] * (1.0 + 1e-9)));
+  return k;
+}
+
 // distance of x to the slab [lo, lo + cs)
 __device__ __forceinline__ double slab_dist(double x, double lo, double cs) {
   return fmax(0.0, fmax(lo - x, x - (lo + cs)));

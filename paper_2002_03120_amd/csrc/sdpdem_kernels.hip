@@ -310,12 +310,6 @@ __device__ __forceinline__ int wave_sum_i(int v) {
 }
 
 // cells to search around a point for partners within H (largest over the axes)
-__device__ __forceinline__ int reach_cells(const Grid& g, double H) {
-  int k = 1;
-  for (int a = 0; a < 3; ++a) k = max(k, (int)ceil(H * g.inv_cs[a] * (1.0 + 1e-9)));
-  return k;
-}
-
 __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
   const int wave = xcd_wave();
   const int lane = threadIdx.x & 63;

@@ -10,8 +10,8 @@ namespace sdpdem {
 // (a2)+(a3) neighbour sets {j : r_ij^2 < h^2} (double precision, no
 // contraction) fused with the density summation (Eq. compdens), the
 // equation of state (Eq. prtcpres) and the free-surface clamp.  The
-// 27-cell stencil is walked row by row; three cells of a row are one
-// contiguous slice of the sorted arrays unless the row wraps.
+// stencil is walked row by row; the cells of a row are one contiguous slice
+// of the sorted arrays unless the row wraps.
 
 __global__ __launch_bounds__(BS) void k_build_density(Dev d) {
   int i;
@@ -38,7 +38,7 @@ __global__ __launch_bounds__(BS) void k_build_density(Dev d) {
   int cnt = 0;
   const size_t npad = (size_t)d.npad;
   int* const nb = d.nbr + i;
-  for_stencil<false>(G, gr, coff, pi.x, pi.y, pi.z, d.h, cc, 1, [&](int k0, int k1) {
+  auto run = [&](int k0, int k1) {
     const int jb = d.cstart[k0];
     const int je = d.cstart[k1];
     for (int j = jb; j < je; ++j) {
@@ -54,7 +54,14 @@ __global__ __launch_bounds__(BS) void k_build_density(Dev d) {
         acc += d.w_norm * (1.0 + 3.0 * q) * om * om * om;
       }
     }
-  });
+  };
+  // cells of h or more: the whole 27-cell stencil (lanes of a cell walk the
+  // same runs in step); smaller cells: the rows and x cells within h only
+  const int kr = reach_cells(gr, d.h);
+  if (kr == 1)
+    for_stencil<false>(G, gr, coff, pi.x, pi.y, pi.z, d.h, cc, 1, run);
+  else
+    for_stencil<true>(G, gr, coff, pi.x, pi.y, pi.z, d.h, cc, kr, run);
   if (cnt > d.maxn) {
     atomicOr(d.status, ST_NBR_OVERFLOW);
     cnt = d.maxn;

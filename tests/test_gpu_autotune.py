@@ -21,12 +21,12 @@ def test_tuner_picks_the_fastest_predicted_shape(AT):
     _, cells = W.viscometer_batch(12, seed=4, side=(12, 20), steps=100)
     n = sum(c[2]["n"] for c in cells)
     print(f"[case] tune {len(cells)} cells, {n} particles", flush=True)
-    res = AT.tune(cells, 1000, sample_steps=10, cell_factors=(1.0, 1.3),
-                  graph_steps=(2, 10), tiles=(n // 3, 1 << 22))
+    res = AT.tune(cells, 1000, sample_steps=10, cell_factors=(0.5, 1.0, 1.3),
+                  graph_steps=(10, 2), tiles=(n // 3, 1 << 22))
     timed = [t for t in res["trials"] if "predicted_s" in t]
-    assert len(timed) == 2 * 2 + 1
+    assert len(timed) == 3 + 1 + 1
     assert res["predicted_s"] == min(t["predicted_s"] for t in timed)
-    assert res["cell_factor"] in (1.0, 1.3) and res["graph_steps"] in (2, 10)
+    assert res["cell_factor"] in (0.5, 1.0, 1.3) and res["graph_steps"] in (2, 10)
     assert res["tile"] in (n // 3, 1 << 22)
     assert all(t["step_ms"] > 0 and t["create_s"] > 0 for t in timed)
 

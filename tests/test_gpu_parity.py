@@ -96,10 +96,11 @@ def test_ragged_and_tiny_sizes(S, oracle_lib):
         _check_all(g, o, p, fields=["F_SDPD", "F_CD", "N_SDPD"])
 
 
-@pytest.mark.parametrize("cf", [1.37, 2.0])
+@pytest.mark.parametrize("cf", [0.25, 0.34, 0.5, 0.75, 1.37, 2.0])
 def test_cell_size_leaves_neighbors_and_forces_unchanged(S, oracle_lib, cf):
-    """The autotuner's cell-size knob: cells of cf x h change only the
-    candidate rows, so the neighbour sets stay bit-exact and the forces stay
+    """The autotuner's cell-size knob: cells of cf x h change only which
+    cells are searched (a reach of ceil(1/cf) cells with distance pruning
+    below h), so the neighbour sets stay bit-exact and the forces stay
     within the same tolerance of the oracle (which has no such knob)."""
     p, parts, _ = W.dam_break(tank=(40, 16, 30), column=(20, 16, 20), n_rigid=60, seed=6,
                               kBT=1e-4)
