@@ -149,6 +149,67 @@ def sedimentation(n_fluid=(32, 32, 64), d=8.0, ratio=2.5, center=None, g=2e-5,
     return _assemble(p, fluid, c[None, :], d, ratio, wp, wt, steps, "sedimentation")
 
 
+def slurry_channel(interval=0, walls=False, L=(21.0, 41.0, 10.0), dx=0.5, h_over_dx=2.0,
+                   kBT=1.0, dt=2e-3, steps=3500, seed=0, layers=3, ratio=2.7,
+                   site_volume_fraction=0.55, **over):
+    """The reverse-Poiseuille channel of Sec. 4.1 and its slurry version of
+    Sec. 4.3 at the paper's constants: box (20, 40, 10), eta = 25,
+    xi = 20 eta / 21, rho0 = 3, p0 = beta = 100, no gravity, driving
+    acceleration 1.5 along y, +y in the upper half of z and -y in the lower
+    half.  Fully periodic (walls=False) or wall-periodic (walls=True: wall
+    particles on the z faces, periodic in x and y).
+
+    interval > 0 interleaves rigid particles with the fluid lattice: every
+    interval-th site in id order (x fastest) becomes a rigid particle of
+    volume site_volume_fraction dx^3 and density ratio `ratio`, so the
+    concentration (rigid volume over box volume) is
+    site_volume_fraction / interval: 3.67 %, 5.5 % and 11 % at intervals 15,
+    10 and 5.  interval = 0 (or -1) places none.
+
+    Spacing, support and thermal energy are not stated in the paper (they
+    live in its parameter files): dx = 0.5, h = 2 dx and kBT = 1 here, the
+    fluid particle mass rho0 dx^3.  The box is 42 x 82 x 20 sites
+    (21 x 41 x 10): spheres of 1.016 dx touch only across faces of sites,
+    and with these counts no two face neighbours (periodic wraps included)
+    are both interleaved sites at intervals 5, 10 and 15 (at 40 x 80 sites
+    intervals 5 and 10 stack the spheres into sheets of overlapping
+    spheres, and such runs blow up).  Runs 7 time units in 3500 steps of
+    0.002: a sphere's Stokes drag 3 pi eta d relaxes its velocity in
+    m_s / (3 pi eta d) = 0.0046, which the step must resolve.  The
+    lubrication gap is floored at dx / 8: the explicit step resolves the
+    lubrication coefficient 6 pi eta R*^2 / gap only down to about that gap
+    at eta = 25."""
+    eta = 25.0
+    nx, ny, nz = (int(round(L[a] / dx)) for a in range(3))
+    periodic = [1, 1, 0 if walls else 1]
+    m_f = 3.0 * dx ** 3
+    p = base_params(org=[0.0, 0.0, 0.0], L=[nx * dx, ny * dx, nz * dx], periodic=periodic,
+                    dx=dx, h=h_over_dx * dx, rho0=3.0, p0=100.0, alpha=7.0, beta_eos=100.0,
+                    eta=eta, xi=20.0 * eta / 21.0, kBT=kBT, dt=dt,
+                    g=[0.0, 0.0, 0.0], f=[0.0, 1.5, 0.0], gravity_type=1, gravity_axis=2,
+                    seed=seed, mass_fluid=m_f, inertia_fluid=0.4 * m_f * (0.5 * dx) ** 2,
+                    # stiffness for spheres of about one lattice site
+                    E_dem=788.0, lub_gap_min=0.125 * dx)
+    p.update(over)
+    sites = _lattice(nx, ny, nz, dx)
+    rig = np.zeros(sites.shape[0], bool)
+    if interval and interval > 0:
+        rig[interval - 1::interval] = True
+    d = (6.0 * site_volume_fraction / math.pi) ** (1.0 / 3.0) * dx
+    if walls:
+        wp, wt = _walls((nx, ny, nz), periodic, layers, dx)
+    else:
+        wp, wt = np.zeros((0, 3)), np.zeros(0, np.uint8)
+    p_, parts, info = _assemble(p, sites[~rig], sites[rig], d, ratio, wp, wt, steps,
+                                "slurry_channel")
+    vol = p["L"][0] * p["L"][1] * p["L"][2]
+    nr = int(rig.sum())
+    info.update(interval=int(interval or 0), walls=bool(walls), rigid_d=d,
+                concentration=nr * math.pi * d ** 3 / 6.0 / vol, D=0.5 * p["L"][2],
+                drive=1.5)
+    return p_, parts, info
+
+
 def _rsa(n, lo, hi, d, rng, max_tries=500_000):
     """Random sequential addition of n non-overlapping spheres of diameter d
     with centres uniform in the box [lo, hi]."""
