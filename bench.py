@@ -137,6 +137,41 @@ def viscometer_leg(k_steps, n_cells=256, run_steps=5000, graph_steps=10, tune=Tr
     return res
 
 
+def scale_leg(steps, cell_factor, warmup=2):
+    """The scale run: a fully periodic SDPD lattice of 256 x 256 x 128 =
+    8,388,608 particles (the reverse-Poiseuille constants, kT = 1e-3, so the
+    thermal pair forces are on), timed over `steps` eager steps after
+    `warmup`; the pair kernel timed by HIP events as in the main figure."""
+    import torch
+
+    from paper_2002_03120_amd import sdpdem as S
+    from paper_2002_03120_amd import workloads as W
+
+    p, parts, info = W.periodic_scale()
+    g = S.System(dict(p, cell_factor=cell_factor), parts)
+    g.step(warmup)
+    g.set_profiling("fluid_forces")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    k_ms, k_launches = g.kernel_time()
+    nnz = int(g.info()[9])
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+    n = int(info["n"])
+    return {
+        "particles": n, "steps": steps, "warmup": warmup, "kT": p["kBT"],
+        "cell_factor": cell_factor,
+        "ms_per_step": round(wall / steps * 1e3, 4),
+        "particle_steps_per_s": round(n * steps / wall, 1),
+        "pair_interactions_per_s": round(2 * nnz * steps / wall, 1),
+        "pair_kernel_ms": round(k_ms / max(k_launches, 1), 4),
+    }
+
+
 def graph_ms_per_step(p, parts, steps, graph_steps=10):
     """The same workload with its step loop replayed from captured graphs
     (same results bit for bit); reported beside the eager figure."""
@@ -174,6 +209,8 @@ def main():
                          "pick for the dam break, 0 runs the tuner before the timed region")
     ap.add_argument("--graph-steps", type=int, default=10,
                     help="steps per captured graph for the graph-replay figure (0: skip)")
+    ap.add_argument("--scale-steps", type=int, default=20,
+                    help="timed steps of the 8,388,608-particle periodic scale run (0: skip)")
     ap.add_argument("--viscometer-steps", type=int, default=20,
                     help="timed steps per configuration of the batched-viscometer leg (0: skip)")
     args = ap.parse_args()
@@ -288,6 +325,8 @@ def main():
     if args.graph_steps > 0:
         result["ms_per_step_graph"] = round(graph_ms_per_step(pg, parts, args.steps,
                                                               args.graph_steps), 4)
+    if args.scale_steps > 0:
+        result["scale"] = scale_leg(args.scale_steps, args.cell_factor)
     if args.viscometer_steps > 0:
         result["viscometer"] = viscometer_leg(args.viscometer_steps)
 

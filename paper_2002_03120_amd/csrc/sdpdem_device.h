@@ -302,6 +302,78 @@ __device__ __forceinline__ void for_stencil(const Geo& B, const Grid& G, int off
   }
 }
 
+// The rows of for_stencil<true> for one thread, with the row geometry in
+// single precision on coordinates relative to the point's own cell (so
+// their magnitude stays below a few cells): the z distance is formed once
+// per z row, rows are walked z-major without an integer division, and the
+// x reach takes one FP32 square root.  Every bound carries a relative
+// margin of 1e-5 of a cell, far above the FP32 rounding of these small
+// numbers, so the runs may hold a few extra cells but never miss one; the
+// distance test in FP64 decides.  Sheared boxes, stencils that wrap onto
+// themselves and points outside their cell take the generic rows.
+template <class Fn>
+__device__ __forceinline__ void for_stencil_pruned(const Geo& B, const Grid& G, int off, double px,
+                                                   double py, double pz, double R,
+                                                   const int cc[3], int k, Fn&& fn) {
+  const double fxd = px - (G.lo[0] + (double)cc[0] * G.cs[0]);
+  const double fyd = py - (G.lo[1] + (double)cc[1] * G.cs[1]);
+  const double fzd = pz - (G.lo[2] + (double)cc[2] * G.cs[2]);
+  const int nx = G.nc[0], ny = G.nc[1], nz = G.nc[2];
+  const bool plain = !B.le && !(G.per[2] && 2 * k + 1 > nz) && !(G.per[1] && 2 * k + 1 > ny) &&
+                     fxd > -G.cs[0] && fxd < 2.0 * G.cs[0] && fyd > -G.cs[1] &&
+                     fyd < 2.0 * G.cs[1] && fzd > -G.cs[2] && fzd < 2.0 * G.cs[2];
+  if (!plain) {
+    for_stencil<true>(B, G, off, px, py, pz, R, cc, k, fn);
+    return;
+  }
+  const float fx = (float)fxd, fy = (float)fyd, fz = (float)fzd;
+  const float csx = (float)G.cs[0], csy = (float)G.cs[1], csz = (float)G.cs[2];
+  const float icx = (float)G.inv_cs[0];
+  const float R2 = (float)(R * R) * (1.0f + 1e-5f);
+  const float mx = 1e-5f * csx;
+  for (int dz = -k; dz <= k; ++dz) {
+    int z = cc[2] + dz;
+    if (z < 0 || z >= nz) {
+      if (!G.per[2]) continue;
+      z += z < 0 ? nz : -nz;
+    }
+    const float sz = fmaxf(0.0f, fmaxf((float)dz * csz - fz, fz - (float)(dz + 1) * csz));
+    const float z2 = sz * sz;
+    if (z2 >= R2) continue;
+    for (int dy = -k; dy <= k; ++dy) {
+      int y = cc[1] + dy;
+      if (y < 0 || y >= ny) {
+        if (!G.per[1]) continue;
+        y += y < 0 ? ny : -ny;
+      }
+      const float sy = fmaxf(0.0f, fmaxf((float)dy * csy - fy, fy - (float)(dy + 1) * csy));
+      const float d2 = z2 + sy * sy;
+      if (d2 >= R2) continue;
+      const float rx = sqrtf(R2 - d2) * (1.0f + 1e-5f) + mx;
+      int xa = cc[0] + (int)floorf((fx - rx) * icx);
+      int xb = cc[0] + (int)floorf((fx + rx) * icx);
+      xa = max(xa, cc[0] - k);
+      xb = min(xb, cc[0] + k);
+      if (xb < xa) continue;
+      const int rowkey = off + (z * ny + y) * nx;
+      if (!G.per[0]) {
+        const int lo = max(xa, 0), hi = min(xb, nx - 1);
+        if (lo <= hi) fn(rowkey + lo, rowkey + hi + 1);
+      } else if (xb - xa + 1 >= nx) {
+        fn(rowkey, rowkey + nx);
+      } else {
+        const int lo = ((xa % nx) + nx) % nx, hi = lo + (xb - xa);  // at most one wrap
+        if (hi >= nx) {
+          fn(rowkey + lo, rowkey + nx);
+          fn(rowkey, rowkey + hi - nx + 1);
+        } else {
+          fn(rowkey + lo, rowkey + hi + 1);
+        }
+      }
+    }
+  }
+}
+
 // Lucy kernel with support H (Eq. kernel), double precision
 __device__ __forceinline__ double lucy_w(double r, double H) {
   if (r >= H) return 0.0;

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(BS) void k_build_density(Dev d) {
   if (kr == 1)
     for_stencil<false>(G, gr, coff, pi.x, pi.y, pi.z, d.h, cc, 1, run);
   else
-    for_stencil<true>(G, gr, coff, pi.x, pi.y, pi.z, d.h, cc, kr, run);
+    for_stencil_pruned(G, gr, coff, pi.x, pi.y, pi.z, d.h, cc, kr, run);
   if (cnt > d.maxn) {
     atomicOr(d.status, ST_NBR_OVERFLOW);
     cnt = d.maxn;
