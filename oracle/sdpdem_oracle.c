@@ -26,6 +26,9 @@
  *  R5  Pressure filtering = Shepard (W-weighted) mean, self included.
  *  R6  dW^S = (dW + dW^T)/2 - tr(dW)/3 * 1 (Eq. reldWij is garbled), the
  *      trace term of Eq. FijT multiplies the identity; dW = sqrt(dt) zeta.
+ *      Only sym(dW) enters, so its six independent entries are drawn
+ *      directly: diagonal N(0,1), off-diagonal N(0,1/2) (the law of
+ *      (zeta_ab + zeta_ba)/2 for independent standard zeta).
  *  R7  Noise comes from Philox4x32-10 keyed by the seed with counter
  *      (min id, max id, step, block); one draw per pair per step, used by
  *      both velocity-Verlet passes, so the per-step variance is sigma^2 dt.
@@ -178,30 +181,29 @@ void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2],
   out[3] = x3;
 }
 
-/* Nine standard normals for the unordered pair {a, b} at a step (R7).
- * Uniforms u = ((x >> 8) + 1) 2^-24 in (0, 1]; Box-Muller (1958) on
- * consecutive pairs (u0,u1) .. (u8,u9); zeta_ab = z[3a + b].             */
+/* Six standard normals for the unordered pair {a, b} at a step (R7): the
+ * independent entries of the symmetric part of dW (R6).  Uniforms
+ * u = ((x >> 8) + 1) 2^-24 in (0, 1] from two Philox blocks; Box-Muller
+ * (1958) on consecutive pairs (u0,u1), (u2,u3), (u4,u5).                 */
 void oracle_pair_normals(uint64_t seed, int64_t id_a, int64_t id_b,
-                         int64_t step, double z[9]) {
+                         int64_t step, double z[6]) {
   int64_t lo = id_a < id_b ? id_a : id_b;
   int64_t hi = id_a < id_b ? id_b : id_a;
   uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
-  double u[12];
-  for (uint32_t blk = 0; blk < 3; ++blk) {
+  double u[8];
+  for (uint32_t blk = 0; blk < 2; ++blk) {
     uint32_t ctr[4] = {(uint32_t)lo, (uint32_t)hi, (uint32_t)step, blk};
     uint32_t x[4];
     oracle_philox4x32_10(ctr, key, x);
     for (int k = 0; k < 4; ++k)
       u[4 * blk + k] = ((double)(x[k] >> 8) + 1.0) * (1.0 / 16777216.0);
   }
-  double zz[10];
-  for (int m = 0; m < 5; ++m) {
+  for (int m = 0; m < 3; ++m) {
     double rad = sqrt(-2.0 * log(u[2 * m]));
     double ang = 2.0 * M_PI * u[2 * m + 1];
-    zz[2 * m] = rad * cos(ang);
-    zz[2 * m + 1] = rad * sin(ang);
+    z[2 * m] = rad * cos(ang);
+    z[2 * m + 1] = rad * sin(ang);
   }
-  for (int k = 0; k < 9; ++k) z[k] = zz[k];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -241,13 +243,14 @@ void oracle_pair_force(const oracle_params* P, const double rij[3],
   if (P->kBT > 0.0 && P->coeff_t != 0.0) {
     double sa = 2.0 * sqrt(P->kBT * ga);
     double sb = 2.0 * sqrt(P->kBT * gb);
-    double z[9];
+    /* sym(dW)/sqrt(dt): diagonal entries z0..z2 ~ N(0,1), off-diagonal
+     * entries (01, 02, 12) = z3..z5 / sqrt(2) ~ N(0,1/2), the law of
+     * (zeta_ab + zeta_ba)/2 for independent standard zeta (R6)          */
+    double z[6];
     oracle_pair_normals(P->seed, idi, idj, step, z);
-    double tr3 = (z[0] + z[4] + z[8]) / 3.0;
-    double S[3][3];
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b)
-        S[a][b] = 0.5 * (z[3 * a + b] + z[3 * b + a]) - (a == b ? tr3 : 0.0);
+    double tr3 = (z[0] + z[1] + z[2]) / 3.0;
+    double h01 = z[3] / sqrt(2.0), h02 = z[4] / sqrt(2.0), h12 = z[5] / sqrt(2.0);
+    double S[3][3] = {{z[0] - tr3, h01, h02}, {h01, z[1] - tr3, h12}, {h02, h12, z[2] - tr3}};
     double sq = sqrt(P->dt);
     for (int a = 0; a < 3; ++a) {
       double se = S[a][0] * e[0] + S[a][1] * e[1] + S[a][2] * e[2];

@@ -432,14 +432,15 @@ __device__ __forceinline__ float u01(uint32_t x) {
   return (float)((x >> 8) + 1u) * 5.9604644775390625e-8f;  // (0, 1], exact
 }
 
-// nine standard normals of the unordered pair {a, b} at a step; the tenth
-// Box-Muller output is not used
+// six standard normals of the unordered pair {a, b} at a step (two Philox
+// blocks, Box-Muller on three pairs of uniforms): the independent entries
+// of the symmetric part of the Wiener matrix of Eq. FijT
 __device__ __forceinline__ void pair_normals(uint32_t a, uint32_t b, uint32_t step, uint32_t k0,
-                                             uint32_t k1, float z[9]) {
+                                             uint32_t k1, float z[6]) {
   uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
-  float u[12];
+  float u[8];
 #pragma unroll
-  for (uint32_t blk = 0; blk < 3; ++blk) {
+  for (uint32_t blk = 0; blk < 2; ++blk) {
     uint32_t c0 = lo, c1 = hi, c2 = step, c3 = blk;
     philox10(c0, c1, c2, c3, k0, k1);
     u[4 * blk + 0] = u01(c0);
@@ -448,12 +449,12 @@ __device__ __forceinline__ void pair_normals(uint32_t a, uint32_t b, uint32_t st
     u[4 * blk + 3] = u01(c3);
   }
 #pragma unroll
-  for (int m = 0; m < 5; ++m) {
+  for (int m = 0; m < 3; ++m) {
     float rad = sqrtf(-2.0f * logf(u[2 * m]));
     float sn, cs;
     sincospif(2.0f * u[2 * m + 1], &sn, &cs);
-    if (2 * m < 9) z[2 * m] = rad * cs;
-    if (2 * m + 1 < 9) z[2 * m + 1] = rad * sn;
+    z[2 * m] = rad * cs;
+    z[2 * m + 1] = rad * sn;
   }
 }
 

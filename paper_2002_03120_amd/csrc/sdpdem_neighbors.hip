@@ -220,17 +220,19 @@ __global__ __launch_bounds__(BS) void k_fluid_forces(Dev d) {
       ty += rry;
       tz += rrz;
       if (noise) {
-        // thermal force, Eq. FijT with dW^S = sym(dW) - tr(dW)/3
-        float z[9];
+        // thermal force, Eq. FijT with dW^S = sym(dW) - tr(dW)/3: sym(dW)
+        // has diagonal entries z0..z2 ~ N(0,1) and off-diagonal entries
+        // z3..z5 / sqrt 2 ~ N(0,1/2), the law of (zeta_ab + zeta_ba)/2
+        float z[6];
         pair_normals(gi, (uint32_t)rj.gid - ib, step, key0, key1, z);
         const float sa = 2.0f * sqrtf(kT * d.CAf * fdd);
         const float sb = 2.0f * sqrtf(kT * d.CBf * fdd);
-        const float tr3 = (z[0] + z[4] + z[8]) * (1.0f / 3.0f);
-        const float s01 = 0.5f * (z[1] + z[3]), s02 = 0.5f * (z[2] + z[6]),
-                    s12 = 0.5f * (z[5] + z[7]);
+        const float tr3 = (z[0] + z[1] + z[2]) * (1.0f / 3.0f);
+        const float s01 = z[3] * 0.70710678118654752f, s02 = z[4] * 0.70710678118654752f,
+                    s12 = z[5] * 0.70710678118654752f;
         const float se0 = (z[0] - tr3) * ex + s01 * ey + s02 * ez;
-        const float se1 = s01 * ex + (z[4] - tr3) * ey + s12 * ez;
-        const float se2 = s02 * ex + s12 * ey + (z[8] - tr3) * ez;
+        const float se1 = s01 * ex + (z[1] - tr3) * ey + s12 * ez;
+        const float se2 = s02 * ex + s12 * ey + (z[2] - tr3) * ez;
         const float ca = d.cT * d.inv_sqrt_dtf * sa;
         const float cb = d.cT * d.inv_sqrt_dtf * sb * tr3;
         fx += ca * se0 + cb * ex;
