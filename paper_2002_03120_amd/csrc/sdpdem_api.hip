@@ -205,6 +205,7 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
   int* nbr_cnt = b.take<int>(np);
   double* rho = b.take<double>(np);
   double* p = b.take<double>(np);
+  D4* xp = b.take<D4>(np);
   float* ps = b.take<float>(np);
   PR* prec = b.take<PR>(np);
   float* fout = b.take<float>(13 * np);
@@ -278,6 +279,7 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
     d.nbr_cnt = nbr_cnt;
     d.rho = rho;
     d.p = p;
+    d.xp = xp;
     d.ps = ps;
     d.prec = prec;
     d.fout = fout;

@@ -192,14 +192,14 @@ __device__ __forceinline__ double slab_dist(double x, double lo, double cs) {
   return fmax(0.0, fmax(lo - x, x - (lo + cs)));
 }
 
+// the row at unwrapped z and y cell indices (zu, yu)
 template <bool PRUNE>
-__device__ __forceinline__ void stencil_row(const Geo& B, const Grid& G, int off, double px,
-                                            double py, double pz, double R, const int cc[3],
-                                            int k, const StencilShape& sh, int r, int& a0,
-                                            int& a1, int& b0, int& b1) {
+__device__ __forceinline__ void stencil_row_zy(const Geo& B, const Grid& G, int off, double px,
+                                               double py, double pz, double R, const int cc[3],
+                                               int k, const StencilShape& sh, int zu, int yu,
+                                               int& a0, int& a1, int& b0, int& b1) {
   a0 = a1 = b0 = b1 = 0;
   const int nx = G.nc[0], ny = G.nc[1], nz = G.nc[2];
-  const int zu = sh.zlo + r / sh.yn, yu = sh.ylo + r % sh.yn;  // unwrapped rows
   int z = zu, y = yu, wz = 0;
   if (z < 0) {
     if (!G.per[2]) return;
@@ -285,6 +285,16 @@ __device__ __forceinline__ void stencil_row(const Geo& B, const Grid& G, int off
   }
 }
 
+// row r of the stencil, z-major
+template <bool PRUNE>
+__device__ __forceinline__ void stencil_row(const Geo& B, const Grid& G, int off, double px,
+                                            double py, double pz, double R, const int cc[3],
+                                            int k, const StencilShape& sh, int r, int& a0,
+                                            int& a1, int& b0, int& b1) {
+  stencil_row_zy<PRUNE>(B, G, off, px, py, pz, R, cc, k, sh, sh.zlo + r / sh.yn,
+                        sh.ylo + r % sh.yn, a0, a1, b0, b1);
+}
+
 // the same cells as fn(first_key, end_key) over the runs, in row order;
 // PRUNE = false keeps the whole 2k+1 cells of every row (one thread per
 // particle: lanes of a cell then walk the same runs in step)
@@ -293,13 +303,14 @@ __device__ __forceinline__ void for_stencil(const Geo& B, const Grid& G, int off
                                             double py, double pz, double R, const int cc[3],
                                             int k, Fn&& fn) {
   const StencilShape sh = stencil_shape(G, cc, k);
-  const int nrows = sh.zn * sh.yn;
-  for (int r = 0; r < nrows; ++r) {
-    int a0, a1, b0, b1;
-    stencil_row<PRUNE>(B, G, off, px, py, pz, R, cc, k, sh, r, a0, a1, b0, b1);
-    if (a1 > a0) fn(a0, a1);
-    if (b1 > b0) fn(b0, b1);
-  }
+  for (int zi = 0; zi < sh.zn; ++zi)
+    for (int yi = 0; yi < sh.yn; ++yi) {
+      int a0, a1, b0, b1;
+      stencil_row_zy<PRUNE>(B, G, off, px, py, pz, R, cc, k, sh, sh.zlo + zi, sh.ylo + yi, a0,
+                            a1, b0, b1);
+      if (a1 > a0) fn(a0, a1);
+      if (b1 > b0) fn(b0, b1);
+    }
 }
 
 // The rows of for_stencil<true> for one thread, with the row geometry in
@@ -372,14 +383,6 @@ __device__ __forceinline__ void for_stencil_pruned(const Geo& B, const Grid& G, 
       }
     }
   }
-}
-
-// Lucy kernel with support H (Eq. kernel), double precision
-__device__ __forceinline__ double lucy_w(double r, double H) {
-  if (r >= H) return 0.0;
-  double q = r / H;
-  double om = 1.0 - q;
-  return 105.0 / (16.0 * PI * H * H * H) * (1.0 + 3.0 * q) * om * om * om;
 }
 
 // Block-wide exclusive scan of one int per thread (wave64 shuffles + LDS).

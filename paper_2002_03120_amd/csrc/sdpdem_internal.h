@@ -137,6 +137,7 @@ struct Dev {
   int* nbr_cnt;
   double* rho;
   double* p;
+  D4* xp;   // x, y, z, p of the last build: the pressure filter's neighbour record
   float* ps;
   PR* prec;  // pair records, sorted order
   float* fout;  // 13 planes of npad: F_sdpd(3) N_sdpd(3) F_cd(3) F_rxn(3) W_zx
@@ -161,7 +162,7 @@ struct Dev {
   D4* rpos_c;
   D4* rvel_c;
   D4* rom_c;
-  D4* rdg_c;       // F^DG / Omega of the sphere, w = 1 if it couples
+  D4* rdg_c;       // F^DG / Omega x Lucy normalisation of H_s; w = 1/H_s (0: no coupling)
   int* rslot_pos;  // slot -> t
   // fluid particles coupled to a sphere in the current pass carry the stamp
   int* cstamp;

@@ -24,6 +24,15 @@ __global__ void k_fill_i32(int* a, int v, size_t count) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) a[i] = v;
 }
+// the same for a 16-byte aligned array: four ints per thread
+__global__ void k_fill_i32x4(int* a, int v, size_t count) {
+  size_t i = 4 * ((size_t)blockIdx.x * blockDim.x + threadIdx.x);
+  if (i + 4 <= count) {
+    *reinterpret_cast<int4*>(a + i) = make_int4(v, v, v, v);
+  } else {
+    for (; i < count; ++i) a[i] = v;
+  }
+}
 __global__ void k_fill_f64(double* a, double v, size_t count) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) a[i] = v;
@@ -31,7 +40,12 @@ __global__ void k_fill_f64(double* a, double v, size_t count) {
 
 void launch_fill_i32(int* a, int v, size_t count, hipStream_t st) {
   if (!count) return;
-  k_fill_i32<<<(unsigned)((count + BS - 1) / BS), BS, 0, st>>>(a, v, count);
+  if (((uintptr_t)a & 15) == 0) {
+    const size_t threads = (count + 3) / 4;
+    k_fill_i32x4<<<(unsigned)((threads + BS - 1) / BS), BS, 0, st>>>(a, v, count);
+  } else {
+    k_fill_i32<<<(unsigned)((count + BS - 1) / BS), BS, 0, st>>>(a, v, count);
+  }
 }
 void launch_fill_f64(double* a, double v, size_t count, hipStream_t st) {
   if (!count) return;
@@ -129,30 +143,56 @@ void launch_step_end(const Dev& d, hipStream_t st) {
 static constexpr int SCAN_ITEMS = 8;
 static constexpr int SCAN_TILE = BS * SCAN_ITEMS;
 
+// the SCAN_ITEMS consecutive counts of one thread: two 16-byte loads when
+// all are in range (the arrays are 256-byte aligned), else one by one
+static_assert(SCAN_ITEMS == 8, "two 16-byte loads and stores per thread");
+__device__ __forceinline__ void load_items(const int* in, int m, int base, int v[SCAN_ITEMS]) {
+  if (base + SCAN_ITEMS <= m) {
+    const int4 a = *reinterpret_cast<const int4*>(in + base);
+    const int4 b = *reinterpret_cast<const int4*>(in + base + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) v[k] = base + k < m ? in[base + k] : 0;
+  }
+}
+
 __global__ __launch_bounds__(BS) void k_scan_reduce(const int* in, int m, int* block_sums) {
   __shared__ int lds[BS / 64 + 1];
   int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+  int v[SCAN_ITEMS];
+  load_items(in, m, base, v);
   int s = 0;
 #pragma unroll
-  for (int k = 0; k < SCAN_ITEMS; ++k) {
-    int idx = base + k;
-    if (idx < m) s += in[idx];
-  }
+  for (int k = 0; k < SCAN_ITEMS; ++k) s += v[k];
   int tot;
   block_exclusive_scan(s, lds, &tot);
   if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
 }
 
-// exclusive scan of the block sums in one block, chunk by chunk
+// exclusive scan of the block sums in one block, chunks of 16 sums per
+// thread (one chunk covers 4096 sums, a grid of 8.4 M cells)
 __global__ __launch_bounds__(BS) void k_scan_blocksums(int* block_sums, int nb) {
   __shared__ int lds[BS / 64 + 1];
+  constexpr int PER = 16;
   int carry = 0;
-  for (int base = 0; base < nb; base += BS) {
-    int idx = base + (int)threadIdx.x;
-    int v = idx < nb ? block_sums[idx] : 0;
+  for (int base = 0; base < nb; base += BS * PER) {
+    const int first = base + (int)threadIdx.x * PER;
+    int v[PER];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      v[k] = first + k < nb ? block_sums[first + k] : 0;
+      s += v[k];
+    }
     int tot;
-    int ex = block_exclusive_scan(v, lds, &tot);
-    if (idx < nb) block_sums[idx] = ex + carry;
+    int ex = block_exclusive_scan(s, lds, &tot) + carry;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      if (first + k < nb) block_sums[first + k] = ex;
+      ex += v[k];
+    }
     carry += tot;
   }
   if (threadIdx.x == 0) block_sums[nb] = carry;
@@ -163,23 +203,31 @@ __global__ __launch_bounds__(BS) void k_scan_apply(const int* in, int m, const i
   __shared__ int lds[BS / 64 + 1];
   int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
   int v[SCAN_ITEMS];
+  load_items(in, m, base, v);
   int s = 0;
 #pragma unroll
-  for (int k = 0; k < SCAN_ITEMS; ++k) {
-    int idx = base + k;
-    v[k] = idx < m ? in[idx] : 0;
-    s += v[k];
-  }
+  for (int k = 0; k < SCAN_ITEMS; ++k) s += v[k];
   int tot;
   int ex = block_exclusive_scan(s, lds, &tot) + block_sums[blockIdx.x];
+  int e[SCAN_ITEMS];
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
-    int idx = base + k;
-    if (idx < m) {
-      start[idx] = ex;
-      cursor[idx] = ex;
-    }
+    e[k] = ex;
     ex += v[k];
+  }
+  if (base + SCAN_ITEMS <= m) {
+    const int4 a = make_int4(e[0], e[1], e[2], e[3]), b = make_int4(e[4], e[5], e[6], e[7]);
+    *reinterpret_cast<int4*>(start + base) = a;
+    *reinterpret_cast<int4*>(start + base + 4) = b;
+    *reinterpret_cast<int4*>(cursor + base) = a;
+    *reinterpret_cast<int4*>(cursor + base + 4) = b;
+  } else {
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k)
+      if (base + k < m) {
+        start[base + k] = e[k];
+        cursor[base + k] = e[k];
+      }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) start[m] = block_sums[nb];
 }
@@ -323,6 +371,7 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
   const int coff = B.cell_off;
   const D4 ps = d.pos[si];
   const double R = ps.w, H = R + d.h, H2 = H * H;
+  const double invH = 1.0 / H, wnorm = 105.0 / (16.0 * PI * H * H * H);  // Eq. kernel
   int oob = 0;
   const int cc[3] = {cell_coord(ps.x, gr, 0, &oob), cell_coord(ps.y, gr, 1, &oob),
                      cell_coord(ps.z, gr, 2, &oob)};
@@ -389,7 +438,8 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
         ++nrig;
         continue;
       }
-      double w = lucy_w(sqrt(r2), H);
+      const double qh = sqrt(r2) * invH, omq = 1.0 - qh;
+      const double w = wnorm * (1.0 + 3.0 * qh) * omq * omq * omq;
       D4 vj = d.vel[j];
       om += w;
       v0 += w * (vj.x + (double)kz * G.le_jump);  // image velocity (Lees-Edwards)
@@ -443,12 +493,13 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
   // virial of the coupling: lever (sum_j w_sj r_sj / Omega_s)_z times the
   // x force; the contacts add theirs later in the pass
   if (d.stress) d.wzx_r[s] = om > 0.0 ? (l2 / om) * (dg[0] + pg[0]) : 0.0;
-  // F^DG / Omega beside the sphere's cell-ordered record, for the reaction
+  // F^DG / Omega times the kernel's normalisation beside the sphere's
+  // cell-ordered record, with 1/H_s (0: the sphere couples to nothing)
   D4 rc;
-  rc.x = om > 0.0 ? dg[0] / om : 0.0;
-  rc.y = om > 0.0 ? dg[1] / om : 0.0;
-  rc.z = om > 0.0 ? dg[2] / om : 0.0;
-  rc.w = om > 0.0 ? 1.0 : 0.0;
+  rc.x = om > 0.0 ? dg[0] / om * wnorm : 0.0;
+  rc.y = om > 0.0 ? dg[1] / om * wnorm : 0.0;
+  rc.z = om > 0.0 ? dg[2] / om * wnorm : 0.0;
+  rc.w = om > 0.0 ? invH : 0.0;
   d.rdg_c[wave] = rc;
 }
 
@@ -486,7 +537,9 @@ __global__ __launch_bounds__(BS) void k_fpi_reaction(Dev d) {
       min_img_box(G, ex, ey, ez);
       double r2 = r2_exact(ex, ey, ez);
       if (!(r2 < H * H)) continue;
-      double w = lucy_w(sqrt(r2), H);
+      // Lucy weight of support H without its normalisation (folded into g)
+      const double q = sqrt(r2) * g.w, omq = 1.0 - q;
+      const double w = (1.0 + 3.0 * q) * omq * omq * omq;
       a0 -= g.x * w;
       a1 -= g.y * w;
       a2 -= g.z * w;

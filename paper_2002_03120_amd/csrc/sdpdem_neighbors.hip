@@ -20,13 +20,14 @@ __global__ __launch_bounds__(BS) void k_build_density(Dev d) {
   const BoxD& B = d.boxes[b];
   if (i >= B.first + B.count) return;
   uint8_t ti = d.type[i];
+  const D4 pi = d.pos[i];
   if (ti == T_OUTER) {
     d.nbr_cnt[i] = 0;
     d.rho[i] = d.rho0;
     d.p[i] = d.p_ref;
+    d.xp[i] = D4{pi.x, pi.y, pi.z, d.p_ref};
     return;
   }
-  const D4 pi = d.pos[i];
   const Geo G = geo_of(B);
   const Grid gr = B.g;
   const int coff = B.cell_off;
@@ -72,6 +73,7 @@ __global__ __launch_bounds__(BS) void k_build_density(Dev d) {
   if (d.clamp && p < 0.0) p = 0.0;  // free-surface correction (Sec. 2.5)
   d.rho[i] = rho;
   d.p[i] = p;
+  d.xp[i] = D4{pi.x, pi.y, pi.z, p};
 }
 
 void launch_build_density(const Dev& d, hipStream_t st) {
@@ -89,8 +91,8 @@ __global__ __launch_bounds__(BS) void k_smooth(Dev d) {
   const BoxD& B = d.boxes[b];
   if (i >= B.first + B.count) return;
   const uint8_t ti = d.type[i];
-  const double pi = d.p[i];
-  const D4 x = d.pos[i];
+  const D4 x = d.xp[i];  // position and pressure
+  const double pi = x.w;
   const Geo G = geo_of(B);
   double ps = pi;
   if (d.smooth && ti != T_OUTER) {
@@ -101,13 +103,13 @@ __global__ __launch_bounds__(BS) void k_smooth(Dev d) {
     const double inv_h = d.inv_h;
     for (int k = 0; k < cnt; ++k) {
       const int j = nb[(size_t)k * npad];
-      const D4 xj = d.pos[j];
+      const D4 xj = d.xp[j];  // one 32-byte record: position and pressure
       double ex = x.x - xj.x, ey = x.y - xj.y, ez = x.z - xj.z;
       min_img_box(G, ex, ey, ez);
       const double q = sqrt_nr(r2_exact(ex, ey, ez)) * inv_h;
       const double om = fmax(1.0 - q, 0.0);
       const double w = d.w_norm * (1.0 + 3.0 * q) * om * om * om;
-      num += d.p[j] * w;
+      num += xj.w * w;
       den += w;
     }
     ps = num / den;
