@@ -237,6 +237,8 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
   D4* rdg_c = b.take<D4>(nr);
   int* rslot_pos = b.take<int>(nr);
   int* cstamp = b.take<int>(np);
+  int* rxn_cnt = b.take<int>(nr ? np : 1);
+  int2* rxn_slot = b.take<int2>(nr ? (size_t)RXN_CAP * np : 1);
   int64_t* dstep = b.take<int64_t>(1);
   int* dstamp = b.take<int>(1);
   int *ctc0 = b.take<int>(nr), *ctc1 = b.take<int>(nr);
@@ -312,6 +314,8 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
     d.rdg_c = rdg_c;
     d.rslot_pos = rslot_pos;
     d.cstamp = cstamp;
+    d.rxn_cnt = rxn_cnt;
+    d.rxn_slot = rxn_slot;
     d.dstep = dstep;
     d.dstamp = dstamp;
   }
@@ -615,6 +619,7 @@ void run_pass(sdpdem_system* s, int velver, int commit, bool integrate, hipStrea
     }
     {
       Prof pr(s, SDPDEM_K_FPI_ACTION, st);
+      launch_fill_i32(d.rxn_cnt, 0, (size_t)d.npad, st);
       launch_fpi_action(d, st);
     }
     {

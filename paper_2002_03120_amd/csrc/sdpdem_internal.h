@@ -11,6 +11,9 @@
 namespace sdpdem {
 
 static constexpr int BS = 256;  // threads per block of the particle kernels
+// coupling slots per fluid particle: the spheres whose support holds it,
+// each with its kernel weight, filled by the action for the reaction
+static constexpr int RXN_CAP = 16;
 
 enum : uint8_t { T_FLUID = 0, T_RIGID = 1, T_INNER = 2, T_OUTER = 3 };
 
@@ -166,6 +169,8 @@ struct Dev {
   int* rslot_pos;  // slot -> t
   // fluid particles coupled to a sphere in the current pass carry the stamp
   int* cstamp;
+  int* rxn_cnt;    // spheres that coupled to the particle in this pass
+  int2* rxn_slot;  // [RXN_CAP][npad]: (cell-ordered sphere record, FP32 Lucy polynomial)
   // device-resident counters (so that a captured graph replays correctly):
   // the step number and the stamp of the current pass
   int64_t* dstep;

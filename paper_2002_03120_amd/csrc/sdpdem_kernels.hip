@@ -13,6 +13,8 @@
 // separation vectors taken as FP64 differences rounded once.
 #include <cmath>
 
+#include <climits>
+
 #include "sdpdem_device.h"
 
 namespace sdpdem {
@@ -439,7 +441,12 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
         continue;
       }
       const double qh = sqrt(r2) * invH, omq = 1.0 - qh;
-      const double w = wnorm * (1.0 + 3.0 * qh) * omq * omq * omq;
+      const double pw = (1.0 + 3.0 * qh) * omq * omq * omq;
+      const double w = wnorm * pw;
+      // hand the pair to the reaction: one slot of j (the arrival order
+      // does not matter, the reaction sums its slots by sphere record)
+      const int slot = atomicAdd(&d.rxn_cnt[j], 1);
+      if (slot < RXN_CAP) d.rxn_slot[(size_t)slot * np + j] = make_int2(wave, __float_as_int((float)pw));
       D4 vj = d.vel[j];
       om += w;
       v0 += w * (vj.x + (double)kz * G.le_jump);  // image velocity (Lees-Edwards)
@@ -518,34 +525,65 @@ __global__ __launch_bounds__(BS) void k_fpi_reaction(Dev d) {
   const BoxD& B = d.boxes[b];
   if (i >= B.first + B.count) return;
   if (d.cstamp[i] != d.dstamp[0] || d.type[i] != T_FLUID) return;
-  D4 pi = d.pos[i];
-  const Geo G = geo_of(B);
-  const Grid gr = B.rg;
-  const int coff = B.rcell_off;
-  int oob = 0;
-  int cc[3] = {cell_coord(pi.x, gr, 0, &oob), cell_coord(pi.y, gr, 1, &oob),
-               cell_coord(pi.z, gr, 2, &oob)};
-  double a0 = 0, a1 = 0, a2 = 0;
-  for_stencil<false>(G, gr, coff, pi.x, pi.y, pi.z, B.couple_R, cc, 1, [&](int cb, int ce) {
-    int tb = d.rstart[cb], te = d.rstart[ce];
-    for (int t = tb; t < te; ++t) {
-      D4 g = d.rdg_c[t];
-      if (g.w == 0.0) continue;
-      D4 ps = d.rpos_c[t];
-      double H = ps.w + d.h;
-      double ex = ps.x - pi.x, ey = ps.y - pi.y, ez = ps.z - pi.z;
-      min_img_box(G, ex, ey, ez);
-      double r2 = r2_exact(ex, ey, ez);
-      if (!(r2 < H * H)) continue;
-      // Lucy weight of support H without its normalisation (folded into g)
-      const double q = sqrt(r2) * g.w, omq = 1.0 - q;
-      const double w = (1.0 + 3.0 * q) * omq * omq * omq;
-      a0 -= g.x * w;
-      a1 -= g.y * w;
-      a2 -= g.z * w;
-    }
-  });
   const size_t np = (size_t)d.npad;
+  const int c = d.rxn_cnt[i];
+  double a0 = 0, a1 = 0, a2 = 0;
+  if (c <= RXN_CAP) {
+    // the slots the action left, summed in ascending sphere-record order
+    // (a fixed order whatever order the slots were filled in)
+    int ts[RXN_CAP];
+    float ws[RXN_CAP];
+#pragma unroll
+    for (int k = 0; k < RXN_CAP; ++k) {
+      const int2 sl = k < c ? d.rxn_slot[(size_t)k * np + i] : make_int2(INT_MAX, 0);
+      ts[k] = sl.x;
+      ws[k] = __int_as_float(sl.y);
+    }
+    int last = -1;
+    for (int m = 0; m < c; ++m) {
+      int best = INT_MAX;
+      float bw = 0.0f;
+#pragma unroll
+      for (int k = 0; k < RXN_CAP; ++k)
+        if (ts[k] > last && ts[k] < best) {
+          best = ts[k];
+          bw = ws[k];
+        }
+      last = best;
+      const D4 g = d.rdg_c[best];
+      a0 -= g.x * (double)bw;
+      a1 -= g.y * (double)bw;
+      a2 -= g.z * (double)bw;
+    }
+  } else {
+    // more spheres than slots: search the rigid grid
+    D4 pi = d.pos[i];
+    const Geo G = geo_of(B);
+    const Grid gr = B.rg;
+    const int coff = B.rcell_off;
+    int oob = 0;
+    int cc[3] = {cell_coord(pi.x, gr, 0, &oob), cell_coord(pi.y, gr, 1, &oob),
+                 cell_coord(pi.z, gr, 2, &oob)};
+    for_stencil<false>(G, gr, coff, pi.x, pi.y, pi.z, B.couple_R, cc, 1, [&](int cb, int ce) {
+      int tb = d.rstart[cb], te = d.rstart[ce];
+      for (int t = tb; t < te; ++t) {
+        D4 g = d.rdg_c[t];
+        if (g.w == 0.0) continue;
+        D4 ps = d.rpos_c[t];
+        double H = ps.w + d.h;
+        double ex = ps.x - pi.x, ey = ps.y - pi.y, ez = ps.z - pi.z;
+        min_img_box(G, ex, ey, ez);
+        double r2 = r2_exact(ex, ey, ez);
+        if (!(r2 < H * H)) continue;
+        // Lucy weight of support H without its normalisation (folded into g)
+        const double q = sqrt(r2) * g.w, omq = 1.0 - q;
+        const double w = (1.0 + 3.0 * q) * omq * omq * omq;
+        a0 -= g.x * w;
+        a1 -= g.y * w;
+        a2 -= g.z * w;
+      }
+    });
+  }
   d.fout[9 * np + i] = (float)a0;
   d.fout[10 * np + i] = (float)a1;
   d.fout[11 * np + i] = (float)a2;
