@@ -115,3 +115,21 @@ def test_cell_size_leaves_neighbors_and_forces_unchanged(S, oracle_lib, cf):
     g = S.System(dict(q, cell_factor=cf), qparts)
     o = oracle_lib.Oracle(q, qparts)
     _check_all(g, o, q, fields=["F_SDPD", "F_CD", "N_SDPD"])
+
+
+def test_reaction_with_more_coupled_spheres_than_slots(S, oracle_lib):
+    """Spheres of d = dx at phi = 0.35: 251 fluid particles lie inside the
+    support of more than 16 spheres (the reaction's slot count), so both
+    the slot path and its rigid-grid fallback are compared with the oracle."""
+    p, parts, info = W.shear_cell(10, phi=0.35, d=1.0, kBT=1e-3, shear_rate=0.0, seed=3)
+    x, t, R = parts["pos"], parts["type"], parts["radius"]
+    L = np.asarray(p["L"])
+    cnt = np.zeros(int((t == W.FLUID).sum()), int)
+    for k in np.nonzero(t == W.RIGID)[0]:
+        dd = x[t == W.FLUID] - x[k]
+        dd -= L * np.rint(dd / L)
+        cnt += np.sqrt((dd * dd).sum(axis=1)) < R[k] + p["h"]
+    assert cnt.max() > 16 and (cnt <= 16).any()
+    parts = W.perturb(parts, p, jitter=0.05, kT=1e-3, seed=6, spin=True)
+    g, o = _pair(S, oracle_lib, p, parts, "dense d = dx spheres")
+    _check_all(g, o, p)
