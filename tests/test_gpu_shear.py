@@ -3,9 +3,11 @@
 A sheared box must give the oracle's neighbour sets bit for bit (the x
 offset of the images and the image velocities included), its force fields
 within the single-step tolerances and its shear stress P_zx within the
-tolerance of the FP32 pair virial.  A batch of independent boxes must give,
-box by box, the same bits as each box run on its own (without thermal
-noise, whose counter uses the global ids).  Every call goes through the C ABI.
+tolerance of the FP32 pair virial, at cells of h and at the autotuner's
+smaller cells.  A batch of independent boxes must give, box by box, the
+same bits as each box run on its own (thermal noise included: its counter
+uses ids relative to the box's smallest id).  Every call goes through the
+C ABI.
 """
 import numpy as np
 import pytest
@@ -46,11 +48,12 @@ def cell(n, phi, d, kT, gd, itr, seed=0, jitter=0.1):
     return p, parts, info
 
 
+@pytest.mark.parametrize("cf", [1.0, 0.5, 0.34])
 @pytest.mark.parametrize("itr,gd,kT", [(137, 0.05, 1e-3), (4001, -0.03, 0.0), (0, 0.08, 2e-3)])
-def test_sheared_fluid_single_step(S, oracle_lib, itr, gd, kT):
+def test_sheared_fluid_single_step(S, oracle_lib, itr, gd, kT, cf):
     p, parts, _ = cell(10, 0.0, 0.0, kT, gd, itr, seed=itr)
-    print(f"[case] sheared fluid itr={itr} gd={gd} kT={kT}", flush=True)
-    g = S.System(p, parts)
+    print(f"[case] sheared fluid itr={itr} gd={gd} kT={kT} cell_factor={cf}", flush=True)
+    g = S.System(dict(p, cell_factor=cf), parts)
     o = oracle_lib.Oracle(p, parts)
     g.set_stress(True)
     assert g.compute_forces(check=False) == 0
@@ -123,13 +126,15 @@ def contact_across_sheared_face(p, parts):
     parts["vel"][a] += np.array([0.01, -0.02, -0.03])
 
 
+@pytest.mark.parametrize("cf", [1.0, 0.5])
 @pytest.mark.parametrize("phi,d,itr", [(0.3, 2.0, 55), (0.25, 4.0, 1234)])
-def test_sheared_suspension_single_step(S, oracle_lib, phi, d, itr):
+def test_sheared_suspension_single_step(S, oracle_lib, phi, d, itr, cf):
     p, parts, info = cell(14, phi, d, 1e-3, 0.04, itr, seed=itr)
     p["enable_lub"] = 1
     contact_across_sheared_face(p, parts)
-    print(f"[case] sheared suspension phi={phi} d={d} n_rigid={info['n_rigid']}", flush=True)
-    g = S.System(p, parts)
+    print(f"[case] sheared suspension phi={phi} d={d} n_rigid={info['n_rigid']} "
+          f"cell_factor={cf}", flush=True)
+    g = S.System(dict(p, cell_factor=cf), parts)
     o = oracle_lib.Oracle(p, parts)
     g.set_stress(True)
     assert g.compute_forces(check=False) == 0
