@@ -1,7 +1,9 @@
 """Parity at the full sizes of the measured workloads, in the launch
-configuration the benchmark uses: the sedimentation box (101,080 particles)
-and the dam break (1,534,168 particles, 2^20 moving).  The oracle evaluates
-every particle here; neighbour sets must match bit for bit."""
+configuration the benchmark uses (fluid cells of h/2) and at cells of h:
+the sedimentation box (101,080 particles), the dam break (1,534,168
+particles, 2^20 moving) and the periodic scale box (8,388,608 particles).
+The oracle evaluates every particle here; neighbour sets must match bit
+for bit."""
 import numpy as np
 import pytest
 
@@ -21,12 +23,14 @@ def S():
     return sdpdem
 
 
-@pytest.mark.parametrize("name", ["sedimentation", "dam_break"])
-def test_full_size_single_step(S, oracle_lib, name):
+@pytest.mark.parametrize("name,cf", [("sedimentation", 0.5), ("sedimentation", 1.0),
+                                     ("dam_break", 0.5), ("dam_break", 1.0),
+                                     ("periodic_scale", 0.5)])
+def test_full_size_single_step(S, oracle_lib, name, cf):
     p, parts, info = W.CONFIGS[name]()
     parts = W.perturb(parts, p, jitter=0.05, kT=1e-4, seed=7)
-    print(f"[case] full-size {name}: n={info['n']}", flush=True)
-    g = S.System(p, parts)
+    print(f"[case] full-size {name}: n={info['n']} cell_factor={cf}", flush=True)
+    g = S.System(dict(p, cell_factor=cf), parts)
     o = oracle_lib.Oracle(p, parts)
     assert g.compute_forces(check=False) == 0
     assert o.compute_forces(check=False) == 0
