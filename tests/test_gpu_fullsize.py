@@ -38,3 +38,38 @@ def test_full_size_single_step(S, oracle_lib, name, cf):
     assert_scalar_fields(g, o, p)
     worst = {f: assert_force_field(g, o, f) for f in VECTOR_FIELDS}
     print("  nnz", nnz, {k: f"{v:.1e}" for k, v in worst.items()}, flush=True)
+
+
+def test_full_viscometer_batch_sampled_boxes(S, oracle_lib):
+    """The bench's batched viscometer (256 Lees-Edwards cells, 7,272,566
+    particles, cells of h/2): one force evaluation of the whole batch, and
+    six of its boxes (the smallest, the largest and four drawn at random)
+    evaluated one by one by the oracle; their rows must match the oracle's
+    neighbours bit for bit and its force fields within the tolerances."""
+    shared, cells = W.viscometer_batch(256, seed=0, steps=5000)
+    parts, boxes, box_of = W.stack_cells(cells)
+    print(f"[case] full viscometer batch n={parts['id'].shape[0]}", flush=True)
+    g = S.System(dict(shared, cell_factor=0.5), parts, boxes=boxes, box_of=box_of)
+    assert g.compute_forces(check=False) == 0
+    rows, cols = g.read_neighbors()  # CSR: row starts (n + 1) and columns
+    fields = {f: g.read_field(f) for f in VECTOR_FIELDS}
+    sizes = np.array([c[2]["n"] for c in cells])
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    rng = np.random.default_rng(1)
+    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)),
+                   *rng.choice(len(cells), 4, replace=False).tolist()})
+    for b in pick:
+        p, pp, info = cells[b]
+        a, e = int(offs[b]), int(offs[b + 1])
+        o = oracle_lib.Oracle(p, pp)
+        assert o.compute_forces(check=False) == 0
+        ro, co = o.read_neighbors()
+        assert np.array_equal(rows[a:e + 1] - rows[a], ro), b
+        assert np.array_equal(cols[rows[a]:rows[e]] - a, co), b
+        for f in VECTOR_FIELDS:
+            gv = fields[f][a:e]
+            ov, sc = o.read_field(f), o.read_field(f + "_ABS")
+            err = np.linalg.norm(gv - ov, axis=1)
+            tiny = 1e-30 + 1e-12 * (sc.max() if sc.size else 0.0)
+            assert np.all(err <= 1e-5 * sc + tiny), (b, f)
+        print(f"  box {b}: n={e - a}, {int(ro[-1])} neighbour slots", flush=True)
