@@ -345,13 +345,30 @@ def main():
         t_more = time.perf_counter() - t0
         steps_cpu = 1 + more
         t_cpu = one + t_more
+        cores = O.num_threads()
+        # the same oracle on one core, one step further on
+        O.set_num_threads(1)
+        t0 = time.perf_counter()
+        o.step(1)
+        t_one_core = time.perf_counter() - t0
+        O.set_num_threads(cores)
+        model = None
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((ln.split(":", 1)[1].strip() for ln in f
+                              if ln.startswith("model name")), None)
+        except OSError:
+            pass
         result["cpu_baseline"] = {
             "value": round(info["n_moving"] * steps_cpu / t_cpu, 1),
             "unit": "moving-particle-steps/s",
-            "cores": O.num_threads(),
+            "cores": cores,
             "kind": "oracle",
             "sample": f"{steps_cpu} step(s) of the same workload from its initial state "
                       f"({t_cpu:.1f} s, FP64 oracle, OpenMP)",
+            "one_core_value": round(info["n_moving"] / t_one_core, 1),
+            "one_core_sample": f"the next step on one thread ({t_one_core:.1f} s)",
+            "cpu_model": model,
         }
     print(json.dumps(result), flush=True)
 
