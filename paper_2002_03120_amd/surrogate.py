@@ -169,6 +169,9 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=400)
     ap.add_argument("--queries", type=int, default=1 << 20)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--max-rel-se", type=float, default=0.1,
+                    help="train only on cells whose relative standard error is below this "
+                         "(the low-shear cells are dominated by thermal noise)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shape (cell = h, 10-step graphs, 4M-particle batches)")
     args = ap.parse_args(argv)
@@ -183,7 +186,7 @@ def main(argv=None):
     torch.cuda.synchronize()
     t_meas = time.perf_counter() - t0
     x = features([c[2] for c in cells])
-    ok = eta > 0
+    ok = (eta > 0) & (se < args.max_rel_se * np.abs(eta))
     y = np.log(np.where(ok, eta, 1.0)).astype(np.float32)
     t0 = time.perf_counter()
     net, hist = train(x[ok], y[ok], epochs=args.epochs, seed=args.seed, log=log)
@@ -208,6 +211,7 @@ def main(argv=None):
     t_q = (time.perf_counter() - t0) / 10
     res = {
         "train_cells": args.cells, "steps_per_run": args.steps, "side": args.side,
+        "trained_on": int(ok.sum()), "max_rel_se": args.max_rel_se,
         "measure_s": round(t_meas, 2), "train_s": round(t_train, 2),
         "launch_shape": None if tuning is None else
             {k: tuning[k] for k in ("cell_factor", "graph_steps", "tile", "tune_s")},
