@@ -605,8 +605,8 @@ bool rigid_active(const sdpdem_system* s) {
 // (a5)-(a9): one force evaluation (Alg. 2) and, if asked, the update.
 void run_pass(sdpdem_system* s, int velver, int commit, bool integrate, hipStream_t st) {
   Dev& d = s->d;
-  // the pass's stamp marks the fluid particles coupled in it
-  launch_pass_begin(d, integrate ? velver : 0, st);
+  // the pass's stamp (set by launch_pass_prep) marks the fluid particles
+  // coupled in it
   {
     Prof pr(s, SDPDEM_K_FLUID_FORCES, st);
     launch_fluid_forces(d, s->noise, st);
@@ -619,7 +619,6 @@ void run_pass(sdpdem_system* s, int velver, int commit, bool integrate, hipStrea
     }
     {
       Prof pr(s, SDPDEM_K_FPI_ACTION, st);
-      launch_fill_i32(d.rxn_cnt, 0, (size_t)d.npad, st);
       launch_fpi_action(d, st);
     }
     {
@@ -832,13 +831,14 @@ namespace {
 // One iteration of Algorithm 1 (enqueue only).
 void step_body(sdpdem_system* s, hipStream_t st) {
   Dev& d = s->d;
-  // Lees-Edwards offsets for positions at this step and after the drift
-  launch_le_shift(s->boxes, d.nbox, d.dstep, 0, d.dt, st);
+  // Lees-Edwards offsets for positions at this step and after the drift,
+  // the pass stamp, the reaction's counts
+  launch_pass_prep(d, s->boxes, 0, 1, rigid_active(s), st);
   if (!s->cache_valid) run_build(s, st);
   run_pass(s, 1, 0, true, st);
   // positions moved: sort, neighbours, density and smoothing at x(n+1);
   // they stay valid for the first pass of the next step
-  launch_le_shift(s->boxes, d.nbox, d.dstep, 1, d.dt, st);
+  launch_pass_prep(d, s->boxes, 1, 2, rigid_active(s), st);
   run_build(s, st);
   run_pass(s, 2, 1, true, st);
   if (s->stress) {
@@ -933,7 +933,7 @@ int sdpdem_set_graph(sdpdem_system* s, int steps_per_graph) {
 int sdpdem_compute_forces(sdpdem_system* s, void* hip_stream) {
   if (!s) return SDPDEM_E_INVALID_ARG;
   hipStream_t st = (hipStream_t)hip_stream;
-  launch_le_shift(s->boxes, s->d.nbox, s->d.dstep, 0, s->d.dt, st);
+  launch_pass_prep(s->d, s->boxes, 0, 0, rigid_active(s), st);
   if (!s->cache_valid) {
     run_build(s, st);
     s->cache_valid = true;

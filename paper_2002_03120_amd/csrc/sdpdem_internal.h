@@ -200,12 +200,13 @@ void launch_cell_sort(const int* start, int ncells, int* perm, const int* sortke
 void launch_permute(const Dev& d, const D4* spos, const D4* svel, const D4* som,
                     const uint8_t* stype, const int* sgid, hipStream_t st);
 void launch_build_density(const Dev& d, hipStream_t st);
-// Lees-Edwards offsets of every box for positions at step *dstep + add
-void launch_le_shift(BoxD* boxes, int nbox, const int64_t* dstep, int add, double dt,
-                     hipStream_t st);
-// stamp of a pass: 4 step + code + 1 (code 1, 2: passes of a step; 0: a
-// force evaluation without update); the step counter's increment
-void launch_pass_begin(const Dev& d, int code, hipStream_t st);
+// start of a pass: Lees-Edwards offsets of every box for positions at step
+// *dstep + add, the pass stamp 4 step + code + 1 (code 1, 2: passes of a
+// step; 0: a force evaluation without update) and, with clear_rxn, the
+// reaction's slot counts set to zero
+void launch_pass_prep(const Dev& d, BoxD* boxes, int add, int code, bool clear_rxn,
+                      hipStream_t st);
+// the step counter's increment
 void launch_step_end(const Dev& d, hipStream_t st);
 // per-box sample of P_zx; with accumulate, also added to the running sums
 void launch_box_stress(const Dev& d, int accumulate, hipStream_t st);

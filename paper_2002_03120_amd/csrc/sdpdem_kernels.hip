@@ -98,21 +98,31 @@ void launch_bin_rigid(const Dev& d, hipStream_t st) {
   k_bin_rigid<<<(d.nr + BS - 1) / BS, BS, 0, st>>>(d);
 }
 
-// Lees-Edwards offsets delta(t) = fmod(shear L_z t, L_x) of every box for
-// positions at step pos_step and at the step after
-__global__ void k_le_shift(BoxD* boxes, int nbox, const int64_t* dstep, int add, double dt) {
+// The start of a pass, one launch: the Lees-Edwards offsets
+// delta(t) = fmod(shear L_z t, L_x) of every box for positions at step
+// *dstep + add and at the step after, the pass stamp 4 step + code + 1, and
+// (when the coupling runs) the reaction's slot counts cleared.
+__global__ void k_pass_prep(BoxD* boxes, int nbox, const int64_t* dstep, int* dstamp, int add,
+                            int code, double dt, int* rxn_cnt, int nfill) {
 #pragma clang fp contract(off)
-  int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nbox) return;
-  const int64_t pos_step = dstep[0] + add;
-  BoxD& B = boxes[b];
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t step = dstep[0];
+  if (tid == 0) dstamp[0] = (int)(4 * step + code + 1);
+  if (rxn_cnt && 4 * tid < nfill) {
+    if (4 * tid + 4 <= nfill)
+      *reinterpret_cast<int4*>(rxn_cnt + 4 * tid) = make_int4(0, 0, 0, 0);
+    else
+      for (int k = 4 * tid; k < nfill; ++k) rxn_cnt[k] = 0;
+  }
+  if (tid >= nbox) return;
+  BoxD& B = boxes[tid];
   if (!B.le) {
     B.le_shift = 0.0;
     B.le_next = 0.0;
     return;
   }
   for (int k = 0; k < 2; ++k) {
-    double t = (double)(pos_step + k) * dt;
+    double t = (double)(step + add + k) * dt;
     double v = (B.shear * B.L[2]) * t;
     double sft = fmod(v, B.L[0]);
     if (sft < 0.0) sft += B.L[0];
@@ -123,21 +133,18 @@ __global__ void k_le_shift(BoxD* boxes, int nbox, const int64_t* dstep, int add,
   }
 }
 
-void launch_le_shift(BoxD* boxes, int nbox, const int64_t* dstep, int add, double dt,
-                     hipStream_t st) {
-  k_le_shift<<<(nbox + 63) / 64, 64, 0, st>>>(boxes, nbox, dstep, add, dt);
+void launch_pass_prep(const Dev& d, BoxD* boxes, int add, int code, bool clear_rxn,
+                      hipStream_t st) {
+  const int nfill = clear_rxn ? d.npad : 0;  // rxn_cnt is 256-byte aligned
+  const int threads = max(d.nbox, (nfill + 3) / 4);
+  k_pass_prep<<<(unsigned)max(1, (threads + BS - 1) / BS), BS, 0, st>>>(
+      boxes, d.nbox, d.dstep, d.dstamp, add, code, d.dt, clear_rxn ? d.rxn_cnt : nullptr, nfill);
 }
 
-__global__ void k_pass_begin(const int64_t* dstep, int* dstamp, int code) {
-  if (threadIdx.x == 0) dstamp[0] = (int)(4 * dstep[0] + code + 1);
-}
 __global__ void k_step_end(int64_t* dstep) {
   if (threadIdx.x == 0) dstep[0] += 1;
 }
 
-void launch_pass_begin(const Dev& d, int code, hipStream_t st) {
-  k_pass_begin<<<1, 64, 0, st>>>(d.dstep, d.dstamp, code);
-}
 void launch_step_end(const Dev& d, hipStream_t st) {
   k_step_end<<<1, 64, 0, st>>>(d.dstep);
 }
