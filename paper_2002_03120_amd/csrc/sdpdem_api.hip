@@ -235,7 +235,6 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
   D4* rvel_c = b.take<D4>(nr);
   D4* rom_c = b.take<D4>(nr);
   D4* rdg_c = b.take<D4>(nr);
-  int* rslot_pos = b.take<int>(nr);
   int* cstamp = b.take<int>(np);
   int* rxn_cnt = b.take<int>(nr ? np : 1);
   int2* rxn_slot = b.take<int2>(nr ? (size_t)RXN_CAP * np : 1);
@@ -312,7 +311,6 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
     d.rvel_c = rvel_c;
     d.rom_c = rom_c;
     d.rdg_c = rdg_c;
-    d.rslot_pos = rslot_pos;
     d.cstamp = cstamp;
     d.rxn_cnt = rxn_cnt;
     d.rxn_slot = rxn_slot;
@@ -640,7 +638,8 @@ void run_pass(sdpdem_system* s, int velver, int commit, bool integrate, hipStrea
   }
   if (integrate) {
     Prof pr(s, SDPDEM_K_INTEGRATE, st);
-    launch_integrate(d, velver, act ? 1 : 0, st);
+    // the second pass of a step also advances the device step counter
+    launch_integrate(d, velver, act ? 1 : 0, velver == 2, st);
   }
 }
 
@@ -845,7 +844,6 @@ void step_body(sdpdem_system* s, hipStream_t st) {
     launch_box_stress(d, 1, st);
     s->stress_samples += 1;
   }
-  launch_step_end(d, st);
   s->cache_valid = true;
   s->step += 1;
 }

@@ -166,7 +166,6 @@ struct Dev {
   D4* rvel_c;
   D4* rom_c;
   D4* rdg_c;       // F^DG / Omega x Lucy normalisation of H_s; w = 1/H_s (0: no coupling)
-  int* rslot_pos;  // slot -> t
   // fluid particles coupled to a sphere in the current pass carry the stamp
   int* cstamp;
   int* rxn_cnt;    // spheres that coupled to the particle in this pass
@@ -206,8 +205,6 @@ void launch_build_density(const Dev& d, hipStream_t st);
 // reaction's slot counts set to zero
 void launch_pass_prep(const Dev& d, BoxD* boxes, int add, int code, bool clear_rxn,
                       hipStream_t st);
-// the step counter's increment
-void launch_step_end(const Dev& d, hipStream_t st);
 // per-box sample of P_zx; with accumulate, also added to the running sums
 void launch_box_stress(const Dev& d, int accumulate, hipStream_t st);
 void launch_smooth(const Dev& d, hipStream_t st);
@@ -217,7 +214,9 @@ void launch_fpi_action(const Dev& d, hipStream_t st);
 void launch_fpi_reaction(const Dev& d, hipStream_t st);
 void launch_dem(const Dev& d, int commit, int* nxt_cnt, int* nxt_partner, double* nxt_dt,
                 hipStream_t st);
-void launch_integrate(const Dev& d, int velver, int rigid_active, hipStream_t st);
+// with end_step, block 0 also advances the device step counter
+void launch_integrate(const Dev& d, int velver, int rigid_active, bool end_step,
+                      hipStream_t st);
 void launch_read_field(const Dev& d, int field, int rigid_active, double* out, hipStream_t st);
 int totals_partial_blocks(int n);
 void launch_totals(const Dev& d, double* partial, double* out, hipStream_t st);

@@ -141,13 +141,7 @@ void launch_pass_prep(const Dev& d, BoxD* boxes, int add, int code, bool clear_r
       boxes, d.nbox, d.dstep, d.dstamp, add, code, d.dt, clear_rxn ? d.rxn_cnt : nullptr, nfill);
 }
 
-__global__ void k_step_end(int64_t* dstep) {
-  if (threadIdx.x == 0) dstep[0] += 1;
-}
 
-void launch_step_end(const Dev& d, hipStream_t st) {
-  k_step_end<<<1, 64, 0, st>>>(d.dstep);
-}
 
 static constexpr int SCAN_ITEMS = 8;
 static constexpr int SCAN_TILE = BS * SCAN_ITEMS;
@@ -314,6 +308,7 @@ void launch_permute(const Dev& d, const D4* spos, const D4* svel, const D4* som,
   k_permute<<<nblocks(d.n), BS, 0, st>>>(d, spos, svel, som, stype, sgid);
 }
 
+
 // ---------------------------------------------------------------------------
 // Rigid particles in rigid-grid cell order: after the rigid counting sort,
 // copy position (+radius), velocity (+mass) and spin (+inertia) of every
@@ -329,7 +324,6 @@ __global__ __launch_bounds__(BS) void k_rigid_gather(Dev d) {
   d.rpos_c[t] = d.pos[i];
   d.rvel_c[t] = d.vel[i];
   d.rom_c[t] = d.om[i];
-  d.rslot_pos[s] = t;
 }
 
 void launch_rigid_gather(const Dev& d, hipStream_t st) {
@@ -861,7 +855,11 @@ __device__ __forceinline__ void total_force(const Dev& d, const BoxD& B, int i, 
   }
 }
 
-__global__ __launch_bounds__(BS) void k_integrate(Dev d, int velver, int rigid_active) {
+__global__ __launch_bounds__(BS) void k_integrate(Dev d, int velver, int rigid_active,
+                                                 int end_step) {
+  // the last pass of a step advances the device step counter (no kernel of
+  // this launch reads it)
+  if (end_step && blockIdx.x == 0 && threadIdx.x == 0) d.dstep[0] += 1;
   int i;
   const int b = blk_box(d, i);
   if (b < 0) return;
@@ -945,8 +943,9 @@ __global__ __launch_bounds__(BS) void k_integrate(Dev d, int velver, int rigid_a
   }
 }
 
-void launch_integrate(const Dev& d, int velver, int rigid_active, hipStream_t st) {
-  k_integrate<<<d.nblk, BS, 0, st>>>(d, velver, rigid_active);
+void launch_integrate(const Dev& d, int velver, int rigid_active, bool end_step,
+                      hipStream_t st) {
+  k_integrate<<<d.nblk, BS, 0, st>>>(d, velver, rigid_active, end_step ? 1 : 0);
 }
 
 // ---------------------------------------------------------------------------
