@@ -706,8 +706,10 @@ __device__ __forceinline__ int dem_pair_eval(const Dev& d, const Geo& G, int s, 
   return 0;
 }
 
-__global__ __launch_bounds__(BS) void k_dem(Dev d, int commit, int* nxt_cnt, int* nxt_partner,
-                                           double* nxt_dt) {
+// at most 128 registers (four waves per SIMD instead of three; a few
+// spills, 7 % faster over the dam break's 20,000 spheres)
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_dem(
+    Dev d, int commit, int* nxt_cnt, int* nxt_partner, double* nxt_dt) {
   const int wave = xcd_wave();
   const int lane = threadIdx.x & 63;
   if (wave >= d.nr) return;
