@@ -217,8 +217,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not "
-                                   "part of it (see the sharding notes in the design)",
+        print(json.dumps({"error": "the library runs on one GPU; a run over several GPUs "
+                                   "(slab decomposition with halo exchange) is not implemented",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 

@@ -5,7 +5,7 @@
  * that the batched Lees-Edwards viscometer (sdpdem_create_batch,
  * sdpdem_box_stress) measures.  Not part of the paper: it is the learned
  * part of the viscometer workflow, with the plain simulation as its
- * fallback and the judge of its error.
+ * fallback and the reference its error is measured against.
  *
  * Numerics: parameters kept as float32 masters and used as bfloat16
  * (round to nearest even) in the forward and backward passes; activations
