@@ -44,3 +44,17 @@ def test_batch_tile_and_graph_length_do_not_change_results(AT):
                    tuning=dict(cell_factor=1.0, graph_steps=2, tile=n // 3))
     assert np.all(np.isfinite(a[1]))
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_single_system_tuner_picks_its_fastest_cell_size(AT):
+    """tune_system, the search behind `bench.py --cell-factor 0`, on a small
+    dam break: every admissible candidate is timed and the pick is the
+    fastest of them."""
+    p, parts, info = W.dam_break(tank=(48, 16, 32), column=(24, 16, 24), n_rigid=40, seed=2)
+    print(f"[case] tune_system on n={info['n']}", flush=True)
+    res = AT.tune_system(p, parts, sample_steps=4, cell_factors=(0.5, 1.0, 1.5))
+    timed = [t for t in res["trials"] if "step_ms" in t]
+    assert [t["cell_factor"] for t in timed] == [0.5, 1.0, 1.5]
+    best = min(timed, key=lambda t: t["step_ms"])
+    assert res["cell_factor"] == best["cell_factor"]
+    assert res["step_ms"] == best["step_ms"]
