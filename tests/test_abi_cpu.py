@@ -58,9 +58,20 @@ def test_workspace_scales_with_problem(lib):
     assert S.sdpdem_workspace_bytes(p3, parts2) > big
 
 
+def test_cell_factor_grows_the_grid_below_h(lib):
+    p, parts, _ = W.reverse_poiseuille(n_side=(20, 20, 20))
+    base = S.sdpdem_workspace_bytes(p, parts)
+    assert S.sdpdem_workspace_bytes(dict(p, cell_factor=1.0), parts) == base  # 0 means 1
+    half = S.sdpdem_workspace_bytes(dict(p, cell_factor=0.5), parts)
+    quarter = S.sdpdem_workspace_bytes(dict(p, cell_factor=0.25), parts)
+    assert base < half < quarter  # the cell arrays grow with the number of cells
+
+
 @pytest.mark.parametrize("bad", [
     dict(xi=0.0), dict(xi=1.0), dict(h=0.0), dict(dt=-1.0), dict(L=[4.0, 10.0, 10.0]),
     dict(max_neighbors=0), dict(gravity_axis=3), dict(rho0=0.0),
+    dict(cell_factor=0.2), dict(cell_factor=-1.0), dict(cell_factor=float("nan")),
+    dict(cell_factor=17.0), dict(cell_factor=4.0),  # 4 h cells: fewer than 3 on a 10-site axis
 ])
 def test_rejects_bad_params(lib, bad):
     p, parts, _ = W.reverse_poiseuille(n_side=(10, 10, 10))
