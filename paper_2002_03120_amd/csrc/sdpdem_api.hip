@@ -224,6 +224,7 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
   int2* blk = b.take<int2>(z.blk.size());
   int* rbox = b.take<int>(nr);
   double* st_inst = b.take<double>((size_t)z.nbox);
+  double* st_part = b.take<double>(z.blk.size());
   double* st_sum = b.take<double>((size_t)z.nbox);
   uint32_t* rkey = b.take<uint32_t>(nr);
   int* rcount = b.take<int>(rnc);
@@ -300,6 +301,7 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
     d.blk = blk;
     d.rbox = rbox;
     d.st_inst = st_inst;
+    d.st_part = st_part;
     d.st_sum = st_sum;
     d.rkey = rkey;
     d.rcount = rcount;
@@ -400,6 +402,7 @@ bool plan(const sdpdem_params* P, const sdpdem_box* boxes, int nbox,
     int64_t id0 = r.empty() ? 0 : q->id[r[0]];
     for (int64_t k : r) id0 = std::min(id0, q->id[k]);
     B.id_base = (uint32_t)id0;
+    B.blk_first = (int)z.blk.size();
     for (int c = 0; c < (B.count + BS - 1) / BS; ++c)
       z.blk.push_back(make_int2(b, B.first + c * BS));
     for (int64_t k : r) z.order.push_back(k);

@@ -320,8 +320,9 @@ __device__ __forceinline__ void for_stencil(const Geo& B, const Grid& G, int off
 // x reach takes one FP32 square root.  Every bound carries a relative
 // margin of 1e-5 of a cell, far above the FP32 rounding of these small
 // numbers, so the runs may hold a few extra cells but never miss one; the
-// distance test in FP64 decides.  Sheared boxes, stencils that wrap onto
-// themselves and points outside their cell take the generic rows.
+// distance test in FP64 decides.  Sheared boxes (measured: the generic
+// rows are faster there), stencils that wrap onto themselves and points
+// outside their cell take the generic rows.
 template <class Fn>
 __device__ __forceinline__ void for_stencil_pruned(const Geo& B, const Grid& G, int off, double px,
                                                    double py, double pz, double R,
@@ -361,10 +362,8 @@ __device__ __forceinline__ void for_stencil_pruned(const Geo& B, const Grid& G, 
       const float d2 = z2 + sy * sy;
       if (d2 >= R2) continue;
       const float rx = sqrtf(R2 - d2) * (1.0f + 1e-5f) + mx;
-      int xa = cc[0] + (int)floorf((fx - rx) * icx);
-      int xb = cc[0] + (int)floorf((fx + rx) * icx);
-      xa = max(xa, cc[0] - k);
-      xb = min(xb, cc[0] + k);
+      const int xa = max(cc[0] + (int)floorf((fx - rx) * icx), cc[0] - k);
+      const int xb = min(cc[0] + (int)floorf((fx + rx) * icx), cc[0] + k);
       if (xb < xa) continue;
       const int rowkey = off + (z * ny + y) * nx;
       if (!G.per[0]) {
@@ -373,7 +372,9 @@ __device__ __forceinline__ void for_stencil_pruned(const Geo& B, const Grid& G, 
       } else if (xb - xa + 1 >= nx) {
         fn(rowkey, rowkey + nx);
       } else {
-        const int lo = ((xa % nx) + nx) % nx, hi = lo + (xb - xa);  // at most one wrap
+        // xa (within k cells of the row) into [0, nx) without a division
+        const int lo = xa < 0 ? xa + nx : (xa >= nx ? xa - nx : xa);
+        const int hi = lo + (xb - xa);  // at most one wrap
         if (hi >= nx) {
           fn(rowkey + lo, rowkey + nx);
           fn(rowkey, rowkey + hi - nx + 1);

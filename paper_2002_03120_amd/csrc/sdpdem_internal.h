@@ -75,6 +75,7 @@ struct BoxD {
   int le;             // shear != 0
   int cell_off, rcell_off;
   int first, count;   // sorted particle range
+  int blk_first;      // the box's first entry in the launch-block table
   int dem_reach;      // rigid-grid cells to search for DEM partners
   double couple_R;    // R_max + h: coupling partners lie within it
   double dem_R;       // 2 R_max + h: DEM and lubrication partners lie within it
@@ -180,6 +181,7 @@ struct Dev {
   // per-box pressure-tensor samples: P_zx now, its running sum and count
   double* st_inst;
   double* st_sum;
+  double* st_part;  // per launch block: its particles' share of P_zx V
   int* status;
 };
 

@@ -957,40 +957,59 @@ void launch_integrate(const Dev& d, int velver, int rigid_active, bool end_step,
 // wzx_r for rigid particles), over the box volume.  One block per box sums
 // its fixed particle range in a fixed order, so the result is repeatable.
 
-__global__ __launch_bounds__(BS) void k_box_stress(Dev d, int rigid_active, int accumulate) {
+// Per-box pressure tensor sample in two launches with a fixed summation
+// order: each launch block sums m v_z v'_x + the virial over its particles
+// (a tree in shared memory), then one thread per box adds its blocks'
+// partial sums in block order.  A box's blocks start at its first particle,
+// so a box gives the same bits alone or in a batch.
+__global__ __launch_bounds__(BS) void k_box_stress_part(Dev d, int rigid_active) {
   __shared__ double sh[BS];
-  const int b = blockIdx.x;
-  const BoxD& B = d.boxes[b];
-  const size_t np = (size_t)d.npad;
-  const double zmid = B.org[2] + 0.5 * B.L[2];
-  double acc = 0.0;
-  for (int i = B.first + (int)threadIdx.x; i < B.first + B.count; i += BS) {
-    const uint8_t t = d.type[i];
-    if (t == T_OUTER) continue;
-    const D4 p = d.pos[i], v = d.vel[i];
-    const double vx = v.x - B.shear * (p.z - zmid);
-    double q = v.w * v.z * vx;
-    if (t == T_FLUID || t == T_INNER)
-      q += (double)d.fout[12 * np + i];
-    else if (t == T_RIGID && rigid_active)
-      q += d.wzx_r[d.gid2slot[d.gid[i]]];
-    acc += q;
+  const unsigned nb = gridDim.x, bb = blockIdx.x;
+  const unsigned lb = (nb % 8u == 0u) ? (bb % 8u) * (nb / 8u) + (bb / 8u) : bb;
+  int i;
+  const int b = blk_box(d, i);
+  double q = 0.0;
+  if (b >= 0) {
+    const BoxD& B = d.boxes[b];
+    if (i < B.first + B.count) {
+      const uint8_t t = d.type[i];
+      if (t != T_OUTER) {
+        const size_t np = (size_t)d.npad;
+        const double zmid = B.org[2] + 0.5 * B.L[2];
+        const D4 p = d.pos[i], v = d.vel[i];
+        const double vx = v.x - B.shear * (p.z - zmid);
+        q = v.w * v.z * vx;
+        if (t == T_FLUID || t == T_INNER)
+          q += (double)d.fout[12 * np + i];
+        else if (t == T_RIGID && rigid_active)
+          q += d.wzx_r[d.gid2slot[d.gid[i]]];
+      }
+    }
   }
-  sh[threadIdx.x] = acc;
+  sh[threadIdx.x] = q;
   __syncthreads();
   for (int o = BS / 2; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    const double pzx = sh[0] / B.vol;
-    d.st_inst[b] = pzx;
-    if (accumulate) d.st_sum[b] += pzx;
-  }
+  if (threadIdx.x == 0) d.st_part[lb] = sh[0];
+}
+
+__global__ void k_box_stress_final(Dev d, int accumulate) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= d.nbox) return;
+  const BoxD& B = d.boxes[b];
+  const int nb = (B.count + BS - 1) / BS;
+  double acc = 0.0;
+  for (int c = 0; c < nb; ++c) acc += d.st_part[B.blk_first + c];
+  const double pzx = acc / B.vol;
+  d.st_inst[b] = pzx;
+  if (accumulate) d.st_sum[b] += pzx;
 }
 
 void launch_box_stress(const Dev& d, int accumulate, hipStream_t st) {
-  k_box_stress<<<d.nbox, BS, 0, st>>>(d, d.have_rxn, accumulate);
+  k_box_stress_part<<<d.nblk, BS, 0, st>>>(d, d.have_rxn);
+  k_box_stress_final<<<(d.nbox + 63) / 64, 64, 0, st>>>(d, accumulate);
 }
 
 // ---------------------------------------------------------------------------
