@@ -72,6 +72,7 @@ __device__ __forceinline__ Geo geo_of(const BoxD& B) {
     g.halfL[a] = B.halfL[a];
     g.per[a] = B.per[a];
   }
+  g.inv_Lx = 1.0 / B.L[0];
   g.le_shift = B.le_shift;
   g.le_jump = B.le_jump;
   g.le = B.le;
@@ -91,8 +92,12 @@ __device__ __forceinline__ int min_img_box(const Geo& B, double& ex, double& ey,
     }
   }
   if (B.le) {
+    // rint(ex / L) with a multiply: it can differ from the quotient's only
+    // where ex / L sits within an ulp of a half-integer, where both images
+    // are equally near (and L/2 is at least 1.5 cells, beyond the SDPD and
+    // coupling cut-offs)
     ex = ex - B.le_shift * (double)kz;
-    ex = ex - B.L[0] * rint(ex / B.L[0]);
+    ex = ex - B.L[0] * rint(ex * B.inv_Lx);
   } else {
     ex = min_img(ex, B.per[0], B.L[0], B.halfL[0]);
   }
