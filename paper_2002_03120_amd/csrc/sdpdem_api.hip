@@ -513,7 +513,10 @@ void bind_current(sdpdem_system* s) {
 
 void prof_flush(sdpdem_system* s) {
   if (s->ev_used == 0) return;
-  hipEventSynchronize(s->ev[s->ev_used - 1].second);
+  if (hipEventSynchronize(s->ev[s->ev_used - 1].second) != hipSuccess) {
+    s->ev_used = 0;  // the samples are lost; the kernel's own error surfaces on its stream
+    return;
+  }
   for (size_t k = 0; k < s->ev_used; ++k) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, s->ev[k].first, s->ev[k].second) == hipSuccess) {
@@ -538,7 +541,7 @@ struct Prof {
           return;
         }
         if (hipEventCreate(&b) != hipSuccess) {
-          hipEventDestroy(a);
+          (void)hipEventDestroy(a);
           on = false;
           return;
         }
@@ -547,12 +550,11 @@ struct Prof {
         prof_flush(s);
       }
     }
-    hipEventRecord(s->ev[s->ev_used].first, st);
+    on = hipEventRecord(s->ev[s->ev_used].first, st) == hipSuccess;
   }
   ~Prof() {
     if (!on) return;
-    hipEventRecord(s->ev[s->ev_used].second, st);
-    s->ev_used += 1;
+    if (hipEventRecord(s->ev[s->ev_used].second, st) == hipSuccess) s->ev_used += 1;
   }
 };
 
@@ -852,7 +854,7 @@ void step_body(sdpdem_system* s, hipStream_t st) {
 }
 
 void drop_graph(sdpdem_system* s) {
-  if (s->gexec) hipGraphExecDestroy(s->gexec);
+  if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
   s->gexec = nullptr;
 }
 
@@ -872,13 +874,13 @@ bool capture(sdpdem_system* s, hipStream_t st) {
   s->step = step0;
   s->stress_samples = samples0;
   if (s->cur != cur0 || s->ct_cur != ct0) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return false;
   }
   if (!ok) return false;
   hipGraphExec_t ex = nullptr;
   const bool inst = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (!inst) return false;
   s->gexec = ex;
   s->g_act = rigid_active(s);
@@ -1193,8 +1195,8 @@ void sdpdem_destroy(sdpdem_system* s) {
   drop_graph(s);
   prof_flush(s);
   for (auto& e : s->ev) {
-    hipEventDestroy(e.first);
-    hipEventDestroy(e.second);
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
   }
   delete s;
 }
