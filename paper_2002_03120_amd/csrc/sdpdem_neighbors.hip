@@ -167,15 +167,13 @@ __global__ __launch_bounds__(BS) void k_fluid_forces(Dev d) {
     const float kT = B.kTf;
     const uint32_t key0 = B.key0, key1 = B.key1;
     const uint32_t step = NOISE ? (uint32_t)d.dstep[0] : 0u;  // noise counter
-    // software-pipelined: the record of slot k+1 and the index of slot k+2
-    // are in flight while slot k is evaluated
+    // the index of slot k+1 is in flight while slot k is evaluated (holding
+    // the next record too costs 19 registers: 7 waves per SIMD instead of 8,
+    // and the kernel is 4 % slower)
     int jn = cnt > 0 ? nb[0] : i;
-    PR rn = load_pr(d.prec, jn);
-    jn = cnt > 1 ? nb[npad] : i;
     for (int k = 0; k < cnt; ++k) {
-      const PR rj = rn;
-      rn = load_pr(d.prec, jn);
-      jn = k + 2 < cnt ? nb[(size_t)(k + 2) * npad] : i;
+      const PR rj = load_pr(d.prec, jn);
+      jn = k + 1 < cnt ? nb[(size_t)(k + 1) * npad] : i;
       double dx_ = ri.x - rj.x, dy_ = ri.y - rj.y, dz_ = ri.z - rj.z;
       const int kz = min_img_box(G, dx_, dy_, dz_);
       const double r2d = dx_ * dx_ + dy_ * dy_ + dz_ * dz_;
