@@ -361,6 +361,7 @@ __device__ __forceinline__ int wave_sum_i(int v) {
 }
 
 // cells to search around a point for partners within H (largest over the axes)
+template <bool STRESS>
 __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
   const int wave = xcd_wave();
   const int lane = threadIdx.x & 63;
@@ -381,7 +382,7 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
   const int kr = reach_cells(gr, H);
   const size_t np = (size_t)d.npad;
   const int stamp = d.dstamp[0];
-  double om = 0, v0 = 0, v1 = 0, v2 = 0, f0 = 0, f1 = 0, f2 = 0, l0 = 0, l1 = 0, l2 = 0;
+  double om = 0, v0 = 0, v1 = 0, v2 = 0, f0 = 0, f1 = 0, f2 = 0, l2 = 0;
   int nrig = 0;
   // the search box row by row: lane r takes row r of each batch of 64 rows
   // (at most two runs of consecutive cells per row)
@@ -456,9 +457,7 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
       f0 += w * (double)d.fout[6 * np + j];
       f1 += w * (double)d.fout[7 * np + j];
       f2 += w * (double)d.fout[8 * np + j];
-      l0 += w * ex;
-      l1 += w * ey;
-      l2 += w * ez;
+      if (STRESS) l2 += w * ez;  // the coupling's lever (z part)
       d.cstamp[j] = stamp;
     }
   }
@@ -469,11 +468,7 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
   f0 = wave_sum(f0);
   f1 = wave_sum(f1);
   f2 = wave_sum(f2);
-  if (d.stress) {
-    l0 = wave_sum(l0);
-    l1 = wave_sum(l1);
-    l2 = wave_sum(l2);
-  }
+  if (STRESS) l2 = wave_sum(l2);
   nrig = wave_sum_i(nrig);
   if (lane != 0) return;
   const double Vs = 4.0 / 3.0 * PI * R * R * R;
@@ -500,7 +495,7 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
   }
   // virial of the coupling: lever (sum_j w_sj r_sj / Omega_s)_z times the
   // x force; the contacts add theirs later in the pass
-  if (d.stress) d.wzx_r[s] = om > 0.0 ? (l2 / om) * (dg[0] + pg[0]) : 0.0;
+  if (STRESS) d.wzx_r[s] = om > 0.0 ? (l2 / om) * (dg[0] + pg[0]) : 0.0;
   // F^DG / Omega times the kernel's normalisation beside the sphere's
   // cell-ordered record, with 1/H_s (0: the sphere couples to nothing)
   D4 rc;
@@ -513,7 +508,7 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
 
 void launch_fpi_action(const Dev& d, hipStream_t st) {
   if (d.nr == 0) return;
-  k_fpi_action<<<nblocks((size_t)d.nr * 64), BS, 0, st>>>(d);
+  (d.stress ? k_fpi_action<true> : k_fpi_action<false>)<<<nblocks((size_t)d.nr * 64), BS, 0, st>>>(d);
 }
 
 // (a7) reaction on the stamped fluid particles, Eq. F_fpi_DG_reac
