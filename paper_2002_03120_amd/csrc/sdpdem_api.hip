@@ -33,13 +33,16 @@ struct sdpdem_system {
   double* tot_out;
   int64_t step = 0;
   bool cache_valid = false;
+  // the reaction's slots hold the coupling pairs of the current positions
+  // and sorted order (a neighbour build invalidates them)
+  bool rxn_valid = false;
   bool noise = false;
   bool stress = false;
   int64_t stress_samples = 0;
   // captured step loop (graph_steps steps, an even number, per launch)
   int graph_steps = 0;
   hipGraphExec_t gexec = nullptr;
-  bool g_act = false, g_stress = false;
+  bool g_act = false, g_stress = false, g_rxn = false;
   int g_cur = 0, g_ct = 0;  // buffer parity the graph was captured with
   BoxD* boxes = nullptr;  // device copy of the box table
   std::vector<BoxD> h_boxes;
@@ -236,11 +239,12 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
   D4* rvel_c = b.take<D4>(nr);
   D4* rom_c = b.take<D4>(nr);
   D4* rdg_c = b.take<D4>(nr);
-  int* cstamp = b.take<int>(np);
   int* rxn_cnt = b.take<int>(nr ? np : 1);
   int2* rxn_slot = b.take<int2>(nr ? (size_t)RXN_CAP * np : 1);
+  int* act_list = b.take<int>(nr ? (size_t)nr * ACT_ROUNDS * 64 : 1);
+  int2* act_meta = b.take<int2>(nr ? nr : 1);
+  double* act_sum = b.take<double>(nr ? 8 * (size_t)nr : 1);
   int64_t* dstep = b.take<int64_t>(1);
-  int* dstamp = b.take<int>(1);
   int *ctc0 = b.take<int>(nr), *ctc1 = b.take<int>(nr);
   int *ctp0 = b.take<int>(nr * z.maxc), *ctp1 = b.take<int>(nr * z.maxc);
   double *ctd0 = b.take<double>(3 * nr * z.maxc), *ctd1 = b.take<double>(3 * nr * z.maxc);
@@ -313,11 +317,12 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
     d.rvel_c = rvel_c;
     d.rom_c = rom_c;
     d.rdg_c = rdg_c;
-    d.cstamp = cstamp;
     d.rxn_cnt = rxn_cnt;
     d.rxn_slot = rxn_slot;
+    d.act_list = act_list;
+    d.act_meta = act_meta;
+    d.act_sum = act_sum;
     d.dstep = dstep;
-    d.dstamp = dstamp;
   }
   return total;
 }
@@ -565,6 +570,7 @@ struct Prof {
 void run_build(sdpdem_system* s, hipStream_t st) {
   Dev& d = s->d;
   const int nc = d.ncells_all;
+  s->rxn_valid = false;  // the sorted order changes
   {
     Prof pr(s, SDPDEM_K_BIN, st);
     launch_fill_i32(d.count, 0, (size_t)nc, st);
@@ -605,11 +611,17 @@ bool rigid_active(const sdpdem_system* s) {
   return s->d.nr > 0 && s->step >= s->P.itr_actv_rigid;
 }
 
-// (a5)-(a9): one force evaluation (Alg. 2) and, if asked, the update.
-void run_pass(sdpdem_system* s, int velver, int commit, bool integrate, hipStream_t st) {
+// whether the coming pass refills the reaction's slots (its pass_prep then
+// clears their counts): after a neighbour build, or when they are stale
+bool needs_fill(const sdpdem_system* s, bool build) {
+  return rigid_active(s) && (build || !s->rxn_valid);
+}
+
+// (a5)-(a9): one force evaluation (Alg. 2) and, if asked, the update; fill
+// as needs_fill said before the pass's pass_prep.
+void run_pass(sdpdem_system* s, int velver, int commit, bool integrate, bool fill,
+              hipStream_t st) {
   Dev& d = s->d;
-  // the pass's stamp (set by launch_pass_prep) marks the fluid particles
-  // coupled in it
   {
     Prof pr(s, SDPDEM_K_FLUID_FORCES, st);
     launch_fluid_forces(d, s->noise, st);
@@ -622,7 +634,8 @@ void run_pass(sdpdem_system* s, int velver, int commit, bool integrate, hipStrea
     }
     {
       Prof pr(s, SDPDEM_K_FPI_ACTION, st);
-      launch_fpi_action(d, st);
+      launch_fpi_action(d, fill, st);
+      if (fill) s->rxn_valid = true;
     }
     {
       Prof pr(s, SDPDEM_K_FPI_REACTION, st);
@@ -733,9 +746,7 @@ int create_impl(const sdpdem_params* params, const sdpdem_box* boxes, int nbox,
                        hipMemcpyHostToDevice, st) == hipSuccess;
   {
     const int64_t step0 = params->itr_start;
-    const int stamp0 = 0;
     ok &= hipMemcpyAsync(d.dstep, &step0, sizeof(int64_t), hipMemcpyHostToDevice, st) == hipSuccess;
-    ok &= hipMemcpyAsync(d.dstamp, &stamp0, sizeof(int), hipMemcpyHostToDevice, st) == hipSuccess;
   }
   if (z.nr) {
     ok &= hipMemcpyAsync(d.rig_gid, hrg.data(), sizeof(int) * z.nr, hipMemcpyHostToDevice, st) == hipSuccess;
@@ -749,7 +760,7 @@ int create_impl(const sdpdem_params* params, const sdpdem_box* boxes, int nbox,
   launch_fill_i32(s->ct_cnt[0], 0, (size_t)z.nr, st);
   launch_fill_i32(s->ct_cnt[1], 0, (size_t)z.nr, st);
   launch_fill_i32(d.status, 0, 64, st);
-  launch_fill_i32(d.cstamp, 0, (size_t)z.npad, st);
+  if (z.nr) launch_fill_i32(d.rxn_cnt, 0, (size_t)z.npad, st);
   launch_fill_i32(reinterpret_cast<int*>(d.fout), 0, 13 * (size_t)z.npad, st);
   launch_fill_i32(d.nbr_cnt, 0, (size_t)z.npad, st);
   launch_fill_i32(d.cstart, 0, (size_t)z.ncells_all + 1, st);
@@ -835,16 +846,19 @@ namespace {
 // One iteration of Algorithm 1 (enqueue only).
 void step_body(sdpdem_system* s, hipStream_t st) {
   Dev& d = s->d;
-  // Lees-Edwards offsets for positions at this step and after the drift,
-  // the pass stamp, the reaction's counts
-  launch_pass_prep(d, s->boxes, 0, 1, rigid_active(s), st);
+  // Lees-Edwards offsets for positions at this step and after the drift;
+  // the reaction's counts when the pass refills its slots
+  const bool fill1 = needs_fill(s, !s->cache_valid);
+  launch_pass_prep(d, s->boxes, 0, fill1, st);
   if (!s->cache_valid) run_build(s, st);
-  run_pass(s, 1, 0, true, st);
+  run_pass(s, 1, 0, true, fill1, st);
   // positions moved: sort, neighbours, density and smoothing at x(n+1);
-  // they stay valid for the first pass of the next step
-  launch_pass_prep(d, s->boxes, 1, 2, rigid_active(s), st);
+  // they (and the coupling slots) stay valid for the first pass of the
+  // next step
+  const bool fill2 = needs_fill(s, true);
+  launch_pass_prep(d, s->boxes, 1, fill2, st);
   run_build(s, st);
-  run_pass(s, 2, 1, true, st);
+  run_pass(s, 2, 1, true, fill2, st);
   if (s->stress) {
     launch_box_stress(d, 1, st);
     s->stress_samples += 1;
@@ -859,13 +873,14 @@ void drop_graph(sdpdem_system* s) {
 }
 
 // Capture graph_steps steps into one executable graph.  Every per-step
-// value the kernels need (step number, pass stamps, Lees-Edwards offsets)
+// value the kernels need (step number, Lees-Edwards offsets)
 // lives in device memory, and the host-side buffer swaps repeat with
 // period two, so an even number of captured steps replays correctly.
 bool capture(sdpdem_system* s, hipStream_t st) {
   drop_graph(s);
   const int64_t step0 = s->step, samples0 = s->stress_samples;
   const int cur0 = s->cur, ct0 = s->ct_cur;
+  const bool rxn0 = s->rxn_valid;
   hipGraph_t g = nullptr;
   if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
   for (int k = 0; k < s->graph_steps; ++k) step_body(s, st);
@@ -873,6 +888,7 @@ bool capture(sdpdem_system* s, hipStream_t st) {
   // nothing ran yet: restore the host mirror of the device state
   s->step = step0;
   s->stress_samples = samples0;
+  s->rxn_valid = rxn0;
   if (s->cur != cur0 || s->ct_cur != ct0) {
     if (g) (void)hipGraphDestroy(g);
     return false;
@@ -884,6 +900,7 @@ bool capture(sdpdem_system* s, hipStream_t st) {
   if (!inst) return false;
   s->gexec = ex;
   s->g_act = rigid_active(s);
+  s->g_rxn = rxn0;
   s->g_stress = s->stress;
   s->g_cur = s->cur;
   s->g_ct = s->ct_cur;
@@ -905,16 +922,18 @@ int sdpdem_step(sdpdem_system* s, int64_t nsteps, void* hip_stream) {
     const bool act_stable =
         s->d.nr == 0 || s->step >= s->P.itr_actv_rigid || s->step + K <= s->P.itr_actv_rigid;
     if (K > 0 && left >= K && s->cache_valid && s->prof_kernel == SDPDEM_K_NONE && act_stable) {
-      // the graph bakes in the double buffers' roles: an odd number of
-      // eager steps since the capture swaps them, so capture again
+      // the graph bakes in the double buffers' roles (an odd number of
+      // eager steps since the capture swaps them) and whether its first
+      // pass refills the coupling slots: capture again when either differs
       if (!s->gexec || s->g_act != act_now || s->g_stress != s->stress || s->g_cur != s->cur ||
-          s->g_ct != s->ct_cur) {
+          s->g_ct != s->ct_cur || s->g_rxn != s->rxn_valid) {
         if (!capture(s, st)) {
           s->graph_steps = 0;  // capture unavailable: stay eager
           continue;
         }
       }
       if (hipGraphLaunch(s->gexec, st) != hipSuccess) return SDPDEM_E_HIP;
+      s->rxn_valid = act_now;  // the last pass built and (with the coupling) refilled
       s->step += K;
       if (s->stress) s->stress_samples += K;
       left -= K;
@@ -936,12 +955,13 @@ int sdpdem_set_graph(sdpdem_system* s, int steps_per_graph) {
 int sdpdem_compute_forces(sdpdem_system* s, void* hip_stream) {
   if (!s) return SDPDEM_E_INVALID_ARG;
   hipStream_t st = (hipStream_t)hip_stream;
-  launch_pass_prep(s->d, s->boxes, 0, 0, rigid_active(s), st);
+  const bool fill = needs_fill(s, !s->cache_valid);
+  launch_pass_prep(s->d, s->boxes, 0, fill, st);
   if (!s->cache_valid) {
     run_build(s, st);
     s->cache_valid = true;
   }
-  run_pass(s, 1, 0, false, st);
+  run_pass(s, 1, 0, false, fill, st);
   if (s->stress) launch_box_stress(s->d, 0, st);
   return sync_status(s, st);
 }

@@ -14,6 +14,9 @@ static constexpr int BS = 256;  // threads per block of the particle kernels
 // coupling slots per fluid particle: the spheres whose support holds it,
 // each with its kernel weight, filled by the action for the reaction
 static constexpr int RXN_CAP = 16;
+// candidate rounds (64 lanes each) of a sphere's coupling search that the
+// action records for the next pass; a longer search is repeated instead
+static constexpr int ACT_ROUNDS = 16;
 
 enum : uint8_t { T_FLUID = 0, T_RIGID = 1, T_INNER = 2, T_OUTER = 3 };
 
@@ -168,14 +171,19 @@ struct Dev {
   D4* rvel_c;
   D4* rom_c;
   D4* rdg_c;       // F^DG / Omega x Lucy normalisation of H_s; w = 1/H_s (0: no coupling)
-  // fluid particles coupled to a sphere in the current pass carry the stamp
-  int* cstamp;
-  int* rxn_cnt;    // spheres that coupled to the particle in this pass
+  // the coupling pairs of the current positions and order (filled by the
+  // action of the first pass after a neighbour build, cleared before it):
+  int* rxn_cnt;    // spheres whose support holds the particle (0: uncoupled)
   int2* rxn_slot;  // [RXN_CAP][npad]: (cell-ordered sphere record, FP32 Lucy polynomial)
-  // device-resident counters (so that a captured graph replays correctly):
-  // the step number and the stamp of the current pass
+  // per cell-ordered sphere record: the fluid particle of every lane and
+  // round of its search (-1: none), and (rounds or -1, rigid centres in H_s)
+  int* act_list;  // [nr][ACT_ROUNDS * 64]
+  int2* act_meta;
+  // per cell-ordered sphere record: the action's sums Omega_s, sum w v (3),
+  // sum w (F^C + F^D) (3) and the lever sum w r_z, for the finishing kernel
+  double* act_sum;  // [nr][8]
+  // device-resident step number (so that a captured graph replays correctly)
   int64_t* dstep;
-  int* dstamp;
   int* ct_cnt;      // current contact table
   int* ct_partner;  // partner id
   double* ct_dt;
@@ -203,17 +211,17 @@ void launch_permute(const Dev& d, const D4* spos, const D4* svel, const D4* som,
                     const uint8_t* stype, const int* sgid, hipStream_t st);
 void launch_build_density(const Dev& d, hipStream_t st);
 // start of a pass: Lees-Edwards offsets of every box for positions at step
-// *dstep + add, the pass stamp 4 step + code + 1 (code 1, 2: passes of a
-// step; 0: a force evaluation without update) and, with clear_rxn, the
-// reaction's slot counts set to zero
-void launch_pass_prep(const Dev& d, BoxD* boxes, int add, int code, bool clear_rxn,
-                      hipStream_t st);
+// *dstep + add and, with clear_rxn, the reaction's slot counts set to zero
+void launch_pass_prep(const Dev& d, BoxD* boxes, int add, bool clear_rxn, hipStream_t st);
 // per-box sample of P_zx; with accumulate, also added to the running sums
 void launch_box_stress(const Dev& d, int accumulate, hipStream_t st);
 void launch_smooth(const Dev& d, hipStream_t st);
 void launch_fluid_forces(const Dev& d, bool noise, hipStream_t st);
 void launch_rigid_gather(const Dev& d, hipStream_t st);
-void launch_fpi_action(const Dev& d, hipStream_t st);
+// the coupling action (the per-sphere gather, then the per-sphere drag and
+// pressure-gradient algebra); with fill it also refills the reaction's
+// slots (counts cleared) and the candidate lists
+void launch_fpi_action(const Dev& d, bool fill, hipStream_t st);
 void launch_fpi_reaction(const Dev& d, hipStream_t st);
 void launch_dem(const Dev& d, int commit, int* nxt_cnt, int* nxt_partner, double* nxt_dt,
                 hipStream_t st);

@@ -100,14 +100,13 @@ void launch_bin_rigid(const Dev& d, hipStream_t st) {
 
 // The start of a pass, one launch: the Lees-Edwards offsets
 // delta(t) = fmod(shear L_z t, L_x) of every box for positions at step
-// *dstep + add and at the step after, the pass stamp 4 step + code + 1, and
-// (when the coupling runs) the reaction's slot counts cleared.
-__global__ void k_pass_prep(BoxD* boxes, int nbox, const int64_t* dstep, int* dstamp, int add,
-                            int code, double dt, int* rxn_cnt, int nfill) {
+// *dstep + add and at the step after and (when the pass refills the
+// coupling slots) the reaction's slot counts cleared.
+__global__ void k_pass_prep(BoxD* boxes, int nbox, const int64_t* dstep, int add, double dt,
+                            int* rxn_cnt, int nfill) {
 #pragma clang fp contract(off)
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t step = dstep[0];
-  if (tid == 0) dstamp[0] = (int)(4 * step + code + 1);
   if (rxn_cnt && 4 * tid < nfill) {
     if (4 * tid + 4 <= nfill)
       *reinterpret_cast<int4*>(rxn_cnt + 4 * tid) = make_int4(0, 0, 0, 0);
@@ -133,12 +132,11 @@ __global__ void k_pass_prep(BoxD* boxes, int nbox, const int64_t* dstep, int* ds
   }
 }
 
-void launch_pass_prep(const Dev& d, BoxD* boxes, int add, int code, bool clear_rxn,
-                      hipStream_t st) {
+void launch_pass_prep(const Dev& d, BoxD* boxes, int add, bool clear_rxn, hipStream_t st) {
   const int nfill = clear_rxn ? d.npad : 0;  // rxn_cnt is 256-byte aligned
   const int threads = max(d.nbox, (nfill + 3) / 4);
   k_pass_prep<<<(unsigned)max(1, (threads + BS - 1) / BS), BS, 0, st>>>(
-      boxes, d.nbox, d.dstep, d.dstamp, add, code, d.dt, clear_rxn ? d.rxn_cnt : nullptr, nfill);
+      boxes, d.nbox, d.dstep, add, d.dt, clear_rxn ? d.rxn_cnt : nullptr, nfill);
 }
 
 
@@ -335,10 +333,17 @@ void launch_rigid_gather(const Dev& d, hipStream_t st) {
 // (a6) fluid-particle action: one wavefront per rigid particle gathers the
 // fluid inside H_s = R_s + h (Sec. 2.4): Omega_s, the W-weighted fluid
 // velocity, the W-weighted F^C + F^D of the neighbours and the number of
-// other rigid centres inside H_s, then forms eps, F^DG and F^PG.  The cell
-// rows of the search box are contiguous slices of the sorted arrays; the
-// wave walks their concatenation with one candidate per lane, and stamps
-// every fluid particle it couples to, so that the reaction visits only those.
+// other rigid centres inside H_s (k_fpi_finish then forms eps, F^DG and
+// F^PG from them).  The cell rows of the search box are contiguous slices of the sorted arrays; the
+// wave walks their concatenation with one candidate per lane.  With FILL it
+// also hands every coupled fluid particle a slot (sphere record, kernel
+// weight) for the reaction and records, round by round and lane by lane,
+// which fluid particle each lane coupled to.  Both depend only on the
+// positions and the sorted order, so the pass after a neighbour build fills
+// them and the next pass (same positions, same order) reuses them: the
+// slot counter's atomics miss the L2 and travel to memory, and the recorded
+// rounds replace the cell search, with every lane summing the same terms
+// in the same order.
 
 __device__ double drag_b(double eps, double dv, double dd, double rho, double mu) {
   // beta / (1 - eps) of the Ergun (eps <= 0.8) and Wen-Yu branches
@@ -360,8 +365,7 @@ __device__ __forceinline__ int wave_sum_i(int v) {
   return v;
 }
 
-// cells to search around a point for partners within H (largest over the axes)
-template <bool STRESS>
+template <bool STRESS, bool FILL>
 __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
   const int wave = xcd_wave();
   const int lane = threadIdx.x & 63;
@@ -371,94 +375,131 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
   const int si = d.rig_sorted[s];
   const BoxD& B = d.boxes[__builtin_amdgcn_readfirstlane(d.rbox[s])];
   const Geo G = geo_of(B);
-  const Grid gr = B.g;
-  const int coff = B.cell_off;
   const D4 ps = d.pos[si];
   const double R = ps.w, H = R + d.h, H2 = H * H;
   const double invH = 1.0 / H, wnorm = 105.0 / (16.0 * PI * H * H * H);  // Eq. kernel
-  int oob = 0;
-  const int cc[3] = {cell_coord(ps.x, gr, 0, &oob), cell_coord(ps.y, gr, 1, &oob),
-                     cell_coord(ps.z, gr, 2, &oob)};
-  const int kr = reach_cells(gr, H);
   const size_t np = (size_t)d.npad;
-  const int stamp = d.dstamp[0];
+  int* const list = d.act_list + (size_t)wave * (ACT_ROUNDS * 64);
   double om = 0, v0 = 0, v1 = 0, v2 = 0, f0 = 0, f1 = 0, f2 = 0, l2 = 0;
   int nrig = 0;
-  // the search box row by row: lane r takes row r of each batch of 64 rows
-  // (at most two runs of consecutive cells per row)
-  const StencilShape sh = stencil_shape(gr, cc, kr);
-  const int nrows = sh.zn * sh.yn;
-  for (int rb = 0; rb < nrows; rb += 64) {
-    int sa = 0, la = 0, sb = 0, lb = 0;
-    if (rb + lane < nrows) {
-      int a0, a1, b0, b1;
-      stencil_row<true>(G, gr, coff, ps.x, ps.y, ps.z, H, cc, kr, sh, rb + lane, a0, a1, b0,
-                        b1);
-      if (a1 > a0) {
-        sa = d.cstart[a0];
-        la = d.cstart[a1] - sa;
-      }
-      if (b1 > b0) {
-        sb = d.cstart[b0];
-        lb = d.cstart[b1] - sb;
-      }
-    }
-    const int len = la + lb;
-    int inc = len;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      int t = __shfl_up(inc, o, 64);
-      if (lane >= o) inc += t;
-    }
-    const int total = __shfl(inc, 63, 64);
-    const int off = inc - len;
-    // every lane takes one candidate of the concatenated runs per round;
-    // all lanes stay active through the shuffles
-    for (int base = 0; base < total; base += 64) {
-      const int t = base + lane;
-      int r = 0;  // last run whose offset is <= t
-#pragma unroll
-      for (int stp = 32; stp > 0; stp >>= 1) {
-        int cand = r + stp;
-        int v = __shfl(off, cand & 63, 64);
-        if (cand < 64 && v <= t) r = cand;
-      }
-      const int offr = __shfl(off, r, 64);
-      const int sar = __shfl(sa, r, 64);
-      const int lar = __shfl(la, r, 64);
-      const int sbr = __shfl(sb, r, 64);
-      if (t >= total) continue;
-      const int q = t - offr;
-      const int j = q < lar ? sar + q : sbr + (q - lar);
-      if (j == si) continue;
-      uint8_t tj = d.type[j];
-      if (tj != T_FLUID && tj != T_RIGID) continue;
-      D4 pj = d.pos[j];
-      double ex = ps.x - pj.x, ey = ps.y - pj.y, ez = ps.z - pj.z;
-      const int kz = min_img_box(G, ex, ey, ez);
-      double r2 = r2_exact(ex, ey, ez);
-      if (!(r2 < H2)) continue;
-      if (tj == T_RIGID) {
-        ++nrig;
-        continue;
-      }
-      const double qh = sqrt(r2) * invH, omq = 1.0 - qh;
-      const double pw = (1.0 + 3.0 * qh) * omq * omq * omq;
-      const double w = wnorm * pw;
+  // the pair geometry of fluid candidate j: image separation, its z image
+  // and r^2 (the same operations on both paths, so the sums agree bit for bit)
+  auto geom = [&](int j, double& ez, int& kz) {
+    const D4 pj = d.pos[j];
+    double ex = ps.x - pj.x, ey = ps.y - pj.y;
+    ez = ps.z - pj.z;
+    kz = min_img_box(G, ex, ey, ez);
+    return r2_exact(ex, ey, ez);
+  };
+  // one coupled fluid particle
+  auto couple = [&](int j, double r2, double ez, int kz) {
+    const double qh = sqrt(r2) * invH, omq = 1.0 - qh;
+    const double pw = (1.0 + 3.0 * qh) * omq * omq * omq;
+    const double w = wnorm * pw;
+    if (FILL) {
       // hand the pair to the reaction: one slot of j (the arrival order
       // does not matter, the reaction sums its slots by sphere record)
       const int slot = atomicAdd(&d.rxn_cnt[j], 1);
-      if (slot < RXN_CAP) d.rxn_slot[(size_t)slot * np + j] = make_int2(wave, __float_as_int((float)pw));
-      D4 vj = d.vel[j];
-      om += w;
-      v0 += w * (vj.x + (double)kz * G.le_jump);  // image velocity (Lees-Edwards)
-      v1 += w * vj.y;
-      v2 += w * vj.z;
-      f0 += w * (double)d.fout[6 * np + j];
-      f1 += w * (double)d.fout[7 * np + j];
-      f2 += w * (double)d.fout[8 * np + j];
-      if (STRESS) l2 += w * ez;  // the coupling's lever (z part)
-      d.cstamp[j] = stamp;
+      if (slot < RXN_CAP)
+        d.rxn_slot[(size_t)slot * np + j] = make_int2(wave, __float_as_int((float)pw));
+    }
+    const D4 vj = d.vel[j];
+    om += w;
+    v0 += w * (vj.x + (double)kz * G.le_jump);  // image velocity (Lees-Edwards)
+    v1 += w * vj.y;
+    v2 += w * vj.z;
+    f0 += w * (double)d.fout[6 * np + j];
+    f1 += w * (double)d.fout[7 * np + j];
+    f2 += w * (double)d.fout[8 * np + j];
+    if (STRESS) l2 += w * ez;  // the coupling's lever (z part)
+  };
+  const int2 meta = FILL ? make_int2(-1, 0) : d.act_meta[wave];
+  const int stored = __builtin_amdgcn_readfirstlane(meta.x);
+  int rounds = 0;  // candidate rounds of the cell search
+  if (!FILL && stored >= 0) {
+    // the pass after the fill: the same candidates in the same lanes and
+    // rounds, read from the list (no cell search, no rejections)
+    for (int r = 0; r < stored; ++r) {
+      const int j = list[r * 64 + lane];
+      if (j < 0) continue;
+      double ez;
+      int kz;
+      const double r2 = geom(j, ez, kz);
+      couple(j, r2, ez, kz);
+    }
+    nrig = lane == 0 ? meta.y : 0;
+  } else {
+    const Grid gr = B.g;
+    const int coff = B.cell_off;
+    int oob = 0;
+    const int cc[3] = {cell_coord(ps.x, gr, 0, &oob), cell_coord(ps.y, gr, 1, &oob),
+                       cell_coord(ps.z, gr, 2, &oob)};
+    const int kr = reach_cells(gr, H);
+    // the search box row by row: lane r takes row r of each batch of 64 rows
+    // (at most two runs of consecutive cells per row)
+    const StencilShape sh = stencil_shape(gr, cc, kr);
+    const int nrows = sh.zn * sh.yn;
+    for (int rb = 0; rb < nrows; rb += 64) {
+      int sa = 0, la = 0, sb = 0, lb = 0;
+      if (rb + lane < nrows) {
+        int a0, a1, b0, b1;
+        stencil_row<true>(G, gr, coff, ps.x, ps.y, ps.z, H, cc, kr, sh, rb + lane, a0, a1, b0,
+                          b1);
+        if (a1 > a0) {
+          sa = d.cstart[a0];
+          la = d.cstart[a1] - sa;
+        }
+        if (b1 > b0) {
+          sb = d.cstart[b0];
+          lb = d.cstart[b1] - sb;
+        }
+      }
+      const int len = la + lb;
+      int inc = len;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += t;
+      }
+      const int total = __shfl(inc, 63, 64);
+      const int off = inc - len;
+      // every lane takes one candidate of the concatenated runs per round;
+      // all lanes stay active through the shuffles
+      for (int base = 0; base < total; base += 64, ++rounds) {
+        const int t = base + lane;
+        int r = 0;  // last run whose offset is <= t
+#pragma unroll
+        for (int stp = 32; stp > 0; stp >>= 1) {
+          int cand = r + stp;
+          int v = __shfl(off, cand & 63, 64);
+          if (cand < 64 && v <= t) r = cand;
+        }
+        const int offr = __shfl(off, r, 64);
+        const int sar = __shfl(sa, r, 64);
+        const int lar = __shfl(la, r, 64);
+        const int sbr = __shfl(sb, r, 64);
+        int rec = -1;  // the fluid particle this lane couples to in this round
+        if (t < total) {
+          const int q = t - offr;
+          const int j = q < lar ? sar + q : sbr + (q - lar);
+          // (the sphere itself is neither partner nor fluid)
+          const uint8_t tj = j != si ? d.type[j] : (uint8_t)T_INNER;
+          if (tj == T_FLUID || tj == T_RIGID) {
+            double ez;
+            int kz;
+            const double r2 = geom(j, ez, kz);
+            if (r2 < H2) {
+              if (tj == T_RIGID) {
+                ++nrig;
+              } else {
+                couple(j, r2, ez, kz);
+                rec = j;
+              }
+            }
+          }
+        }
+        if (FILL && rounds < ACT_ROUNDS) list[rounds * 64 + lane] = rec;
+      }
     }
   }
   om = wave_sum(om);
@@ -471,6 +512,34 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
   if (STRESS) l2 = wave_sum(l2);
   nrig = wave_sum_i(nrig);
   if (lane != 0) return;
+  // the list of this fill (-1: more rounds than it holds, search again)
+  if (FILL) d.act_meta[wave] = make_int2(rounds <= ACT_ROUNDS ? rounds : -1, nrig);
+  double* out = d.act_sum + 8 * (size_t)wave;
+  out[0] = om;
+  out[1] = v0;
+  out[2] = v1;
+  out[3] = v2;
+  out[4] = f0;
+  out[5] = f1;
+  out[6] = f2;
+  out[7] = l2;
+}
+
+// (a6, second half) one thread per sphere, in cell order: eps, F^DG and
+// F^PG from the sums its action wave left (the per-sphere FP64 algebra,
+// divisions and powers, runs here with every lane busy instead of on one
+// lane of each action wave)
+template <bool STRESS>
+__global__ __launch_bounds__(BS) void k_fpi_finish(Dev d) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= d.nr) return;
+  const int s = d.ritems[t];
+  const int si = d.rig_sorted[s];
+  const double R = d.pos[si].w, H = R + d.h;
+  const double invH = 1.0 / H, wnorm = 105.0 / (16.0 * PI * H * H * H);  // Eq. kernel
+  const double* a = d.act_sum + 8 * (size_t)t;
+  const double om = a[0], v0 = a[1], v1 = a[2], v2 = a[3], f0 = a[4], f1 = a[5], f2 = a[6];
+  const int nrig = d.act_meta[t].y;
   const double Vs = 4.0 / 3.0 * PI * R * R * R;
   const double VH = 4.0 / 3.0 * PI * H * H * H;
   double eps = 1.0 - Vs * (double)nrig / VH;
@@ -484,18 +553,18 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
     double dva = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
     double B_ = drag_b(eps, dva, 2.0 * R, d.rho0, d.eta);
     double kp = d.rho0 * Vs / d.m_f;
-    for (int a = 0; a < 3; ++a) dg[a] = -B_ * Vs * dv[a];
+    for (int k = 0; k < 3; ++k) dg[k] = -B_ * Vs * dv[k];
     pg[0] = kp * (f0 / om);
     pg[1] = kp * (f1 / om);
     pg[2] = kp * (f2 / om);
   }
-  for (int a = 0; a < 3; ++a) {
-    d.f_dg[3 * s + a] = dg[a];
-    d.f_pg[3 * s + a] = pg[a];
+  for (int k = 0; k < 3; ++k) {
+    d.f_dg[3 * s + k] = dg[k];
+    d.f_pg[3 * s + k] = pg[k];
   }
   // virial of the coupling: lever (sum_j w_sj r_sj / Omega_s)_z times the
   // x force; the contacts add theirs later in the pass
-  if (STRESS) d.wzx_r[s] = om > 0.0 ? (l2 / om) * (dg[0] + pg[0]) : 0.0;
+  if (STRESS) d.wzx_r[s] = om > 0.0 ? (a[7] / om) * (dg[0] + pg[0]) : 0.0;
   // F^DG / Omega times the kernel's normalisation beside the sphere's
   // cell-ordered record, with 1/H_s (0: the sphere couples to nothing)
   D4 rc;
@@ -503,15 +572,19 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
   rc.y = om > 0.0 ? dg[1] / om * wnorm : 0.0;
   rc.z = om > 0.0 ? dg[2] / om * wnorm : 0.0;
   rc.w = om > 0.0 ? invH : 0.0;
-  d.rdg_c[wave] = rc;
+  d.rdg_c[t] = rc;
 }
 
-void launch_fpi_action(const Dev& d, hipStream_t st) {
+void launch_fpi_action(const Dev& d, bool fill, hipStream_t st) {
   if (d.nr == 0) return;
-  (d.stress ? k_fpi_action<true> : k_fpi_action<false>)<<<nblocks((size_t)d.nr * 64), BS, 0, st>>>(d);
+  auto k = d.stress ? (fill ? k_fpi_action<true, true> : k_fpi_action<true, false>)
+                    : (fill ? k_fpi_action<false, true> : k_fpi_action<false, false>);
+  k<<<nblocks((size_t)d.nr * 64), BS, 0, st>>>(d);
+  auto f = d.stress ? k_fpi_finish<true> : k_fpi_finish<false>;
+  f<<<(d.nr + BS - 1) / BS, BS, 0, st>>>(d);
 }
 
-// (a7) reaction on the stamped fluid particles, Eq. F_fpi_DG_reac
+// (a7) reaction on the coupled fluid particles, Eq. F_fpi_DG_reac
 // normalised per rigid particle: -sum_s F^DG_s w_sj / Omega_s over the
 // rigid s with j in C_s.  The rigid grid's cells are at least H_max wide.
 __global__ __launch_bounds__(BS) void k_fpi_reaction(Dev d) {
@@ -520,9 +593,11 @@ __global__ __launch_bounds__(BS) void k_fpi_reaction(Dev d) {
   if (b < 0) return;
   const BoxD& B = d.boxes[b];
   if (i >= B.first + B.count) return;
-  if (d.cstamp[i] != d.dstamp[0] || d.type[i] != T_FLUID) return;
-  const size_t np = (size_t)d.npad;
+  // the action's slot count: nonzero exactly for the fluid particles
+  // inside some sphere's support
   const int c = d.rxn_cnt[i];
+  if (c == 0) return;
+  const size_t np = (size_t)d.npad;
   double a0 = 0, a1 = 0, a2 = 0;
   if (c <= RXN_CAP) {
     // the slots the action left, summed in ascending sphere-record order
@@ -833,8 +908,7 @@ __device__ __forceinline__ void total_force(const Dev& d, const BoxD& B, int i, 
   for (int a = 0; a < 3; ++a) {
     double body = m * d.body[a] * sg;
     if (t == T_FLUID) {
-      double rx = (d.have_rxn && d.cstamp[i] == d.dstamp[0]) ? (double)d.fout[(9 + a) * np + i]
-                                                              : 0.0;
+      double rx = (d.have_rxn && d.rxn_cnt[i] > 0) ? (double)d.fout[(9 + a) * np + i] : 0.0;
       F[a] = (double)d.fout[a * np + i] + rx + body;
       N[a] = (double)d.fout[(3 + a) * np + i];
     } else if (t == T_INNER) {
@@ -1054,7 +1128,7 @@ __global__ __launch_bounds__(BS) void k_read_field(Dev d, int field, int rigid_a
     case SDPDEM_F_CD:
     case SDPDEM_F_RXN: {
       int base = field == SDPDEM_F_SDPD ? 0 : field == SDPDEM_N_SDPD ? 3 : field == SDPDEM_F_CD ? 6 : 9;
-      if (field != SDPDEM_F_RXN || (d.have_rxn && d.cstamp[i] == d.dstamp[0]))
+      if (field != SDPDEM_F_RXN || (d.have_rxn && d.rxn_cnt[i] > 0))
         for (int a = 0; a < 3; ++a) v[a] = (double)d.fout[(base + a) * np + i];
     } break;
     case SDPDEM_F_DG:

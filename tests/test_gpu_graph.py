@@ -1,6 +1,7 @@
 """Steps replayed from a captured HIP graph give the same bits as eager
-steps: the step counter, pass stamps and Lees-Edwards offsets live in
-device memory and the buffer swaps repeat with period two.  Replays are
+steps: the step counter and Lees-Edwards offsets live in device memory,
+the buffer swaps repeat with period two, and a graph records whether its
+first pass refills the coupling slots.  Replays are
 interleaved with eager work and reads, and cross the rigid activation."""
 import numpy as np
 import pytest

@@ -116,6 +116,26 @@ def test_contacts_and_forces_follow_oracle(S, oracle_lib):
         assert_force_field(g2, o2, f)
 
 
+def test_reused_coupling_slots_match_a_fresh_fill(S):
+    """A force evaluation right after a step reuses the coupling slots the
+    step's last pass filled (same positions, same sorted order); a system
+    created from the same state fills them afresh.  Same bits."""
+    print("[case] coupling slots reused vs refilled", flush=True)
+    p, parts = _colliding_spheres()
+    g = S.System(p, parts)
+    g.step(7)
+    g.compute_forces()
+    state = {k: np.array(v, copy=True) for k, v in parts.items()}
+    state["pos"], state["vel"], state["angvel"] = (g.read_field(f) for f in ("POS", "VEL", "ANGVEL"))
+    pairs, dts = g.read_contacts()
+    f = S.System(dict(p, itr_start=g.current_step), state)
+    f.load_contacts(pairs, dts)
+    f.compute_forces()
+    assert np.any(g.read_field("F_RXN"))
+    for fld in ("F_RXN", "F_DG", "F_PG", "EPS", "F_SDPD"):
+        assert np.array_equal(g.read_field(fld), f.read_field(fld)), fld
+
+
 def test_restart_is_bit_exact(S):
     print("[case] restart", flush=True)
     p, parts = _colliding_spheres(lub=1)
