@@ -188,7 +188,13 @@ int sdpdem_create_batch(const sdpdem_params* params, const sdpdem_box* boxes, in
                         sdpdem_system** out);
 
 /* Algorithm 1: nsteps steps of two velocity-Verlet passes each.  Returns the
- * device status (overflow, non-finite, out of domain) seen at the end. */
+ * device status (overflow, non-finite, out of domain) seen at the end.
+ * With rigid particles the library keeps a second stream of its own (at
+ * the default priority) for work that does not depend on what runs beside
+ * it: the rigid grid beside the neighbour lists, the sphere records and DEM
+ * contacts beside the SDPD pair forces and the coupling.  It is forked from
+ * the caller's stream and joined back into it within the same build or
+ * pass, so work the caller orders on its stream sees everything. */
 int sdpdem_step(sdpdem_system* sys, int64_t nsteps, void* hip_stream);
 
 /* Replay the step loop from a captured HIP graph of steps_per_graph steps
@@ -251,7 +257,8 @@ int sdpdem_box_stress(sdpdem_system* sys, double* inst, double* sum, int64_t* ns
 
 /* Diagnostics: out = [n, n_rigid, cells x, y, z of box 0, rigid cells x,
  * y, z of box 0, max neighbour count of the last build, pairs of the last
- * build, number of boxes, 0...]. */
+ * build, number of boxes, steps replayed from captured graphs so far,
+ * 1 if the contacts run on the library's second stream, 0...]. */
 int sdpdem_info(sdpdem_system* sys, int64_t out[16], void* hip_stream);
 
 /* Time every launch of one kernel (enum sdpdem_kernel) with HIP events on

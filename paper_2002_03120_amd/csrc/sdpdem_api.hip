@@ -43,6 +43,17 @@ struct sdpdem_system {
   int graph_steps = 0;
   hipGraphExec_t gexec = nullptr;
   bool g_act = false, g_stress = false, g_rxn = false;
+  // a second stream of the library's own for work that does not depend on
+  // what runs beside it (the rigid grid, the sphere records, the contacts),
+  // forked from the caller's stream and joined back into it within the
+  // same build or pass (null: one stream)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_gather = nullptr, ev_join = nullptr;
+  int64_t graph_steps_run = 0;  // steps replayed from graphs so far
+  // the coming pass's sphere records and contacts are enqueued already
+  // (by the build), on the side stream if side_open, whose records event
+  // was recorded if gather_ok
+  bool rigid_issued = false, side_open = false, gather_ok = true;
   int g_cur = 0, g_ct = 0;  // buffer parity the graph was captured with
   BoxD* boxes = nullptr;  // device copy of the box table
   std::vector<BoxD> h_boxes;
@@ -222,7 +233,7 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
   double* n_dem = b.take<double>(3 * nr);
   double* eps = b.take<double>(nr);
   double* omega = b.take<double>(nr);
-  double* wzx_r = b.take<double>(nr);
+  double* wzx_r = b.take<double>(2 * nr);
   BoxD* boxes = b.take<BoxD>((size_t)z.nbox);
   int2* blk = b.take<int2>(z.blk.size());
   int* rbox = b.take<int>(nr);
@@ -567,7 +578,45 @@ struct Prof {
 
 // (a1)-(a4): sort by cell, permute the state, neighbours + density +
 // pressure, smoothing, and the rigid grid.
-void run_build(sdpdem_system* s, hipStream_t st) {
+// Order the side stream after everything enqueued on st so far; false
+// (nothing forked) without a side stream or when the events fail.
+bool fork_side(sdpdem_system* s, hipStream_t st) {
+  return s->side && hipEventRecord(s->ev_fork, st) == hipSuccess &&
+         hipStreamWaitEvent(s->side, s->ev_fork, 0) == hipSuccess;
+}
+
+// Order st after everything enqueued on the side stream so far.
+void join_side(sdpdem_system* s, hipStream_t st) {
+  if (hipEventRecord(s->ev_join, s->side) != hipSuccess ||
+      hipStreamWaitEvent(st, s->ev_join, 0) != hipSuccess)
+    (void)hipStreamSynchronize(s->side);  // no device-side wait: wait here
+}
+
+bool rigid_active(const sdpdem_system* s) {
+  return s->d.nr > 0 && s->step >= s->P.itr_actv_rigid;
+}
+
+// The coming pass's sphere records and contacts on stream rs (the side
+// stream when fk); false if the records' event could not be recorded.
+bool issue_rigid(sdpdem_system* s, hipStream_t rs, bool fk, int commit) {
+  Dev& d = s->d;
+  const int nx = s->ct_cur ^ 1;
+  {
+    Prof pr(s, SDPDEM_K_RIGID_GRID, rs);
+    launch_rigid_gather(d, rs);
+  }
+  const bool ok = !fk || hipEventRecord(s->ev_gather, rs) == hipSuccess;
+  {
+    Prof pr(s, SDPDEM_K_DEM, rs);
+    launch_dem(d, commit, s->ct_cnt[nx], s->ct_partner[nx], s->ct_dt[nx], rs);
+  }
+  return ok;
+}
+
+// The neighbour build; with commit_next >= 0 a force pass with that commit
+// flag follows at once, and the build already issues that pass's sphere
+// records and contacts (which need only the permuted state).
+void run_build(sdpdem_system* s, hipStream_t st, int commit_next) {
   Dev& d = s->d;
   const int nc = d.ncells_all;
   s->rxn_valid = false;  // the sorted order changes
@@ -589,6 +638,23 @@ void run_build(sdpdem_system* s, hipStream_t st) {
     Prof pr(s, SDPDEM_K_PERMUTE, st);
     launch_permute(d, s->pos[src], s->vel[src], s->om[src], s->type[src], s->gid[src], st);
   }
+  // the rigid grid, the sphere records and the contacts need the permuted
+  // state only: with a side stream they run there beside the neighbour
+  // lists and the pressure filter (the pass joins the side stream)
+  const bool fk = d.nr > 0 && fork_side(s, st);
+  hipStream_t rs = fk ? s->side : st;
+  if (d.nr > 0) {
+    Prof pr(s, SDPDEM_K_RIGID_GRID, rs);
+    launch_fill_i32(d.rcount, 0, (size_t)d.rncells_all, rs);
+    launch_bin_rigid(d, rs);
+    launch_scan(d.rcount, d.rncells_all, d.rstart, d.rcursor, s->rblock_sums, rs);
+    launch_scatter(d.rkey, d.nr, d.rcursor, d.ritems, rs);
+    launch_cell_sort(d.rstart, d.rncells_all, d.ritems, nullptr, rs);
+  }
+  if (commit_next >= 0 && rigid_active(s)) {
+    s->gather_ok = issue_rigid(s, rs, fk, commit_next);
+    s->rigid_issued = true;
+  }
   {
     Prof pr(s, SDPDEM_K_NEIGHBORS_DENSITY, st);
     launch_build_density(d, st);
@@ -597,18 +663,12 @@ void run_build(sdpdem_system* s, hipStream_t st) {
     Prof pr(s, SDPDEM_K_SMOOTH, st);
     launch_smooth(d, st);
   }
-  if (d.nr > 0) {
-    Prof pr(s, SDPDEM_K_RIGID_GRID, st);
-    launch_fill_i32(d.rcount, 0, (size_t)d.rncells_all, st);
-    launch_bin_rigid(d, st);
-    launch_scan(d.rcount, d.rncells_all, d.rstart, d.rcursor, s->rblock_sums, st);
-    launch_scatter(d.rkey, d.nr, d.rcursor, d.ritems, st);
-    launch_cell_sort(d.rstart, d.rncells_all, d.ritems, nullptr, st);
+  if (fk) {
+    if (s->rigid_issued)
+      s->side_open = true;
+    else
+      join_side(s, st);
   }
-}
-
-bool rigid_active(const sdpdem_system* s) {
-  return s->d.nr > 0 && s->step >= s->P.itr_actv_rigid;
 }
 
 // whether the coming pass refills the reaction's slots (its pass_prep then
@@ -622,16 +682,24 @@ bool needs_fill(const sdpdem_system* s, bool build) {
 void run_pass(sdpdem_system* s, int velver, int commit, bool integrate, bool fill,
               hipStream_t st) {
   Dev& d = s->d;
+  const bool act = rigid_active(s);
+  // The sphere records and the contacts need neither the SDPD forces nor
+  // the coupling, and the coupling needs the records but not the contacts:
+  // unless the build already issued them, they run on the side stream
+  // beside the pair forces (and the contacts beside the coupling chain).
+  bool fk = s->side_open;
+  if (act && !s->rigid_issued) {
+    fk = fork_side(s, st);
+    s->gather_ok = issue_rigid(s, fk ? s->side : st, fk, commit);
+  }
+  s->rigid_issued = false;
   {
     Prof pr(s, SDPDEM_K_FLUID_FORCES, st);
     launch_fluid_forces(d, s->noise, st);
   }
-  const bool act = rigid_active(s);
   if (act) {
-    {
-      Prof pr(s, SDPDEM_K_RIGID_GRID, st);
-      launch_rigid_gather(d, st);
-    }
+    if (fk && (!s->gather_ok || hipStreamWaitEvent(st, s->ev_gather, 0) != hipSuccess))
+      (void)hipStreamSynchronize(s->side);  // no device-side wait: wait here
     {
       Prof pr(s, SDPDEM_K_FPI_ACTION, st);
       launch_fpi_action(d, fill, st);
@@ -641,11 +709,10 @@ void run_pass(sdpdem_system* s, int velver, int commit, bool integrate, bool fil
       Prof pr(s, SDPDEM_K_FPI_REACTION, st);
       launch_fpi_reaction(d, st);
     }
-    {
-      Prof pr(s, SDPDEM_K_DEM, st);
-      int nx = s->ct_cur ^ 1;
-      launch_dem(d, commit, s->ct_cnt[nx], s->ct_partner[nx], s->ct_dt[nx], st);
-    }
+  }
+  if (fk) join_side(s, st);
+  s->side_open = false;
+  if (act) {
     if (commit) {
       s->ct_cur ^= 1;
       bind_current(s);
@@ -682,6 +749,30 @@ int sync_status(sdpdem_system* s, hipStream_t st) {
 
 
 namespace {
+
+void free_side_stream(sdpdem_system* s) {
+  for (hipEvent_t* e : {&s->ev_fork, &s->ev_gather, &s->ev_join}) {
+    if (*e) (void)hipEventDestroy(*e);
+    *e = nullptr;
+  }
+  if (s->side) (void)hipStreamDestroy(s->side);
+  s->side = nullptr;
+}
+
+// The side stream (default priority) and its events; without them every
+// build and pass stays on the caller's stream.
+void make_side_stream(sdpdem_system* s) {
+  if (hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking) != hipSuccess) {
+    s->side = nullptr;
+    return;
+  }
+  for (hipEvent_t* e : {&s->ev_fork, &s->ev_gather, &s->ev_join})
+    if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) {
+      *e = nullptr;
+      free_side_stream(s);
+      return;
+    }
+}
 
 int create_impl(const sdpdem_params* params, const sdpdem_box* boxes, int nbox,
                 const sdpdem_particles* q, const int32_t* box_of, void* d_workspace,
@@ -771,7 +862,7 @@ int create_impl(const sdpdem_params* params, const sdpdem_box* boxes, int nbox,
   launch_fill_f64(d.n_dem, 0.0, 3 * (size_t)z.nr, st);
   launch_fill_f64(d.eps, 0.0, (size_t)z.nr, st);
   launch_fill_f64(d.omega, 0.0, (size_t)z.nr, st);
-  launch_fill_f64(d.wzx_r, 0.0, (size_t)z.nr, st);
+  launch_fill_f64(d.wzx_r, 0.0, 2 * (size_t)z.nr, st);
   launch_fill_f64(d.st_inst, 0.0, (size_t)z.nbox, st);
   launch_fill_f64(d.st_sum, 0.0, (size_t)z.nbox, st);
   launch_fill_f64(d.rho, params->rho0, (size_t)z.npad, st);
@@ -782,6 +873,7 @@ int create_impl(const sdpdem_params* params, const sdpdem_box* boxes, int nbox,
     delete s;
     return SDPDEM_E_HIP;
   }
+  if (z.nr) make_side_stream(s);
   *out = s;
   return SDPDEM_OK;
 }
@@ -850,14 +942,14 @@ void step_body(sdpdem_system* s, hipStream_t st) {
   // the reaction's counts when the pass refills its slots
   const bool fill1 = needs_fill(s, !s->cache_valid);
   launch_pass_prep(d, s->boxes, 0, fill1, st);
-  if (!s->cache_valid) run_build(s, st);
+  if (!s->cache_valid) run_build(s, st, 0);
   run_pass(s, 1, 0, true, fill1, st);
   // positions moved: sort, neighbours, density and smoothing at x(n+1);
   // they (and the coupling slots) stay valid for the first pass of the
   // next step
   const bool fill2 = needs_fill(s, true);
   launch_pass_prep(d, s->boxes, 1, fill2, st);
-  run_build(s, st);
+  run_build(s, st, 1);
   run_pass(s, 2, 1, true, fill2, st);
   if (s->stress) {
     launch_box_stress(d, 1, st);
@@ -935,6 +1027,7 @@ int sdpdem_step(sdpdem_system* s, int64_t nsteps, void* hip_stream) {
       if (hipGraphLaunch(s->gexec, st) != hipSuccess) return SDPDEM_E_HIP;
       s->rxn_valid = act_now;  // the last pass built and (with the coupling) refilled
       s->step += K;
+      s->graph_steps_run += K;
       if (s->stress) s->stress_samples += K;
       left -= K;
     } else {
@@ -958,7 +1051,7 @@ int sdpdem_compute_forces(sdpdem_system* s, void* hip_stream) {
   const bool fill = needs_fill(s, !s->cache_valid);
   launch_pass_prep(s->d, s->boxes, 0, fill, st);
   if (!s->cache_valid) {
-    run_build(s, st);
+    run_build(s, st, 0);
     s->cache_valid = true;
   }
   run_pass(s, 1, 0, false, fill, st);
@@ -974,7 +1067,7 @@ int sdpdem_set_stress(sdpdem_system* s, int on, void* hip_stream) {
   s->stress_samples = 0;
   launch_fill_f64(s->d.st_sum, 0.0, (size_t)s->d.nbox, st);
   launch_fill_f64(s->d.st_inst, 0.0, (size_t)s->d.nbox, st);
-  if (s->d.nr) launch_fill_f64(s->d.wzx_r, 0.0, (size_t)s->d.nr, st);
+  if (s->d.nr) launch_fill_f64(s->d.wzx_r, 0.0, 2 * (size_t)s->d.nr, st);
   launch_fill_i32(reinterpret_cast<int*>(s->d.fout + 12 * (size_t)s->d.npad), 0,
                   (size_t)s->d.npad, st);
   if (hipStreamSynchronize(st) != hipSuccess) return SDPDEM_E_HIP;
@@ -1174,6 +1267,8 @@ int sdpdem_info(sdpdem_system* s, int64_t out[16], void* hip_stream) {
     out[5 + a] = s->h_boxes[0].rg.nc[a];
   }
   out[10] = s->d.nbox;
+  out[11] = s->graph_steps_run;
+  out[12] = s->side ? 1 : 0;
   std::vector<int> cnt((size_t)s->d.n);
   hipStream_t st = (hipStream_t)hip_stream;
   if (hipMemcpyAsync(cnt.data(), s->d.nbr_cnt, sizeof(int) * s->d.n, hipMemcpyDeviceToHost, st) !=
@@ -1214,6 +1309,7 @@ void sdpdem_destroy(sdpdem_system* s) {
   if (!s) return;
   drop_graph(s);
   prof_flush(s);
+  free_side_stream(s);
   for (auto& e : s->ev) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);

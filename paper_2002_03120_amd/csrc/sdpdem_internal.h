@@ -160,7 +160,7 @@ struct Dev {
   double* n_dem;
   double* eps;
   double* omega;
-  double* wzx_r;  // virial W_zx of every rigid slot (coupling + contacts)
+  double* wzx_r;  // virial W_zx of every rigid slot: [2 s] coupling, [2 s + 1] contacts
   uint32_t* rkey;
   int* rcount;
   int* rstart;

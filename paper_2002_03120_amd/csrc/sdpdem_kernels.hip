@@ -563,8 +563,8 @@ __global__ __launch_bounds__(BS) void k_fpi_finish(Dev d) {
     d.f_pg[3 * s + k] = pg[k];
   }
   // virial of the coupling: lever (sum_j w_sj r_sj / Omega_s)_z times the
-  // x force; the contacts add theirs later in the pass
-  if (STRESS) d.wzx_r[s] = om > 0.0 ? (a[7] / om) * (dg[0] + pg[0]) : 0.0;
+  // x force (the contacts keep theirs beside it)
+  if (STRESS) d.wzx_r[2 * s] = om > 0.0 ? (a[7] / om) * (dg[0] + pg[0]) : 0.0;
   // F^DG / Omega times the kernel's normalisation beside the sphere's
   // cell-ordered record, with 1/H_s (0: the sphere couples to nothing)
   D4 rc;
@@ -879,7 +879,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_
     d.f_lub[3 * s + a] = acc.FL[a];
     d.n_dem[3 * s + a] = acc.N[a];
   }
-  if (d.stress) d.wzx_r[s] += acc.Wzx;
+  if (d.stress) d.wzx_r[2 * s + 1] = acc.Wzx;
   if (commit) {
     nxt_cnt[s] = ncnt < mc ? ncnt : mc;
     if (overflow || ncnt > mc) atomicOr(d.status, ST_CONTACT_OVERFLOW);
@@ -1050,8 +1050,10 @@ __global__ __launch_bounds__(BS) void k_box_stress_part(Dev d, int rigid_active)
         q = v.w * v.z * vx;
         if (t == T_FLUID || t == T_INNER)
           q += (double)d.fout[12 * np + i];
-        else if (t == T_RIGID && rigid_active)
-          q += d.wzx_r[d.gid2slot[d.gid[i]]];
+        else if (t == T_RIGID && rigid_active) {
+          const int k = d.gid2slot[d.gid[i]];
+          q += d.wzx_r[2 * k] + d.wzx_r[2 * k + 1];  // coupling + contacts
+        }
       }
     }
   }

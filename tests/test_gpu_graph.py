@@ -41,6 +41,11 @@ def run(S, p, parts, chunks, graph, stress=False, boxes=None, box_of=None):
     if stress:
         out.append(g.box_stress()[1])
     out.append(g.current_step)
+    info = g.info()
+    if graph:
+        assert info[11] > 0, "no step was replayed from a graph"
+    if np.any(parts["type"] == W.RIGID):
+        assert info[12] == 1, "the contacts did not get the second stream"
     g.close()
     return out, reads
 
