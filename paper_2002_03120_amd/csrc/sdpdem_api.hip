@@ -547,7 +547,9 @@ struct Prof {
   sdpdem_system* s;
   hipStream_t st;
   bool on;
-  Prof(sdpdem_system* s_, int kid, hipStream_t st_) : s(s_), st(st_), on(s_->prof_kernel == kid) {
+  bool ext;  // the launch records the event pair itself (single-kernel scopes)
+  Prof(sdpdem_system* s_, int kid, hipStream_t st_, bool ext_ = false)
+      : s(s_), st(st_), on(s_->prof_kernel == kid), ext(ext_) {
     if (!on) return;
     if (s->ev_used == s->ev.size()) {
       if (s->ev.size() < 4096) {
@@ -566,11 +568,13 @@ struct Prof {
         prof_flush(s);
       }
     }
-    on = hipEventRecord(s->ev[s->ev_used].first, st) == hipSuccess;
+    on = ext || hipEventRecord(s->ev[s->ev_used].first, st) == hipSuccess;
   }
+  hipEvent_t t0() const { return on && ext ? s->ev[s->ev_used].first : nullptr; }
+  hipEvent_t t1() const { return on && ext ? s->ev[s->ev_used].second : nullptr; }
   ~Prof() {
     if (!on) return;
-    if (hipEventRecord(s->ev[s->ev_used].second, st) == hipSuccess) s->ev_used += 1;
+    if (ext || hipEventRecord(s->ev[s->ev_used].second, st) == hipSuccess) s->ev_used += 1;
   }
 };
 
@@ -694,8 +698,8 @@ void run_pass(sdpdem_system* s, int velver, int commit, bool integrate, bool fil
   }
   s->rigid_issued = false;
   {
-    Prof pr(s, SDPDEM_K_FLUID_FORCES, st);
-    launch_fluid_forces(d, s->noise, st);
+    Prof pr(s, SDPDEM_K_FLUID_FORCES, st, true);
+    launch_fluid_forces(d, s->noise, st, pr.t0(), pr.t1());
   }
   if (act) {
     if (fk && (!s->gather_ok || hipStreamWaitEvent(st, s->ev_gather, 0) != hipSuccess))
@@ -1292,6 +1296,18 @@ int sdpdem_set_profiling(sdpdem_system* s, int kernel) {
   s->prof_kernel = kernel;
   s->prof_ms = 0.0;
   s->prof_n = 0;
+  // create the timing events now, not while the timed launches are being
+  // enqueued (creating them there costs host time per launch)
+  if (kernel != SDPDEM_K_NONE)
+    while (s->ev.size() < 1024) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess) break;
+      if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        break;
+      }
+      s->ev.emplace_back(a, b);
+    }
   return SDPDEM_OK;
 }
 

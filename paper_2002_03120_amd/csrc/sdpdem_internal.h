@@ -216,7 +216,9 @@ void launch_pass_prep(const Dev& d, BoxD* boxes, int add, bool clear_rxn, hipStr
 // per-box sample of P_zx; with accumulate, also added to the running sums
 void launch_box_stress(const Dev& d, int accumulate, hipStream_t st);
 void launch_smooth(const Dev& d, hipStream_t st);
-void launch_fluid_forces(const Dev& d, bool noise, hipStream_t st);
+// with t0 and t1, the launch records the two timing events itself
+void launch_fluid_forces(const Dev& d, bool noise, hipStream_t st, hipEvent_t t0 = nullptr,
+                         hipEvent_t t1 = nullptr);
 void launch_rigid_gather(const Dev& d, hipStream_t st);
 // the coupling action (the per-sphere gather, then the per-sphere drag and
 // pressure-gradient algebra); with fill it also refills the reaction's

@@ -2,6 +2,8 @@
 // SDPD pair forces: one thread per particle in cell-sorted order, blocks
 // mapped to XCDs in contiguous chunks, neighbour data gathered through L1/L2
 // (the sorted order keeps a wave's neighbourhood compact).
+#include <hip/hip_ext.h>
+
 #include "sdpdem_device.h"
 
 namespace sdpdem {
@@ -274,18 +276,20 @@ __global__ __launch_bounds__(BS) void k_fluid_forces(Dev d) {
   if (STRESS) o[12 * np + i] = Wzx;
 }
 
-void launch_fluid_forces(const Dev& d, bool noise, hipStream_t st) {
-  if (noise) {
-    if (d.stress)
-      k_fluid_forces<true, true><<<d.nblk, BS, 0, st>>>(d);
-    else
-      k_fluid_forces<true, false><<<d.nblk, BS, 0, st>>>(d);
-  } else {
-    if (d.stress)
-      k_fluid_forces<false, true><<<d.nblk, BS, 0, st>>>(d);
-    else
-      k_fluid_forces<false, false><<<d.nblk, BS, 0, st>>>(d);
+void launch_fluid_forces(const Dev& d, bool noise, hipStream_t st, hipEvent_t t0,
+                         hipEvent_t t1) {
+  auto k = noise ? (d.stress ? k_fluid_forces<true, true> : k_fluid_forces<true, false>)
+                 : (d.stress ? k_fluid_forces<false, true> : k_fluid_forces<false, false>);
+  if (t0 && t1) {
+    // the dispatch itself stamps the two events (no marker packets around
+    // the kernel, which would stall the stream)
+    Dev arg = d;
+    void* args[] = {&arg};
+    if (hipExtLaunchKernel(reinterpret_cast<const void*>(k), dim3(d.nblk), dim3(BS), args, 0, st,
+                           t0, t1, 0) == hipSuccess)
+      return;
   }
+  k<<<d.nblk, BS, 0, st>>>(d);
 }
 
 // neighbour columns k0..k0+kn-1 as ids (-1 past a row's end), for export
