@@ -136,6 +136,37 @@ def test_reused_coupling_slots_match_a_fresh_fill(S):
         assert np.array_equal(g.read_field(fld), f.read_field(fld)), fld
 
 
+def test_replayed_search_of_a_big_sphere_matches_a_fresh_fill(S):
+    """A sphere whose coupling search needs more candidate rounds than the
+    action records (radius 5, support 6.5: about 1400 candidates) is
+    searched again in the pass that replays the others; the result still
+    matches a fresh fill bit for bit."""
+    print("[case] big spheres: search record overflow", flush=True)
+    p, parts, _ = W.reverse_poiseuille(n_side=(36, 36, 36), kBT=1e-3, g=0.0, dt=0.01)
+    parts = W.perturb(parts, p, jitter=0.0, kT=1e-3, seed=5)
+    R = 5.0
+    vs = 4.0 / 3.0 * math.pi * R ** 3
+    for c in [(9.0, 9.0, 9.0), (27.0, 26.0, 25.0), (9.5, 27.0, 26.5)]:
+        k = int(np.argmin(((parts["pos"] - np.asarray(c)) ** 2).sum(axis=1)))
+        parts["type"][k] = W.RIGID
+        parts["mass"][k] = 2.5 * vs
+        parts["inertia"][k] = 0.4 * 2.5 * vs * R * R
+        parts["radius"][k] = R
+    g = S.System(p, parts)
+    g.step(3)
+    g.compute_forces()
+    state = {k: np.array(v, copy=True) for k, v in parts.items()}
+    state["pos"], state["vel"], state["angvel"] = (g.read_field(f) for f in ("POS", "VEL", "ANGVEL"))
+    pairs, dts = g.read_contacts()
+    f = S.System(dict(p, itr_start=g.current_step), state)
+    f.load_contacts(pairs, dts)
+    f.compute_forces()
+    rig = parts["type"] == W.RIGID
+    assert np.all(g.read_field("EPS")[rig] > 0)
+    for fld in ("F_RXN", "F_DG", "F_PG", "EPS"):
+        assert np.array_equal(g.read_field(fld), f.read_field(fld)), fld
+
+
 def test_restart_is_bit_exact(S):
     print("[case] restart", flush=True)
     p, parts = _colliding_spheres(lub=1)
