@@ -926,8 +926,8 @@ __device__ __forceinline__ void total_force(const Dev& d, const BoxD& B, int i, 
   }
 }
 
-__global__ __launch_bounds__(BS) void k_integrate(Dev d, int velver, int rigid_active,
-                                                 int end_step) {
+template <int VELVER>
+__global__ __launch_bounds__(BS) void k_integrate(Dev d, int rigid_active, int end_step) {
   // the last pass of a step advances the device step counter (no kernel of
   // this launch reads it)
   if (end_step && blockIdx.x == 0 && threadIdx.x == 0) d.dstep[0] += 1;
@@ -939,7 +939,11 @@ __global__ __launch_bounds__(BS) void k_integrate(Dev d, int velver, int rigid_a
   uint8_t t = d.type[i];
   if (t == T_OUTER) return;
   if (t == T_RIGID && !rigid_active) return;
-  D4 p = d.pos[i], v = d.vel[i], w = d.om[i];
+  D4 v = d.vel[i], w = d.om[i];
+  // the second half-kick reads the position only for the split body force
+  // (positions do not move in that pass, and the first one checked them)
+  D4 p = {0.0, 0.0, 0.0, 0.0};
+  if (VELVER == 1 || d.gtype == 1) p = d.pos[i];
   double F[3], N[3];
   total_force(d, B, i, t, p, rigid_active, F, N);
   const double hdt = 0.5 * d.dt;
@@ -950,7 +954,7 @@ __global__ __launch_bounds__(BS) void k_integrate(Dev d, int velver, int rigid_a
   w.y += hdt * N[1] / w.w;
   w.z += hdt * N[2] / w.w;
   int bad = 0;
-  if (velver == 1 && (t == T_FLUID || t == T_RIGID)) {
+  if (VELVER == 1 && (t == T_FLUID || t == T_RIGID)) {
     double x[3] = {p.x + d.dt * v.x, p.y + d.dt * v.y, p.z + d.dt * v.z};
     double vv[3] = {v.x, v.y, v.z};
     if (B.le) {
@@ -997,12 +1001,12 @@ __global__ __launch_bounds__(BS) void k_integrate(Dev d, int velver, int rigid_a
     d.pos[i] = p;
   }
   if (!isfinite(v.x) || !isfinite(v.y) || !isfinite(v.z) || !isfinite(w.x) || !isfinite(w.y) ||
-      !isfinite(w.z) || !isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z))
+      !isfinite(w.z) || (VELVER == 1 && (!isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z))))
     bad |= ST_NONFINITE;
   if (bad) atomicOr(d.status, bad);
   d.vel[i] = v;
   d.om[i] = w;
-  if (velver == 2) {
+  if (VELVER == 2) {
     // positions did not move: refresh the pair record for the next pass
     PR* r = d.prec + i;
     r->vx = (float)v.x;
@@ -1016,7 +1020,8 @@ __global__ __launch_bounds__(BS) void k_integrate(Dev d, int velver, int rigid_a
 
 void launch_integrate(const Dev& d, int velver, int rigid_active, bool end_step,
                       hipStream_t st) {
-  k_integrate<<<d.nblk, BS, 0, st>>>(d, velver, rigid_active, end_step ? 1 : 0);
+  auto k = velver == 2 ? k_integrate<2> : k_integrate<1>;
+  k<<<d.nblk, BS, 0, st>>>(d, rigid_active, end_step ? 1 : 0);
 }
 
 // ---------------------------------------------------------------------------
