@@ -95,7 +95,7 @@ __global__ __launch_bounds__(BS) void k_bin_rigid(Dev d) {
 
 void launch_bin_rigid(const Dev& d, hipStream_t st) {
   if (d.nr == 0) return;
-  k_bin_rigid<<<(d.nr + BS - 1) / BS, BS, 0, st>>>(d);
+  k_bin_rigid<<<(d.nr + 63) / 64, 64, 0, st>>>(d);  // one wave per block: more CUs
 }
 
 // The start of a pass, one launch: the Lees-Edwards offsets
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(BS) void k_rigid_gather(Dev d) {
 
 void launch_rigid_gather(const Dev& d, hipStream_t st) {
   if (d.nr == 0) return;
-  k_rigid_gather<<<(d.nr + BS - 1) / BS, BS, 0, st>>>(d);
+  k_rigid_gather<<<(d.nr + 63) / 64, 64, 0, st>>>(d);  // one wave per block: more CUs
 }
 
 // ---------------------------------------------------------------------------
@@ -580,8 +580,10 @@ void launch_fpi_action(const Dev& d, bool fill, hipStream_t st) {
   auto k = d.stress ? (fill ? k_fpi_action<true, true> : k_fpi_action<true, false>)
                     : (fill ? k_fpi_action<false, true> : k_fpi_action<false, false>);
   k<<<nblocks((size_t)d.nr * 64), BS, 0, st>>>(d);
+  // one wavefront per block: the few thousand threads of the finish spread
+  // over as many CUs as possible (its FP64 divisions and powers are latency)
   auto f = d.stress ? k_fpi_finish<true> : k_fpi_finish<false>;
-  f<<<(d.nr + BS - 1) / BS, BS, 0, st>>>(d);
+  f<<<(d.nr + 63) / 64, 64, 0, st>>>(d);
 }
 
 // (a7) reaction on the coupled fluid particles, Eq. F_fpi_DG_reac
