@@ -212,7 +212,7 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
   uint32_t* key = b.take<uint32_t>(np);
   int* count = b.take<int>(nc);
   int* cstart = b.take<int>(nc + 1);
-  int* cursor = b.take<int>(nc);
+  int* rank = b.take<int>(np);
   int* perm = b.take<int>(np);
   int* bsum = b.take<int>((size_t)scan_block_sums_size((int)nc) + 1);
   int* nbr = b.take<int>((size_t)z.maxn * np);
@@ -290,7 +290,7 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
     d.key = key;
     d.count = count;
     d.cstart = cstart;
-    d.cursor = cursor;
+    d.rank = rank;
     d.perm = perm;
     d.nbr = nbr;
     d.nbr_cnt = nbr_cnt;
@@ -631,8 +631,8 @@ void run_build(sdpdem_system* s, hipStream_t st, int commit_next) {
   }
   {
     Prof pr(s, SDPDEM_K_SORT, st);
-    launch_scan(d.count, nc, d.cstart, d.cursor, s->block_sums, st);
-    launch_scatter(d.key, d.n, d.cursor, d.perm, st);
+    launch_scan(d.count, nc, d.cstart, nullptr, s->block_sums, st);
+    launch_scatter_ranked(d.key, d.rank, d.n, d.cstart, d.perm, st);
     launch_cell_sort(d.cstart, nc, d.perm, s->gid[s->cur], st);
   }
   const int src = s->cur;

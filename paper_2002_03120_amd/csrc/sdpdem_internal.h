@@ -138,7 +138,7 @@ struct Dev {
   uint32_t* key;
   int* count;
   int* cstart;  // ncells_all + 1
-  int* cursor;
+  int* rank;  // per particle: its arrival order in its cell at binning
   int* perm;
   // neighbours and fields
   int* nbr;  // [maxn * npad], neighbour k of particle i at k*npad + i
@@ -199,11 +199,14 @@ void launch_fill_i32(int* a, int v, size_t count, hipStream_t st);
 void launch_fill_f64(double* a, double v, size_t count, hipStream_t st);
 void launch_bin(const Dev& d, hipStream_t st);
 void launch_bin_rigid(const Dev& d, hipStream_t st);
-// exclusive scan of count[0..m) into start[0..m] and cursor[0..m)
+// exclusive scan of count[0..m) into start[0..m] and (unless null) cursor[0..m)
 void launch_scan(const int* count, int m, int* start, int* cursor, int* block_sums,
                  hipStream_t st);
 int scan_block_sums_size(int m);
 void launch_scatter(const uint32_t* key, int n, int* cursor, int* perm, hipStream_t st);
+// perm[start[key[i]] + rank[i]] = i (the ranks the binning handed out)
+void launch_scatter_ranked(const uint32_t* key, const int* rank, int n, const int* start,
+                           int* perm, hipStream_t st);
 // sort each cell's slice of perm by sortkey[perm[k]] (sortkey == null: by value)
 void launch_cell_sort(const int* start, int ncells, int* perm, const int* sortkey,
                       hipStream_t st);

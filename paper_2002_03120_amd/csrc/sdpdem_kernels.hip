@@ -71,7 +71,9 @@ __global__ __launch_bounds__(BS) void k_bin(Dev d) {
   if (oob) atomicOr(d.status, ST_OUT_OF_DOMAIN);
   int c = B.cell_off + cell_index(B.g, cx, cy, cz);
   d.key[i] = (uint32_t)c;
-  atomicAdd(&d.count[c], 1);
+  // the arrival order in the cell places the particle in the scatter (the
+  // cell sort then fixes the order inside the cell)
+  d.rank[i] = atomicAdd(&d.count[c], 1);
 }
 
 void launch_bin(const Dev& d, hipStream_t st) {
@@ -220,14 +222,16 @@ __global__ __launch_bounds__(BS) void k_scan_apply(const int* in, int m, const i
     const int4 a = make_int4(e[0], e[1], e[2], e[3]), b = make_int4(e[4], e[5], e[6], e[7]);
     *reinterpret_cast<int4*>(start + base) = a;
     *reinterpret_cast<int4*>(start + base + 4) = b;
-    *reinterpret_cast<int4*>(cursor + base) = a;
-    *reinterpret_cast<int4*>(cursor + base + 4) = b;
+    if (cursor) {
+      *reinterpret_cast<int4*>(cursor + base) = a;
+      *reinterpret_cast<int4*>(cursor + base + 4) = b;
+    }
   } else {
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k)
       if (base + k < m) {
         start[base + k] = e[k];
-        cursor[base + k] = e[k];
+        if (cursor) cursor[base + k] = e[k];
       }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) start[m] = block_sums[nb];
@@ -255,6 +259,19 @@ __global__ __launch_bounds__(BS) void k_scatter(const uint32_t* key, int n, int*
 void launch_scatter(const uint32_t* key, int n, int* cursor, int* perm, hipStream_t st) {
   if (n == 0) return;
   k_scatter<<<nblocks(n), BS, 0, st>>>(key, n, cursor, perm);
+}
+
+__global__ __launch_bounds__(BS) void k_scatter_ranked(const uint32_t* key, const int* rank,
+                                                      int n, const int* start, int* perm) {
+  int i = xcd_tid();
+  if (i >= n) return;
+  perm[start[key[i]] + rank[i]] = i;
+}
+
+void launch_scatter_ranked(const uint32_t* key, const int* rank, int n, const int* start,
+                           int* perm, hipStream_t st) {
+  if (n == 0) return;
+  k_scatter_ranked<<<nblocks(n), BS, 0, st>>>(key, rank, n, start, perm);
 }
 
 // Insertion sort of each cell's slice: ties of the counting sort are
