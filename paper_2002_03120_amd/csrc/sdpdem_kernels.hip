@@ -351,16 +351,17 @@ void launch_rigid_gather(const Dev& d, hipStream_t st) {
 // fluid inside H_s = R_s + h (Sec. 2.4): Omega_s, the W-weighted fluid
 // velocity, the W-weighted F^C + F^D of the neighbours and the number of
 // other rigid centres inside H_s (k_fpi_finish then forms eps, F^DG and
-// F^PG from them).  The cell rows of the search box are contiguous slices of the sorted arrays; the
-// wave walks their concatenation with one candidate per lane.  With FILL it
-// also hands every coupled fluid particle a slot (sphere record, kernel
-// weight) for the reaction and records, round by round and lane by lane,
-// which fluid particle each lane coupled to.  Both depend only on the
-// positions and the sorted order, so the pass after a neighbour build fills
-// them and the next pass (same positions, same order) reuses them: the
-// slot counter's atomics miss the L2 and travel to memory, and the recorded
-// rounds replace the cell search, with every lane summing the same terms
-// in the same order.
+// F^PG from them).  The cell rows of the search box are contiguous slices
+// of the sorted arrays; the wave walks their concatenation with one
+// candidate per lane.  With FILL it also hands every coupled fluid particle
+// a slot (sphere record, kernel weight) for the reaction and records,
+// round by round and lane by lane, which fluid particle each lane coupled
+// to.  Both depend only on the positions and the sorted order, so the pass
+// after a neighbour build fills them and the next pass (same positions,
+// same order) reuses them: the slot counter's atomics miss the L2 and
+// travel to memory, and the recorded rounds replace the cell search, with
+// every lane summing the same terms in the same order (a sphere whose
+// search needed more rounds than the record holds searches again).
 
 __device__ double drag_b(double eps, double dv, double dd, double rho, double mu) {
   // beta / (1 - eps) of the Ergun (eps <= 0.8) and Wen-Yu branches
