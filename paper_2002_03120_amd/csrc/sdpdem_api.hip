@@ -709,7 +709,8 @@ void run_pass(sdpdem_system* s, int velver, int commit, bool integrate, bool fil
       launch_fpi_action(d, fill, st);
       if (fill) s->rxn_valid = true;
     }
-    {
+    // the reaction of an updating pass is formed inside the update
+    if (!integrate) {
       Prof pr(s, SDPDEM_K_FPI_REACTION, st);
       launch_fpi_reaction(d, st);
     }
@@ -728,7 +729,7 @@ void run_pass(sdpdem_system* s, int velver, int commit, bool integrate, bool fil
   if (integrate) {
     Prof pr(s, SDPDEM_K_INTEGRATE, st);
     // the second pass of a step also advances the device step counter
-    launch_integrate(d, velver, act ? 1 : 0, velver == 2, st);
+    launch_integrate(d, velver, act ? 1 : 0, velver == 2, act, st);
   }
 }
 

@@ -230,8 +230,10 @@ void launch_fpi_action(const Dev& d, bool fill, hipStream_t st);
 void launch_fpi_reaction(const Dev& d, hipStream_t st);
 void launch_dem(const Dev& d, int commit, int* nxt_cnt, int* nxt_partner, double* nxt_dt,
                 hipStream_t st);
-// with end_step, block 0 also advances the device step counter
-void launch_integrate(const Dev& d, int velver, int rigid_active, bool end_step,
+// with end_step, block 0 also advances the device step counter; with
+// fuse_rxn the launch also forms the drag reaction (launch_fpi_reaction's
+// work) of the coupled fluid particles
+void launch_integrate(const Dev& d, int velver, int rigid_active, bool end_step, bool fuse_rxn,
                       hipStream_t st);
 void launch_read_field(const Dev& d, int field, int rigid_active, double* out, hipStream_t st);
 int totals_partial_blocks(int n);

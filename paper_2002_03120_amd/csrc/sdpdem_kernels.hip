@@ -607,16 +607,11 @@ void launch_fpi_action(const Dev& d, bool fill, hipStream_t st) {
 // (a7) reaction on the coupled fluid particles, Eq. F_fpi_DG_reac
 // normalised per rigid particle: -sum_s F^DG_s w_sj / Omega_s over the
 // rigid s with j in C_s.  The rigid grid's cells are at least H_max wide.
-__global__ __launch_bounds__(BS) void k_fpi_reaction(Dev d) {
-  int i;
-  const int b = blk_box(d, i);
-  if (b < 0) return;
-  const BoxD& B = d.boxes[b];
-  if (i >= B.first + B.count) return;
-  // the action's slot count: nonzero exactly for the fluid particles
-  // inside some sphere's support
-  const int c = d.rxn_cnt[i];
-  if (c == 0) return;
+// The reaction on fluid particle i with c > 0 coupling slots; also stored
+// in the F_RXN planes (read by the field readout and, when not fused, by
+// the update).  Returns the stored FP32 values.
+__device__ __forceinline__ void reaction_of(const Dev& d, const BoxD& B, int i, int c,
+                                            float out[3]) {
   const size_t np = (size_t)d.npad;
   double a0 = 0, a1 = 0, a2 = 0;
   if (c <= RXN_CAP) {
@@ -675,9 +670,26 @@ __global__ __launch_bounds__(BS) void k_fpi_reaction(Dev d) {
       }
     });
   }
-  d.fout[9 * np + i] = (float)a0;
-  d.fout[10 * np + i] = (float)a1;
-  d.fout[11 * np + i] = (float)a2;
+  out[0] = (float)a0;
+  out[1] = (float)a1;
+  out[2] = (float)a2;
+  d.fout[9 * np + i] = out[0];
+  d.fout[10 * np + i] = out[1];
+  d.fout[11 * np + i] = out[2];
+}
+
+__global__ __launch_bounds__(BS) void k_fpi_reaction(Dev d) {
+  int i;
+  const int b = blk_box(d, i);
+  if (b < 0) return;
+  const BoxD& B = d.boxes[b];
+  if (i >= B.first + B.count) return;
+  // the action's slot count: nonzero exactly for the fluid particles
+  // inside some sphere's support
+  const int c = d.rxn_cnt[i];
+  if (c == 0) return;
+  float out[3];
+  reaction_of(d, B, i, c, out);
 }
 
 void launch_fpi_reaction(const Dev& d, hipStream_t st) {
@@ -915,9 +927,11 @@ void launch_dem(const Dev& d, int commit, int* nxt_cnt, int* nxt_partner, double
 // ---------------------------------------------------------------------------
 // (a9) velocity Verlet (Alg. 1, update) with the boundary treatment.
 
+// rxo: the fluid particle's reaction when the caller formed it (null: read
+// the F_RXN planes)
 __device__ __forceinline__ void total_force(const Dev& d, const BoxD& B, int i, uint8_t t,
                                             const D4& p, int rigid_active, double F[3],
-                                            double N[3]) {
+                                            double N[3], const float* rxo = nullptr) {
   double sg = 1.0;
   if (d.gtype == 1) {
     double x = d.gaxis == 0 ? p.x : (d.gaxis == 1 ? p.y : p.z);
@@ -928,7 +942,9 @@ __device__ __forceinline__ void total_force(const Dev& d, const BoxD& B, int i, 
   for (int a = 0; a < 3; ++a) {
     double body = m * d.body[a] * sg;
     if (t == T_FLUID) {
-      double rx = (d.have_rxn && d.rxn_cnt[i] > 0) ? (double)d.fout[(9 + a) * np + i] : 0.0;
+      double rx = rxo ? (double)rxo[a]
+                      : (d.have_rxn && d.rxn_cnt[i] > 0) ? (double)d.fout[(9 + a) * np + i]
+                                                         : 0.0;
       F[a] = (double)d.fout[a * np + i] + rx + body;
       N[a] = (double)d.fout[(3 + a) * np + i];
     } else if (t == T_INNER) {
@@ -946,7 +962,9 @@ __device__ __forceinline__ void total_force(const Dev& d, const BoxD& B, int i, 
   }
 }
 
-template <int VELVER>
+// RXN: the reaction of the coupled fluid particles is formed here too
+// (one launch less; the particle's F_RXN is used from registers)
+template <int VELVER, bool RXN>
 __global__ __launch_bounds__(BS) void k_integrate(Dev d, int rigid_active, int end_step) {
   // the last pass of a step advances the device step counter (no kernel of
   // this launch reads it)
@@ -965,7 +983,10 @@ __global__ __launch_bounds__(BS) void k_integrate(Dev d, int rigid_active, int e
   D4 p = {0.0, 0.0, 0.0, 0.0};
   if (VELVER == 1 || d.gtype == 1) p = d.pos[i];
   double F[3], N[3];
-  total_force(d, B, i, t, p, rigid_active, F, N);
+  float rxf[3] = {0.0f, 0.0f, 0.0f};
+  const int c = RXN && t == T_FLUID ? d.rxn_cnt[i] : 0;
+  if (c > 0) reaction_of(d, B, i, c, rxf);
+  total_force(d, B, i, t, p, rigid_active, F, N, RXN && t == T_FLUID ? rxf : nullptr);
   const double hdt = 0.5 * d.dt;
   v.x += hdt * F[0] / v.w;
   v.y += hdt * F[1] / v.w;
@@ -1038,9 +1059,10 @@ __global__ __launch_bounds__(BS) void k_integrate(Dev d, int rigid_active, int e
   }
 }
 
-void launch_integrate(const Dev& d, int velver, int rigid_active, bool end_step,
+void launch_integrate(const Dev& d, int velver, int rigid_active, bool end_step, bool fuse_rxn,
                       hipStream_t st) {
-  auto k = velver == 2 ? k_integrate<2> : k_integrate<1>;
+  auto k = fuse_rxn ? (velver == 2 ? k_integrate<2, true> : k_integrate<1, true>)
+                    : (velver == 2 ? k_integrate<2, false> : k_integrate<1, false>);
   k<<<d.nblk, BS, 0, st>>>(d, rigid_active, end_step ? 1 : 0);
 }
 
