@@ -964,8 +964,9 @@ __device__ __forceinline__ void total_force(const Dev& d, const BoxD& B, int i, 
 
 // RXN: the reaction of the coupled fluid particles is formed here too
 // (one launch less; the particle's F_RXN is used from registers)
+// (64 registers, eight waves per SIMD, fit without spills)
 template <int VELVER, bool RXN>
-__global__ __launch_bounds__(BS) void k_integrate(Dev d, int rigid_active, int end_step) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_integrate(Dev d, int rigid_active, int end_step) {
   // the last pass of a step advances the device step counter (no kernel of
   // this launch reads it)
   if (end_step && blockIdx.x == 0 && threadIdx.x == 0) d.dstep[0] += 1;
@@ -977,15 +978,16 @@ __global__ __launch_bounds__(BS) void k_integrate(Dev d, int rigid_active, int e
   uint8_t t = d.type[i];
   if (t == T_OUTER) return;
   if (t == T_RIGID && !rigid_active) return;
+  // the reaction first, before the particle's own state is live
+  float rxf[3] = {0.0f, 0.0f, 0.0f};
+  const int c = RXN && t == T_FLUID ? d.rxn_cnt[i] : 0;
+  if (c > 0) reaction_of(d, B, i, c, rxf);
   D4 v = d.vel[i], w = d.om[i];
   // the second half-kick reads the position only for the split body force
   // (positions do not move in that pass, and the first one checked them)
   D4 p = {0.0, 0.0, 0.0, 0.0};
   if (VELVER == 1 || d.gtype == 1) p = d.pos[i];
   double F[3], N[3];
-  float rxf[3] = {0.0f, 0.0f, 0.0f};
-  const int c = RXN && t == T_FLUID ? d.rxn_cnt[i] : 0;
-  if (c > 0) reaction_of(d, B, i, c, rxf);
   total_force(d, B, i, t, p, rigid_active, F, N, RXN && t == T_FLUID ? rxf : nullptr);
   const double hdt = 0.5 * d.dt;
   v.x += hdt * F[0] / v.w;
