@@ -15,7 +15,7 @@ namespace sdpdem {
 // stencil is walked row by row; the cells of a row are one contiguous slice
 // of the sorted arrays unless the row wraps.
 
-__global__ __launch_bounds__(BS) void k_build_density(Dev d) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_build_density(Dev d) {
   int i;
   const int b = blk_box(d, i);
   if (b < 0) return;
