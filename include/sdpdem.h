@@ -266,6 +266,11 @@ int sdpdem_info(sdpdem_system* sys, int64_t out[16], void* hip_stream);
  * returns the accumulated milliseconds and launch count and resets them. */
 int sdpdem_set_profiling(sdpdem_system* sys, int kernel);
 int sdpdem_kernel_time(sdpdem_system* sys, double* total_ms, int64_t* launches);
+/* Time only the first of every `every` launches of the profiled kernel
+ * (every >= 1; 1, the default, times all): the timing events perturb the
+ * stream less, and sdpdem_kernel_time counts the timed launches only.
+ * Resets the count; SDPDEM_E_INVALID_ARG for every < 1. */
+int sdpdem_set_profiling_every(sdpdem_system* sys, int every);
 
 void sdpdem_destroy(sdpdem_system* sys);
 const char* sdpdem_status_string(int status);

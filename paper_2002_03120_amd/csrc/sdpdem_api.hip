@@ -60,6 +60,8 @@ struct sdpdem_system {
   std::vector<int> h_gid2slot;
   // profiling
   int prof_kernel = SDPDEM_K_NONE;
+  int prof_every = 1;      // time the first of every prof_every launches
+  int64_t prof_seen = 0;   // launches of the profiled kernel so far
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
   size_t ev_used = 0;
   double prof_ms = 0.0;
@@ -549,7 +551,8 @@ struct Prof {
   bool on;
   bool ext;  // the launch records the event pair itself (single-kernel scopes)
   Prof(sdpdem_system* s_, int kid, hipStream_t st_, bool ext_ = false)
-      : s(s_), st(st_), on(s_->prof_kernel == kid), ext(ext_) {
+      : s(s_), st(st_), on(s_->prof_kernel == kid && s_->prof_seen++ % s_->prof_every == 0),
+        ext(ext_) {
     if (!on) return;
     if (s->ev_used == s->ev.size()) {
       if (s->ev.size() < 4096) {
@@ -1297,6 +1300,7 @@ int sdpdem_set_profiling(sdpdem_system* s, int kernel) {
   s->prof_kernel = kernel;
   s->prof_ms = 0.0;
   s->prof_n = 0;
+  s->prof_seen = 0;
   // create the timing events now, not while the timed launches are being
   // enqueued (creating them there costs host time per launch)
   if (kernel != SDPDEM_K_NONE)
@@ -1309,6 +1313,14 @@ int sdpdem_set_profiling(sdpdem_system* s, int kernel) {
       }
       s->ev.emplace_back(a, b);
     }
+  return SDPDEM_OK;
+}
+
+int sdpdem_set_profiling_every(sdpdem_system* s, int every) {
+  if (!s || every < 1) return SDPDEM_E_INVALID_ARG;
+  prof_flush(s);
+  s->prof_every = every;
+  s->prof_seen = 0;
   return SDPDEM_OK;
 }
 

@@ -122,6 +122,7 @@ def lib():
         L.sdpdem_get_step.restype = i64
         L.sdpdem_info.argtypes = [vp, vp, vp]
         L.sdpdem_set_profiling.argtypes = [vp, ctypes.c_int]
+        L.sdpdem_set_profiling_every.argtypes = [vp, ctypes.c_int]
         L.sdpdem_kernel_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
         L.sdpdem_destroy.argtypes = [vp]
         L.sdpdem_destroy.restype = None
@@ -415,7 +416,9 @@ class System:
     def current_step(self):
         return sdpdem_get_step(self.h)
 
-    def set_profiling(self, kernel):
+    def set_profiling(self, kernel, every=1):
+        """Time the launches of `kernel` (the first of every `every`)."""
+        _check(lib().sdpdem_set_profiling_every(self.h, int(every)), "sdpdem_set_profiling_every")
         sdpdem_set_profiling(self.h, kernel)
 
     def set_graph(self, steps_per_graph):

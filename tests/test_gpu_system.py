@@ -219,3 +219,23 @@ def test_error_codes(S):
     with pytest.raises(S.SdpdemError) as e:
         S.System(dict(p, xi=-1.0), parts)
     assert e.value.code == S.E_INVALID_ARG
+
+
+def test_sampled_kernel_timing(S):
+    """Timing the first of every k launches counts only those launches."""
+    print("[case] sampled kernel timing", flush=True)
+    p, parts, _ = W.reverse_poiseuille(n_side=(8, 8, 8), kBT=0.0)
+    g = S.System(p, parts)
+    g.step(1)
+    g.set_profiling("fluid_forces", every=3)
+    g.step(5)  # ten pair-kernel launches: 0, 3, 6 and 9 are timed
+    ms, n = g.kernel_time()
+    assert n == 4 and ms > 0.0
+    g.set_profiling("fluid_forces")
+    g.step(2)
+    ms, n = g.kernel_time()
+    assert n == 4
+    g.set_profiling("none")
+    with pytest.raises(S.SdpdemError):
+        g.set_profiling("fluid_forces", every=0)
+    g.close()
