@@ -21,8 +21,9 @@
  *    arrays passed in are copied before the call returns.  The
  *    sdpdem_system handle is a small host object owned by the library.
  *  - Streams: every call takes a hipStream_t as void*.  sdpdem_step and
- *    sdpdem_compute_forces only enqueue work, then synchronise once on the
- *    stream to read the device status word; the read calls synchronise.
+ *    sdpdem_compute_forces enqueue work, then synchronise once on the
+ *    stream to read the device status word; the reads into host memory
+ *    synchronise; sdpdem_read_field into device memory only enqueues.
  *  - Order: particles are identified by ids that must be a permutation of
  *    0..n-1; every array crossing the ABI is in id order, whatever order
  *    the library keeps internally.
@@ -156,11 +157,17 @@ enum sdpdem_kernel {
 
 typedef struct sdpdem_system sdpdem_system;
 
-/* Bytes of device workspace needed for these parameters and particles. */
+/* Bytes of device workspace needed for these parameters and particles:
+ * the particle arrays of Sec. 3.2 (one record per particle, sized by the
+ * parameter table, Table ipparam) plus the cell grid and neighbour rows of
+ * Alg. 1.  Writes *bytes; SDPDEM_E_INVALID_ARG for what sdpdem_create
+ * rejects.  Touches no device. */
 int sdpdem_workspace_bytes(const sdpdem_params* params,
                            const sdpdem_particles* particles, size_t* bytes);
 
-/* Validate, upload and build the system in the caller's workspace.
+/* Validate, upload and build the system in the caller's workspace: the
+ * initialisation part of the particle system of Sec. 3.1 (parameters of
+ * Table ipparam, particle types of Sec. 2.5).
  * Rejects (SDPDEM_E_INVALID_ARG): ids not a permutation of 0..n-1, unknown
  * types, non-positive h, dx, dt, rho0, masses or rigid radii, xi outside
  * [40 eta/51, 5 eta/3] (gamma^a, gamma^b of Sec. 2.1 must stay >= 0),
@@ -170,7 +177,9 @@ int sdpdem_create(const sdpdem_params* params, const sdpdem_particles* particles
                   sdpdem_system** out);
 
 /* Batched systems: nbox independent boxes advanced together, every kernel
- * launch covering all of them (the batched viscometer).  box_of[k] gives
+ * launch covering all of them (the batched viscometer; each box is one
+ * particle system of Sec. 3.1, run through Alg. 1 like a plain one, and
+ * its viscosity plays the role of the measurement of Sec. 4.1).  box_of[k] gives
  * the box of particle row k; ids run over 0..n-1 across all boxes.  No
  * pair, contact or coupling ever joins particles of different boxes.
  * The thermal noise of a pair is keyed by its box's seed and the two ids
@@ -187,8 +196,11 @@ int sdpdem_create_batch(const sdpdem_params* params, const sdpdem_box* boxes, in
                         void* d_workspace, size_t workspace_bytes, void* hip_stream,
                         sdpdem_system** out);
 
-/* Algorithm 1: nsteps steps of two velocity-Verlet passes each.  Returns the
- * device status (overflow, non-finite, out of domain) seen at the end.
+/* Algorithm 1: nsteps steps of two velocity-Verlet passes each (Sec. 2.6),
+ * each pass the force evaluation of Algorithm 2.  Returns the device status
+ * (overflow, non-finite, out of domain) seen at the end: the call enqueues
+ * the steps on the stream and then synchronises that stream once to read
+ * the status word, so it returns after the steps have run.
  * With rigid particles the library keeps a second stream of its own (at
  * the default priority) for work that does not depend on what runs beside
  * it: the rigid grid beside the neighbour lists, the sphere records and DEM
@@ -197,7 +209,7 @@ int sdpdem_create_batch(const sdpdem_params* params, const sdpdem_box* boxes, in
  * pass, so work the caller orders on its stream sees everything. */
 int sdpdem_step(sdpdem_system* sys, int64_t nsteps, void* hip_stream);
 
-/* Replay the step loop from a captured HIP graph of steps_per_graph steps
+/* Replay the step loop of Algorithm 1 from a captured HIP graph of steps_per_graph steps
  * (an even number; 0 switches it off, the default).  sdpdem_step then runs
  * whole graphs where it can and single steps otherwise; results are the
  * same bits as without graphs.  Capture needs a stream other than the null
@@ -206,38 +218,68 @@ int sdpdem_step(sdpdem_system* sys, int64_t nsteps, void* hip_stream);
  * (itr_actv_rigid) change the launch sequence. */
 int sdpdem_set_graph(sdpdem_system* sys, int steps_per_graph);
 
-/* One evaluation of every force at the current state (Alg. 2), no update. */
+/* One evaluation of every force at the current state (Alg. 2: the list,
+ * density and pressure steps of Alg. 1 when the positions changed, then
+ * compute_fluid, compute_fpi_action, compute_fpi_reaction, compute_rigid),
+ * no update.  Synchronises the stream once to read the status word. */
 int sdpdem_compute_forces(sdpdem_system* sys, void* hip_stream);
 
-/* Copy a field to host memory (dst holds n*comps doubles, id order). */
-int sdpdem_read_field(sdpdem_system* sys, int field, double* dst, size_t bytes,
-                      void* hip_stream);
+/* Copy a field (enum sdpdem_field; the quantities of Secs. 2.1-2.6 and
+ * the outputs of Alg. 1's output(), Sec. 3.3) in id order: dst holds
+ * n * sdpdem_field_comps(field) doubles (row i = id i; 3 components x, y,
+ * z for vector fields).  dst_is_device = 0: dst is host memory and the
+ * call synchronises the stream.  dst_is_device = 1: dst is device memory
+ * (8-byte aligned) and the copy is only enqueued on the stream.
+ * SDPDEM_E_INVALID_ARG for an unknown field, bytes too small, a null or
+ * misaligned dst. */
+int sdpdem_read_field(sdpdem_system* sys, int field, void* dst, size_t bytes,
+                      int dst_is_device, void* hip_stream);
+/* Doubles per row of a field for sdpdem_read_field (1 for the scalars rho,
+ * p of Eqs. compdens and prtcpres, the filtered pressure and eps of Eq.
+ * fvfdef; 3 otherwise; 0 for an unknown field). */
 int sdpdem_field_comps(int field);
 
-/* Neighbour sets of the last build as CSR: row i = neighbours of id i,
- * columns ascending; outer walls have empty rows.  With cols == NULL only
- * row_ptr (n+1 entries) and *nnz are written. */
+/* Neighbour sets of the last build (compute_neighbor_list of Alg. 1, the
+ * per-particle lists of Sec. 3.2: j != i with |r_ij| < h) as CSR in host
+ * memory: row i = neighbours of id i, columns ascending ids; outer walls
+ * have empty rows.  row_ptr holds n+1 entries; cols holds cap entries;
+ * with cols == NULL only row_ptr and *nnz are written.
+ * SDPDEM_E_INVALID_ARG if cap < nnz.  Synchronises the stream. */
 int sdpdem_read_neighbors(sdpdem_system* sys, int64_t* row_ptr, int32_t* cols,
                           int64_t cap, int64_t* nnz, void* hip_stream);
 
-/* Rigid contact table: pairs (i < j) and the tangential displacement held
- * by i (the row of j holds its negative).  pairs == NULL: count only. */
+/* Rigid contact table (the contact flags and tangential displacements
+ * delta_t of Eqs. tandispseq and tandispn, Sec. 2.2, kept per pair as in
+ * the neighbour lists of Sec. 3.2) in host memory: pairs [cap][2] ids
+ * (i < j) and delta_t [cap][3] held by i (the row of j holds its
+ * negative).  pairs == NULL: count only.  SDPDEM_E_INVALID_ARG if cap is
+ * too small.  Synchronises the stream. */
 int sdpdem_read_contacts(sdpdem_system* sys, int32_t* pairs, double* delta_t,
                          int64_t cap, int64_t* n_contacts, void* hip_stream);
-/* Replace the contact table (restart); each pair fills both rows. */
+/* Replace the contact table (restart from a backup, Sec. 3.3; the
+ * history delta_t of Eq. tandispn): pairs [n][2] ids, delta_t [n][3] held
+ * by the first id of each pair; each pair fills both rows.  Host memory.
+ * SDPDEM_E_INVALID_ARG for ids that are not rigid or repeated pairs,
+ * SDPDEM_E_CONTACT_OVERFLOW beyond max_contacts per sphere. */
 int sdpdem_load_contacts(sdpdem_system* sys, const int32_t* pairs,
                          const double* delta_t, int64_t n_contacts,
                          void* hip_stream);
 
-/* FP64 totals over all non-outer-wall particles:
- * out = [P(3), L(3) about the origin, KE_trans, KE_rot, max|v|, min rho,
- *        max rho, total mass, step, 0, 0, 0].  Synchronises. */
+/* FP64 totals of the quantities Eqs. newton1 and newton2 (Sec. 2.6)
+ * evolve, over all non-outer-wall particles, in host memory:
+ * out = [P(3), L(3) about the origin (m x cross v + I omega), KE_trans,
+ *        KE_rot, max|v|, min rho, max rho, total mass, step, 0, 0, 0].
+ * Synchronises the stream. */
 int sdpdem_totals(sdpdem_system* sys, double out[16], void* hip_stream);
 
+/* The step counter of Alg. 1 (itr_start plus the steps taken); -1 for a
+ * null handle. */
 int64_t sdpdem_get_step(const sdpdem_system* sys);
 
-/* Shear-stress sampling for viscometry (not in the paper; Lees-Edwards
- * boxes).  With sampling on, every step ends with one sample per box of
+/* Shear-stress sampling for viscometry: the viscosity the paper measures
+ * from the reverse-Poiseuille mean velocity (Eq. poiseuave, Sec. 4.1) is
+ * measured here from the shear stress of Lees-Edwards boxes (not in the
+ * paper).  With sampling on, every step ends with one sample per box of
  * the pressure-tensor component
  *   P_zx = ( sum_i m_i v'_z v'_x + sum_pairs r_z F_x ) / V,
  * v' = v - shear_rate (z - z_mid) e_x, the pair sum over the SDPD pair
@@ -255,24 +297,33 @@ int sdpdem_set_stress(sdpdem_system* sys, int on, void* hip_stream);
 int sdpdem_box_stress(sdpdem_system* sys, double* inst, double* sum, int64_t* nsamples,
                       void* hip_stream);
 
-/* Diagnostics: out = [n, n_rigid, cells x, y, z of box 0, rigid cells x,
+/* Diagnostics of the background grid and neighbour lists of Alg. 1
+ * (Sec. 3.2), host memory, synchronises:
+ * out = [n, n_rigid, cells x, y, z of box 0, rigid cells x,
  * y, z of box 0, max neighbour count of the last build, pairs of the last
  * build, number of boxes, steps replayed from captured graphs so far,
  * 1 if the contacts run on the library's second stream, 0...]. */
 int sdpdem_info(sdpdem_system* sys, int64_t out[16], void* hip_stream);
 
-/* Time every launch of one kernel (enum sdpdem_kernel) with HIP events on
+/* Per-routine timing, the breakdown of Fig. CompTimeTotal over the
+ * routines of Algs. 1 and 2.
+ * Time every launch of one kernel (enum sdpdem_kernel) with HIP events on
  * the launch stream; SDPDEM_K_NONE switches timing off.  sdpdem_kernel_time
  * returns the accumulated milliseconds and launch count and resets them. */
 int sdpdem_set_profiling(sdpdem_system* sys, int kernel);
 int sdpdem_kernel_time(sdpdem_system* sys, double* total_ms, int64_t* launches);
-/* Time only the first of every `every` launches of the profiled kernel
+/* Sampled per-routine timing for the breakdown of Fig. CompTimeTotal.
+ * Time only the first of every `every` launches of the profiled kernel
  * (every >= 1; 1, the default, times all): the timing events perturb the
  * stream less, and sdpdem_kernel_time counts the timed launches only.
  * Resets the count; SDPDEM_E_INVALID_ARG for every < 1. */
 int sdpdem_set_profiling_every(sdpdem_system* sys, int every);
 
+/* Release the handle of a particle system (Sec. 3.1); the caller frees
+ * the workspace afterwards.  A null handle is ignored. */
 void sdpdem_destroy(sdpdem_system* sys);
+/* Name of a status code: the argument checks of the parameter table
+ * (Table ipparam) and the run-time checks of Alg. 1's steps. */
 const char* sdpdem_status_string(int status);
 
 #ifdef __cplusplus

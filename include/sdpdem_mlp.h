@@ -40,31 +40,42 @@ typedef struct sdpdem_mlp_config {
 
 typedef struct sdpdem_mlp sdpdem_mlp;
 
+/* Bytes of device workspace for the network that stands in for the
+ * viscosity measurement of Secs. 4.1 and 4.3 (Eq. poiseuave): parameters,
+ * bfloat16 copies, gradients, Adam moments and a batch of activations.
+ * Touches no device. */
 int sdpdem_mlp_workspace_bytes(const sdpdem_mlp_config* cfg, size_t* bytes);
 
-/* init_params: host float32[SDPDEM_MLP_PARAMS] in the order W1 [4 x 64]
+/* Create the surrogate of the effective viscosity of Secs. 4.1 and 4.3.
+ * init_params: host float32[SDPDEM_MLP_PARAMS] in the order W1 [4 x 64]
  * row-major (input-major), b1[64], W2 [64 x 64], b2, W3 [64 x 64], b3,
  * W4 [64 x 1], b4[1].  Rejects std <= 0, lr <= 0, betas outside [0, 1),
  * eps < 0, max_batch outside 1..256, a short or missing workspace. */
 int sdpdem_mlp_create(const sdpdem_mlp_config* cfg, const float* init_params, void* d_workspace,
                       size_t workspace_bytes, void* hip_stream, sdpdem_mlp** out);
 
-/* y[i] = network(x[i]) for i < n; x: device float32 [n][4], y: device
- * float32 [n]. */
+/* Answer viscosity queries in place of runs of Alg. 1 (Secs. 4.1, 4.3):
+ * y[i] = network(x[i]) for i < n; x: device float32 [n][4], y: device
+ * float32 [n].  Only enqueues. */
 int sdpdem_mlp_predict(sdpdem_mlp* m, const float* d_x, float* d_y, int64_t n, void* hip_stream);
 
-/* One training step on a batch (device x [batch][4], targets t [batch]):
+/* One training step towards viscosities measured by the batched runs of
+ * Alg. 1 (the measurement of Sec. 4.1 on sheared boxes), on a batch
+ * (device x [batch][4], targets t [batch]):
  * forward, loss, backward; with update != 0 also one Adam step.  The loss
  * and gradient of the step stay readable with sdpdem_mlp_read. */
 int sdpdem_mlp_train_step(sdpdem_mlp* m, const float* d_x, const float* d_t, int32_t batch,
                           int32_t update, void* hip_stream);
 
-/* Host copies (any pointer may be NULL): float32 master parameters, the
+/* State of the viscosity surrogate (Secs. 4.1, 4.3), synchronises.
+ * Host copies (any pointer may be NULL): float32 master parameters, the
  * parameters as used (bfloat16 values widened to float32), the gradient of
  * the last train_step, its loss, and the number of Adam steps taken. */
 int sdpdem_mlp_read(sdpdem_mlp* m, float* params, float* used_params, float* grad, float* loss,
                     int64_t* steps, void* hip_stream);
 
+/* Release the surrogate's handle (the viscosity model of Secs. 4.1,
+ * 4.3); the caller frees the workspace afterwards. */
 void sdpdem_mlp_destroy(sdpdem_mlp* m);
 
 #ifdef __cplusplus

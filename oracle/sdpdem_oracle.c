@@ -50,7 +50,8 @@
  *      where x[axis] - org[axis] < L[axis]/2.
  *  R14 Periodic axes use the minimum image (no halo copies); a wall axis
  *      mirrors a particle that leaves [org, org+L] and reverses its velocity
- *      (all components for no-slip, the normal one for slip).
+ *      (the normal component of every face crossed for slip; for no-slip
+ *      the whole velocity, once per drift even at an edge or corner).
  *  R15 The neighbour test is r^2 < h^2, strict, with
  *      r^2 = (dx*dx + dy*dy) + dz*dz in double precision.
  *  R19 Lees-Edwards shear (not in the paper; for the viscometer): flow
@@ -959,6 +960,7 @@ static int update(oracle_system* s, int velver) {
         if (x[0] < P->org[0]) x[0] += P->L[0];
         else if (x[0] >= P->org[0] + P->L[0]) x[0] -= P->L[0];
       }
+      int hit = 0; /* a wall face was crossed in this drift */
       for (int a = 0; a < 3; ++a) {
         double lo = P->org[a], hi = P->org[a] + P->L[a];
         double* x = &s->pos[3 * i + a];
@@ -967,13 +969,15 @@ static int update(oracle_system* s, int velver) {
           else if (*x >= hi) *x -= P->L[a];
         } else if (*x < lo || *x > hi) {
           *x = (*x < lo) ? 2.0 * lo - *x : 2.0 * hi - *x;
-          if (P->noslip)
-            for (int b = 0; b < 3; ++b) s->vel[3 * i + b] = -s->vel[3 * i + b];
-          else
-            s->vel[3 * i + a] = -s->vel[3 * i + a];
+          hit = 1;
+          if (!P->noslip) s->vel[3 * i + a] = -s->vel[3 * i + a];
           if (*x < lo || *x > hi) out = 1;
         }
       }
+      /* no-slip: the whole velocity is reversed once, however many faces
+       * (an edge or a corner) the drift crossed */
+      if (hit && P->noslip)
+        for (int b = 0; b < 3; ++b) s->vel[3 * i + b] = -s->vel[3 * i + b];
     }
     for (int a = 0; a < 3; ++a)
       if (!isfinite(s->vel[3 * i + a]) || !isfinite(s->w[3 * i + a]) ||

@@ -1098,13 +1098,20 @@ int sdpdem_box_stress(sdpdem_system* s, double* inst, double* sum, int64_t* nsam
   return hipGetLastError() == hipSuccess ? SDPDEM_OK : SDPDEM_E_HIP;
 }
 
-int sdpdem_read_field(sdpdem_system* s, int field, double* dst, size_t bytes, void* hip_stream) {
+int sdpdem_read_field(sdpdem_system* s, int field, void* dst, size_t bytes, int dst_is_device,
+                      void* hip_stream) {
   if (!s || !dst) return SDPDEM_E_INVALID_ARG;
   int comps = sdpdem_field_comps(field);
   if (comps == 0) return SDPDEM_E_INVALID_ARG;
   size_t need = (size_t)s->d.n * comps * sizeof(double);
   if (bytes < need) return SDPDEM_E_INVALID_ARG;
   hipStream_t st = (hipStream_t)hip_stream;
+  if (dst_is_device) {
+    // the gather kernel writes the id-ordered rows straight into dst
+    if ((uintptr_t)dst % alignof(double) != 0) return SDPDEM_E_INVALID_ARG;
+    launch_read_field(s->d, field, rigid_active(s) ? 1 : 0, static_cast<double*>(dst), st);
+    return hipGetLastError() == hipSuccess ? SDPDEM_OK : SDPDEM_E_HIP;
+  }
   launch_read_field(s->d, field, rigid_active(s) ? 1 : 0, s->field_buf, st);
   if (hipMemcpyAsync(dst, s->field_buf, need, hipMemcpyDeviceToHost, st) != hipSuccess)
     return SDPDEM_E_HIP;

@@ -1016,6 +1016,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
       else if (x[0] >= B.org[0] + B.L[0])
         x[0] -= B.L[0];
     }
+    bool hit = false;  // a wall face was crossed in this drift
     for (int a = 0; a < 3; ++a) {
       double lo = B.org[a], hi = B.org[a] + B.L[a];
       if (B.per[a]) {
@@ -1025,15 +1026,16 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
           x[a] -= B.L[a];
       } else if (x[a] < lo || x[a] > hi) {
         x[a] = x[a] < lo ? 2.0 * lo - x[a] : 2.0 * hi - x[a];
-        if (d.noslip) {
-          vv[0] = -vv[0];
-          vv[1] = -vv[1];
-          vv[2] = -vv[2];
-        } else {
-          vv[a] = -vv[a];
-        }
+        hit = true;
+        if (!d.noslip) vv[a] = -vv[a];  // slip: the normal component
         if (x[a] < lo || x[a] > hi) bad |= ST_OUT_OF_DOMAIN;
       }
+    }
+    // no-slip: the whole velocity reversed once, also at an edge or corner
+    if (hit && d.noslip) {
+      vv[0] = -vv[0];
+      vv[1] = -vv[1];
+      vv[2] = -vv[2];
     }
     p.x = x[0];
     p.y = x[1];

@@ -112,7 +112,7 @@ def lib():
         L.sdpdem_box_stress.argtypes = [vp, vp, vp, ctypes.POINTER(i64), vp]
         L.sdpdem_step.argtypes = [vp, i64, vp]
         L.sdpdem_compute_forces.argtypes = [vp, vp]
-        L.sdpdem_read_field.argtypes = [vp, ctypes.c_int, vp, sz, vp]
+        L.sdpdem_read_field.argtypes = [vp, ctypes.c_int, vp, sz, ctypes.c_int, vp]
         L.sdpdem_field_comps.argtypes = [ctypes.c_int]
         L.sdpdem_read_neighbors.argtypes = [vp, vp, vp, i64, ctypes.POINTER(i64), vp]
         L.sdpdem_read_contacts.argtypes = [vp, vp, vp, i64, ctypes.POINTER(i64), vp]
@@ -278,13 +278,23 @@ def sdpdem_compute_forces(h, stream=None) -> int:
     return lib().sdpdem_compute_forces(h, _stream(stream))
 
 
-def sdpdem_read_field(h, name: str, n: int, stream=None) -> np.ndarray:
+def sdpdem_read_field(h, name: str, n: int, stream=None, out=None):
+    """Host copy (numpy) of a field in id order; with `out` a float64 device
+    tensor of n x comps elements the rows are written there instead and the
+    copy is only enqueued on the stream."""
     f = FIELDS[name]
     c = lib().sdpdem_field_comps(f)
-    out = np.empty((n, c), dtype=np.float64)
-    _check(lib().sdpdem_read_field(h, f, out.ctypes.data, out.nbytes, _stream(stream)),
+    if out is not None:
+        if not out.is_cuda or out.dtype.itemsize != 8 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 device tensor")
+        _check(lib().sdpdem_read_field(h, f, ctypes.c_void_p(out.data_ptr()),
+                                       out.numel() * 8, 1, _stream(stream)),
+               "sdpdem_read_field")
+        return out
+    host = np.empty((n, c), dtype=np.float64)
+    _check(lib().sdpdem_read_field(h, f, host.ctypes.data, host.nbytes, 0, _stream(stream)),
            "sdpdem_read_field")
-    return out if c > 1 else out[:, 0]
+    return host if c > 1 else host[:, 0]
 
 
 def sdpdem_read_neighbors(h, n: int, stream=None):
@@ -394,8 +404,8 @@ class System:
             _check(rc, "sdpdem_compute_forces")
         return rc
 
-    def read_field(self, name):
-        return sdpdem_read_field(self.h, name, self.n, self.stream)
+    def read_field(self, name, out=None):
+        return sdpdem_read_field(self.h, name, self.n, self.stream, out=out)
 
     def read_neighbors(self):
         return sdpdem_read_neighbors(self.h, self.n, self.stream)

@@ -107,3 +107,30 @@ def test_create_rejects_small_workspace_without_device(lib):
     rc = lib.sdpdem_create(ctypes.byref(pp), ctypes.byref(q), None, 1 << 30, None,
                            ctypes.byref(h))
     assert rc == S.E_INVALID_ARG
+
+
+_CITE = re.compile(r"\b(Sec\.|Secs\.|Eq\.|Eqs\.|Alg\.|Algs\.|Algorithms?|Table|Fig\.)\s")
+
+
+def _declarations_with_comments():
+    """(header, symbol, the comment block that precedes its declaration)."""
+    import glob
+    out = []
+    for f in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))):
+        src = open(f).read()
+        # top-level declarations: a line that starts with a type and names sdpdem_*(
+        for m in re.finditer(r"^(?:const\s+)?[a-z_0-9]+\s*\**\s*(sdpdem_[a-z_]+)\s*\(", src,
+                             re.M):
+            before = src[:m.start()]
+            end = before.rfind("*/")
+            start = before.rfind("/*", 0, end) if end >= 0 else -1
+            out.append((os.path.basename(f), m.group(1),
+                        before[start:end] if start >= 0 else ""))
+    return out
+
+
+def test_every_declaration_cites_its_passage():
+    decls = _declarations_with_comments()
+    assert len(decls) >= 25
+    missing = [(h, name) for h, name, c in decls if not _CITE.search(c)]
+    assert not missing, missing

@@ -187,6 +187,27 @@ def test_wall_reflection(oracle_lib, noslip):
     assert x[1] == pytest.approx(5.0 + 0.3 * 0.6 + (-0.3 if noslip else 0.3) * 0.4, abs=1e-12)
 
 
+@pytest.mark.parametrize("noslip", [1, 0])
+def test_wall_corner_reflection(oracle_lib, noslip):
+    """A drift that crosses two wall faces at once (an edge of the box):
+    both coordinates are mirrored; no-slip reverses the whole velocity once
+    (a second reversal would leave it unchanged), slip reverses the two
+    normal components (Sec. 2.5)."""
+    p, parts, _ = W.random_box(1, (10.0, 10.0, 10.0), (0, 0, 1), seed=0)
+    p.update(kBT=0.0, dt=0.1, noslip=noslip)
+    parts["pos"][0] = [9.95, 0.08, 5.0]
+    parts["vel"][0] = [1.0, -1.0, 0.25]
+    o = oracle_lib.Oracle(p, parts)
+    o.step(1)
+    x = o.read_field("POS")[0]
+    v = o.read_field("VEL")[0]
+    assert x[0] == pytest.approx(2 * 10.0 - 10.05, abs=1e-12)
+    assert x[1] == pytest.approx(-(0.08 - 0.1), abs=1e-12)
+    assert x[2] == pytest.approx(5.025, abs=1e-12)
+    expect = [-1.0, 1.0, -0.25] if noslip else [-1.0, 1.0, 0.25]
+    assert list(v) == expect
+
+
 def test_error_codes(oracle_lib):
     O = oracle_lib
     p, parts, _ = W.reverse_poiseuille(n_side=(6, 6, 6), kBT=0.0)
