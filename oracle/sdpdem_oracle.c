@@ -503,7 +503,7 @@ static void query_ball(const oracle_system* s, const double* x, double R,
       }
     }
   }
-  qsort(out->v, (size_t)out->n, sizeof(int32_t), cmp_i32);
+  if (out->n > 1) qsort(out->v, (size_t)out->n, sizeof(int32_t), cmp_i32);
 }
 
 #define ALL_TYPES 0xFu

@@ -10,10 +10,15 @@ from paper_2002_03120_amd import workloads as W
 MU, RHO = 0.1, 1.0
 
 
-def _drag_force(oracle_lib, eps, dv, d):
+def _drag_force(oracle_lib, eps, dv, d, rho=RHO):
     """Per-particle drag magnitude B V_s |dv| (B = beta/(1-eps))."""
     vs = math.pi * d ** 3 / 6.0
-    return oracle_lib.drag_b(eps, dv, d, RHO, MU) * vs * dv
+    return oracle_lib.drag_b(eps, dv, d, rho, MU) * vs * dv
+
+
+# the fluid densities of the workloads: 1 and the slurry channel's 3 (Sec. 4.1),
+# where a density dropped from Re_p or from the inertial terms shows
+DENSITIES = [1.0, 3.0]
 
 
 @pytest.mark.parametrize("d", [1.0, 3.0, 8.0])
@@ -22,35 +27,38 @@ def test_stokes_limit(oracle_lib, d):
     assert _drag_force(oracle_lib, 1.0, dv, d) == pytest.approx(3 * math.pi * MU * d * dv, rel=1e-6)
 
 
+@pytest.mark.parametrize("rho", DENSITIES)
 @pytest.mark.parametrize("re", [0.5, 10.0, 300.0, 999.0])
-def test_single_sphere_drag_equation(oracle_lib, re):
+def test_single_sphere_drag_equation(oracle_lib, re, rho):
     # F = 1/2 C_D rho A v^2 with C_D = 24/Re (1 + 0.15 Re^0.687), A = pi d^2/4
     d = 2.0
-    dv = re * MU / (RHO * d)
+    dv = re * MU / (rho * d)
     cd = 24.0 / re * (1.0 + 0.15 * re ** 0.687)
-    expect = 0.5 * cd * RHO * math.pi * d * d / 4.0 * dv * dv
-    assert _drag_force(oracle_lib, 1.0, dv, d) == pytest.approx(expect, rel=1e-12)
+    expect = 0.5 * cd * rho * math.pi * d * d / 4.0 * dv * dv
+    assert _drag_force(oracle_lib, 1.0, dv, d, rho) == pytest.approx(expect, rel=1e-12)
 
 
+@pytest.mark.parametrize("rho", DENSITIES)
 @pytest.mark.parametrize("eps", [0.81, 0.9, 1.0])
-def test_newton_regime_with_voidage_factor(oracle_lib, eps):
+def test_newton_regime_with_voidage_factor(oracle_lib, eps, rho):
     # Re_p > 1000: C_D = 0.44 and the swarm factor eps^(-1.65) of Wen and Yu
     d = 2.0
-    dv = 5000.0 * MU / (RHO * d * eps)
-    expect = 0.5 * 0.44 * RHO * math.pi * d * d / 4.0 * dv * dv * eps ** -1.65
-    assert _drag_force(oracle_lib, eps, dv, d) == pytest.approx(expect, rel=1e-12)
+    dv = 5000.0 * MU / (rho * d * eps)
+    expect = 0.5 * 0.44 * rho * math.pi * d * d / 4.0 * dv * dv * eps ** -1.65
+    assert _drag_force(oracle_lib, eps, dv, d, rho) == pytest.approx(expect, rel=1e-12)
 
 
+@pytest.mark.parametrize("rho", DENSITIES)
 @pytest.mark.parametrize("eps", [0.35, 0.5, 0.8])
 @pytest.mark.parametrize("dv", [1e-3, 0.2, 3.0])
-def test_ergun_pressure_drop(oracle_lib, eps, dv):
+def test_ergun_pressure_drop(oracle_lib, eps, dv, rho):
     # dense branch: the interphase force per bed volume beta |dv| balances
     # eps times the Ergun pressure gradient at superficial velocity eps |dv|
     d = 1.5
     U = eps * dv
     dpdl = (150.0 * MU * (1 - eps) ** 2 * U / (eps ** 3 * d * d)
-            + 1.75 * RHO * (1 - eps) * U * U / (eps ** 3 * d))
-    beta = oracle_lib.drag_b(eps, dv, d, RHO, MU) * (1.0 - eps)
+            + 1.75 * rho * (1 - eps) * U * U / (eps ** 3 * d))
+    beta = oracle_lib.drag_b(eps, dv, d, rho, MU) * (1.0 - eps)
     assert beta * dv == pytest.approx(eps * dpdl, rel=1e-12)
 
 
