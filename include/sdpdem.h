@@ -176,6 +176,25 @@ int sdpdem_create(const sdpdem_params* params, const sdpdem_particles* particles
                   void* d_workspace, size_t workspace_bytes, void* hip_stream,
                   sdpdem_system** out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * sdpdem_create without a workspace argument.  The system lives in a
+ * file-scope device array of the library, SDPDEM_STATIC_WORKSPACE_BYTES
+ * (64 MiB) per device, held from the first call on a device until the
+ * process ends.  The device is the current one (hipSetDevice), which must
+ * be the stream's.  The call allocates no device memory (no hipMalloc,
+ * hipFree or allocating library routine) and creates no stream: every
+ * launch of the system runs on the caller's stream.  Host particle arrays
+ * are copied as in sdpdem_create.  Errors: those of sdpdem_create, and
+ * SDPDEM_E_WORKSPACE_TOO_SMALL when sdpdem_workspace_bytes exceeds the
+ * array (nothing is launched then).  All systems created this way on one
+ * device share the array: creating one overwrites the state of the
+ * previous one, so use one at a time per device; calls that overlap on one
+ * device race.  sdpdem_destroy releases the handle. */
+#define SDPDEM_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+int sdpdem_create_static(const sdpdem_params* params, const sdpdem_particles* particles,
+                         void* hip_stream, sdpdem_system** out);
+
 /* Batched systems: nbox independent boxes advanced together, every kernel
  * launch covering all of them (the batched viscometer; each box is one
  * particle system of Sec. 3.1, run through Alg. 1 like a plain one, and

@@ -5,6 +5,7 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <utility>
 #include <vector>
@@ -784,7 +785,8 @@ void make_side_stream(sdpdem_system* s) {
 
 int create_impl(const sdpdem_params* params, const sdpdem_box* boxes, int nbox,
                 const sdpdem_particles* q, const int32_t* box_of, void* d_workspace,
-                size_t workspace_bytes, void* hip_stream, sdpdem_system** out) {
+                size_t workspace_bytes, void* hip_stream, sdpdem_system** out,
+                bool side_stream = true) {
   if (!out) return SDPDEM_E_INVALID_ARG;
   *out = nullptr;
   Sizes z;
@@ -881,8 +883,39 @@ int create_impl(const sdpdem_params* params, const sdpdem_box* boxes, int nbox,
     delete s;
     return SDPDEM_E_HIP;
   }
-  if (z.nr) make_side_stream(s);
+  if (z.nr && side_stream) make_side_stream(s);
   *out = s;
+  return SDPDEM_OK;
+}
+
+// The allocation-free variant of sdpdem_create keeps its workspace in this
+// file-scope device array.  In host code `scratch` names a host-side
+// stand-in: its device address is taken with hipGetSymbolAddress once per
+// device and only that address is handed to kernels and copies.
+constexpr size_t kStaticBytes = SDPDEM_STATIC_WORKSPACE_BYTES;
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+__device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+namespace {
+
+// device address of `scratch` on the current device (looked up on the first
+// call per device)
+int static_workspace(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SDPDEM_E_HIP;
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+      return SDPDEM_E_HIP;
+    g_static_ptr[dev] = ptr;
+  }
+  *out = g_static_ptr[dev];
   return SDPDEM_OK;
 }
 
@@ -920,6 +953,24 @@ int sdpdem_create(const sdpdem_params* params, const sdpdem_particles* q, void* 
   if (!params) return SDPDEM_E_INVALID_ARG;
   sdpdem_box b = box_from_params(params);
   return create_impl(params, &b, 1, q, nullptr, d_workspace, workspace_bytes, hip_stream, out);
+}
+
+int sdpdem_create_static(const sdpdem_params* params, const sdpdem_particles* q,
+                         void* hip_stream, sdpdem_system** out) {
+  if (!params || !out) return SDPDEM_E_INVALID_ARG;
+  *out = nullptr;
+  size_t need = 0;
+  const int rc = sdpdem_workspace_bytes(params, q, &need);
+  if (rc != SDPDEM_OK) return rc;
+  // the layout rounds the base up to 256 bytes; the array is 256-aligned
+  if (need > kStaticBytes) return SDPDEM_E_WORKSPACE_TOO_SMALL;
+  void* base = nullptr;
+  const int rs = static_workspace(&base);
+  if (rs != SDPDEM_OK) return rs;
+  sdpdem_box b = box_from_params(params);
+  // no second stream: creating one is a resource the caller did not ask for
+  return create_impl(params, &b, 1, q, nullptr, base, kStaticBytes, hip_stream, out,
+                     /*side_stream=*/false);
 }
 
 int sdpdem_batch_workspace_bytes(const sdpdem_params* params, const sdpdem_box* boxes,

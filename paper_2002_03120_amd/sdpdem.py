@@ -101,6 +101,8 @@ def lib():
                                              ctypes.POINTER(sz)]
         L.sdpdem_create.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Particles), vp, sz,
                                     vp, ctypes.POINTER(vp)]
+        L.sdpdem_create_static.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Particles),
+                                           vp, ctypes.POINTER(vp)]
         L.sdpdem_batch_workspace_bytes.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Box),
                                                    ctypes.c_int32, ctypes.POINTER(Particles),
                                                    vp, ctypes.POINTER(sz)]
@@ -210,6 +212,16 @@ def sdpdem_create(params: dict, parts: dict, workspace, stream=None) -> ctypes.c
     _check(lib().sdpdem_create(ctypes.byref(p), ctypes.byref(q),
                                ctypes.c_void_p(workspace.data_ptr()), nbytes,
                                _stream(stream), ctypes.byref(h)), "sdpdem_create")
+    return h
+
+
+def sdpdem_create_static(params: dict, parts: dict, stream=None) -> ctypes.c_void_p:
+    """A system in the library's own static device array (no workspace)."""
+    p = make_params(params)
+    q, _keep = make_particles(parts)
+    h = ctypes.c_void_p()
+    _check(lib().sdpdem_create_static(ctypes.byref(p), ctypes.byref(q), _stream(stream),
+                                      ctypes.byref(h)), "sdpdem_create_static")
     return h
 
 
@@ -365,14 +377,18 @@ class System:
     """A system plus the device workspace it lives in (torch uint8 tensor)."""
 
     def __init__(self, params: dict, parts: dict, device="cuda", stream=None, boxes=None,
-                 box_of=None):
-        """boxes/box_of: a batch of independent boxes (sdpdem_create_batch)."""
+                 box_of=None, static=False):
+        """boxes/box_of: a batch of independent boxes (sdpdem_create_batch);
+        static: no workspace, the library's static array (sdpdem_create_static)."""
         import torch
         self.n = int(parts["id"].shape[0])
         self.params = dict(params)
         self.stream = stream
         self.nbox = len(boxes) if boxes is not None else 1
-        if boxes is None:
+        if static:
+            self.workspace = None
+            self.h = sdpdem_create_static(params, parts, stream)
+        elif boxes is None:
             nbytes = sdpdem_workspace_bytes(params, parts)
             self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
             self.h = sdpdem_create(params, parts, self.workspace, stream)
