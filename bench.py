@@ -47,24 +47,27 @@ PAIR_KERNEL_SOURCES = ("paper_2002_03120_amd/csrc/sdpdem_neighbors.hip",
                        "paper_2002_03120_amd/csrc/sdpdem_internal.h")
 
 
-def profiled_counters():
-    """HBM traffic and VALU figures of the pair kernel from the committed
-    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE runs scaled by a
-    plain copy of known size).  Returned only while the kernel sources hash
-    to the value recorded with the counters; otherwise None."""
+def pair_kernel_sha256():
     import hashlib
-    import re
-    path = os.path.join(ROOT, "profiles", "fluid_forces_dam_break_pmc.md")
-    if not os.path.exists(path):
-        return None
-    kv = dict(re.findall(r"^\s{4}(\w+): (\S+)\s*$", open(path).read(), flags=re.M))
     h = hashlib.sha256()
     for f in PAIR_KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    if kv.get("source_sha256") != h.hexdigest():
+    return h.hexdigest()
+
+
+def profiled_counters(name="fluid_forces_dam_break_pmc.md"):
+    """Counter figures of the pair kernel from a committed rocprofv3 summary
+    in profiles/ (its machine-readable block).  Returned only while the
+    kernel sources hash to the value recorded with the counters (a changed
+    kernel invalidates them); otherwise None."""
+    import re
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
         return None
-    return {"traffic": float(kv["traffic_bytes_per_launch"]), "valu_busy": float(kv["valu_busy"]),
-            "lane_use": float(kv["lane_use"])}
+    kv = dict(re.findall(r"^\s{4}(\w+): (\S+)\s*$", open(path).read(), flags=re.M))
+    if kv.get("source_sha256") != pair_kernel_sha256():
+        return None
+    return {k: float(v) for k, v in kv.items() if k not in ("kernel", "source_sha256")}
 
 
 def viscometer_leg(k_steps, n_cells=256, run_steps=5000, graph_steps=10, tune=True):
@@ -166,14 +169,70 @@ def scale_leg(steps, cell_factor, warmup=2):
     del g
     torch.cuda.empty_cache()
     n = int(info["n"])
-    return {
+    k_avg_s = k_ms / max(k_launches, 1) / 1e3
+    res = {
         "particles": n, "steps": steps, "warmup": warmup, "kT": p["kBT"],
         "cell_factor": cell_factor,
         "ms_per_step": round(wall / steps * 1e3, 4),
         "particle_steps_per_s": round(n * steps / wall, 1),
         "pair_interactions_per_s": round(2 * nnz * steps / wall, 1),
-        "pair_kernel_ms": round(k_ms / max(k_launches, 1), 4),
+        "pair_kernel_ms": round(k_avg_s * 1e3, 4),
     }
+    # With thermal noise the pair kernel is bound by vector-ALU issue: its
+    # roofline is VALU lane-instructions per second against the plain issue
+    # peak, the instructions per neighbour slot taken from the committed
+    # counter run (SQ_INSTS_VALU x 64 / slots) while the sources match it.
+    prof = profiled_counters("fluid_forces_noise_scale_pmc.md")
+    if prof and "valu_lane_instr_per_slot" in prof:
+        achieved = prof["valu_lane_instr_per_slot"] * nnz / k_avg_s / 1e9
+        res["roofline"] = {
+            "kernel": "fluid_forces (thermal)", "bound": "alu", "unit": "G lane-instr/s",
+            "achieved": round(achieved, 1), "peak": VALU_PEAK_GOPS,
+            "frac": round(achieved / VALU_PEAK_GOPS, 4),
+            "instr_per_slot": prof["valu_lane_instr_per_slot"],
+            "slots_per_launch": nnz, "avg_launch_ms": round(k_avg_s * 1e3, 4),
+            "valu_busy_counter": prof.get("valu_busy"),
+        }
+    return res
+
+
+def window_leg(sysm, p, start_step, steps, n_moving):
+    """A timing window later in the dam break: the system is advanced
+    (untimed) to start_step, then `steps` steps are timed; the neighbour
+    slots per active particle show how the collapse changes the work."""
+    import torch
+    cur = sysm.current_step
+    if start_step > cur:
+        sysm.step(start_step - cur)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sysm.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    inf = sysm.info()
+    tot = sysm.totals()
+    return {"from_step": start_step, "steps": steps, "ms_per_step": round(wall / steps * 1e3, 4),
+            "moving_particle_steps_per_s": round(n_moving * steps / wall, 1),
+            "pair_slots": int(inf[9]), "max_speed": round(float(tot[8]), 4),
+            "time": round(start_step * p["dt"], 3)}
+
+
+def cpu_model():
+    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.strip().startswith("Model name:"):
+                return ln.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
+                        None)
+    except OSError:
+        return None
 
 
 def graph_ms_per_step(p, parts, steps, graph_steps=10):
@@ -217,6 +276,9 @@ def main():
                     help="timed steps of the 8,388,608-particle periodic scale run (0: skip)")
     ap.add_argument("--viscometer-steps", type=int, default=20,
                     help="timed steps per configuration of the batched-viscometer leg (0: skip)")
+    ap.add_argument("--window-step", type=int, default=2000,
+                    help="also time --window-steps steps from this step of the collapse (0: skip)")
+    ap.add_argument("--window-steps", type=int, default=20)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -300,6 +362,14 @@ def main():
         roof["valu_busy"] = prof["valu_busy"]
         roof["valu_lane_use"] = prof["lane_use"]
     tot = sysm.totals()
+    status_after = {"max_speed": float(tot[8]), "rho_min": float(tot[9]), "rho_max": float(tot[10])}
+    slots_first = nnz
+    windows = [{"from_step": args.warmup, "steps": args.steps,
+                "ms_per_step": round(wall / args.steps * 1e3, 4), "pair_slots": slots_first,
+                "note": "the headline window above"}]
+    if args.window_step > 0 and args.window_steps > 0:
+        windows.append(window_leg(sysm, p, max(args.window_step, args.warmup + args.steps),
+                                  args.window_steps, info["n_moving"]))
     result = {
         "metric": "particle-steps/s at 1M SDPD+20k DEM",
         "value": round(value, 1),
@@ -323,8 +393,8 @@ def main():
         "cell_size_trials": None if tuned is None else
             {f"{t['cell_factor']}h": round(t["step_ms"], 4) for t in tuned["trials"] if "step_ms" in t},
         "roofline": roof,
-        "status_after": {"max_speed": float(tot[8]), "rho_min": float(tot[9]),
-                         "rho_max": float(tot[10])},
+        "status_after": status_after,
+        "windows": windows,
     }
 
     del sysm
@@ -359,13 +429,15 @@ def main():
         o.step(1)
         t_one_core = time.perf_counter() - t0
         O.set_num_threads(cores)
-        model = None
-        try:
-            with open("/proc/cpuinfo") as f:
-                model = next((ln.split(":", 1)[1].strip() for ln in f
-                              if ln.startswith("model name")), None)
-        except OSError:
-            pass
+        del o
+        # the reverse-Poiseuille box (8,000 particles, 200 steps) in full
+        pc, partsc, infoc = W.reverse_poiseuille()
+        oc = O.Oracle(pc, partsc)
+        t0 = time.perf_counter()
+        oc.step(infoc["steps"])
+        t_c1 = time.perf_counter() - t0
+        del oc
+        model = cpu_model()
         result["cpu_baseline"] = {
             "value": round(info["n_moving"] * steps_cpu / t_cpu, 1),
             "unit": "moving-particle-steps/s",
@@ -376,6 +448,11 @@ def main():
             "one_core_value": round(info["n_moving"] / t_one_core, 1),
             "one_core_sample": f"the next step on one thread ({t_one_core:.1f} s)",
             "cpu_model": model,
+            "reverse_poiseuille_full": {
+                "particles": int(infoc["n"]), "steps": int(infoc["steps"]),
+                "seconds": round(t_c1, 2),
+                "particle_steps_per_s": round(infoc["n"] * infoc["steps"] / t_c1, 1),
+                "cores": cores},
         }
     print(json.dumps(result), flush=True)
 
