@@ -177,6 +177,7 @@ def scale_leg(steps, cell_factor, warmup=2):
         "particle_steps_per_s": round(n * steps / wall, 1),
         "pair_interactions_per_s": round(2 * nnz * steps / wall, 1),
         "pair_kernel_ms": round(k_avg_s * 1e3, 4),
+        "pair_slots": nnz,
     }
     # With thermal noise the pair kernel is bound by vector-ALU issue: its
     # roofline is VALU lane-instructions per second against the plain issue
@@ -190,10 +191,50 @@ def scale_leg(steps, cell_factor, warmup=2):
             "achieved": round(achieved, 1), "peak": VALU_PEAK_GOPS,
             "frac": round(achieved / VALU_PEAK_GOPS, 4),
             "instr_per_slot": prof["valu_lane_instr_per_slot"],
+            # measured HBM bytes per launch (FETCH_SIZE, WRITE_SIZE), profiles/
+            "traffic": round(prof["traffic_bytes_per_launch"]),
             "slots_per_launch": nnz, "avg_launch_ms": round(k_avg_s * 1e3, 4),
             "valu_busy_counter": prof.get("valu_busy"),
         }
     return res
+
+
+def measured_peaks():
+    """The chip's measured plain-FMA issue rates (FP32 and FP64, 8 chains of
+    dependent fused multiply-adds per thread, unpacked) and device copy
+    bandwidth (2 GiB, read + write), from the benchmark's helper library."""
+    import ctypes
+
+    import torch
+
+    from paper_2002_03120_amd import build as B
+    if not os.path.exists(B.PEAKS_LIB):
+        return None
+    L = ctypes.CDLL(B.PEAKS_LIB)
+    L.sdpdem_peak_fma.restype = ctypes.c_double
+    L.sdpdem_peak_fma.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                  ctypes.c_void_p]
+    L.sdpdem_peak_copy.restype = ctypes.c_double
+    L.sdpdem_peak_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                   ctypes.c_void_p]
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    blocks = 256 * 32
+    out = torch.empty(blocks, dtype=torch.float64, device="cuda")
+    f32 = L.sdpdem_peak_fma(0, blocks, 4096, ctypes.c_void_p(out.data_ptr()), st)
+    f64 = L.sdpdem_peak_fma(1, blocks, 2048, ctypes.c_void_p(out.data_ptr()), st)
+    nbytes = 2 << 30
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    cp = L.sdpdem_peak_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                            nbytes, st)
+    torch.cuda.synchronize()
+    del src, dst, out
+    torch.cuda.empty_cache()
+    return {"fp32_fma_lane_ops_per_s": round(f32, 1), "fp64_fma_lane_ops_per_s": round(f64, 1),
+            "copy_bytes_per_s": round(cp, 1),
+            "note": "8 chains of dependent unpacked FMAs per thread, 8192 x 256 threads; "
+                    "a 2 GiB device copy (read + write bytes)"}
 
 
 def window_leg(sysm, p, start_step, steps, n_moving):
@@ -295,6 +336,7 @@ def main():
     from paper_2002_03120_amd import workloads as W
 
     torch.cuda.set_device(0)
+    peaks = measured_peaks()
     if args.calibrate_copy_mib:
         src = torch.empty(args.calibrate_copy_mib << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -352,7 +394,7 @@ def main():
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         # measured HBM bytes per launch (rocprofv3 counters, profiles/)
-        "traffic": round(prof["traffic"]) if prof else None,
+        "traffic": round(prof["traffic_bytes_per_launch"]) if prof else None,
         "avg_launch_ms": round(k_avg_s * 1e3, 4),
         "launches": k_launches,
         "timed_every": PROF_EVERY,
@@ -361,6 +403,8 @@ def main():
     if prof:
         roof["valu_busy"] = prof["valu_busy"]
         roof["valu_lane_use"] = prof["lane_use"]
+    if peaks and peaks["copy_bytes_per_s"] > 0:
+        roof["frac_of_measured_copy"] = round(achieved * 1e9 / peaks["copy_bytes_per_s"], 4)
     tot = sysm.totals()
     status_after = {"max_speed": float(tot[8]), "rho_min": float(tot[9]), "rho_max": float(tot[10])}
     slots_first = nnz
@@ -393,6 +437,7 @@ def main():
         "cell_size_trials": None if tuned is None else
             {f"{t['cell_factor']}h": round(t["step_ms"], 4) for t in tuned["trials"] if "step_ms" in t},
         "roofline": roof,
+        "measured_peaks": peaks,
         "status_after": status_after,
         "windows": windows,
     }
