@@ -1,11 +1,14 @@
 // sdpdem_mlp.hip -- the viscosity surrogate: a 4-64-64-64-1 SiLU MLP with
 // bfloat16 parameters, float32 activations and float32 accumulation on the
-// matrix cores (v_mfma_f32_16x16x4_f32), trained with Adam.  Inference is
-// one wavefront per 16 rows; a training step (forward, MSE loss, backward,
-// Adam) is one workgroup, so every reduction has a fixed order and a step
-// is bit-for-bit repeatable.
+// matrix cores, trained with Adam.  Inference runs the hidden layers on the
+// bfloat16 matrix cores (v_mfma_f32_16x16x32_bf16, activations split into
+// three exact bfloat16 parts); a training step (forward, MSE loss,
+// backward, Adam) is one workgroup on the FP32 matrix cores
+// (v_mfma_f32_16x16x4_f32), so every reduction has a fixed order and a
+// step is bit-for-bit repeatable.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -41,7 +44,11 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float x) {
   return (uint16_t)(u >> 16);
 }
 
-__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + expf(-z)); }
+// logistic function from the hardware exp2 and reciprocal (about one ulp
+// each; the FP64 oracle agrees to the tolerance of the parity tests)
+__device__ __forceinline__ float sigm(float z) {
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.44269504088896341f * z));
+}
 __device__ __forceinline__ float silu(float z) { return z * sigm(z); }
 __device__ __forceinline__ float silu_grad(float z) {
   const float s = sigm(z);
@@ -60,52 +67,111 @@ __device__ __forceinline__ v4f mfma_tile(int K, FA fa, FB fb, v4f acc) {
 }
 
 // ---------------------------------------------------------------------------
-// inference: wavefront w of a block takes 16 rows; activations in LDS
+// inference on the bfloat16 matrix cores (v_mfma_f32_16x16x32_bf16).  The
+// parameters are bfloat16 values already; an FP32 activation is the exact
+// sum of three bfloat16 parts (its top 8 significant bits, the next 8, the
+// last 8), so three bf16 products accumulated in FP32 give the FP32
+// product, and the layer equals its FP32 evaluation up to the order of the
+// sums.  A block stages the hidden layers' weights, transposed, in LDS once
+// and its wavefronts then take groups of 16 rows in turn; each wavefront
+// keeps its 16 x 64 activation tiles in LDS.
 
-constexpr int LDA = HID + 1;  // padded row stride of the LDS tiles
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned short v8u16 __attribute__((ext_vector_type(8)));
 
-__global__ __launch_bounds__(256) void k_mlp_predict(const uint16_t* __restrict__ wq, Norm nrm,
-                                                     const float* __restrict__ x,
-                                                     float* __restrict__ y, int64_t n) {
-  __shared__ float sh[4][2][16 * LDA];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
-  const int64_t row0 = ((int64_t)blockIdx.x * 4 + w) * 16;
-  float* h0 = sh[w][0];
-  float* h1 = sh[w][1];
-  // layer 1: K = 4 features, one MFMA per 16 x 16 tile
-  {
-    const int64_t row = row0 + r;
-    const float a = row < n ? (x[row * 4 + q] - nrm.mean[q]) * nrm.inv_std[q] : 0.0f;
-    for (int jt = 0; jt < 4; ++jt) {
-      const float bias = bf16_to_f32(wq[OB1 + 16 * jt + r]);
-      v4f acc = {bias, bias, bias, bias};
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bf16_to_f32(wq[OW1 + q * HID + 16 * jt + r]),
-                                                 acc, 0, 0, 0);
-      for (int v = 0; v < 4; ++v) h0[(4 * q + v) * LDA + 16 * jt + r] = silu(acc[v]);
-    }
+constexpr int LDA = HID + 4;  // padded row stride of the activation tiles
+constexpr int PRED_WAVES = 4;
+
+// x = hi + mid + lo exactly, each part a bfloat16 (truncations of x and of
+// the remainders: every part holds at most 8 significant bits)
+__device__ __forceinline__ void split3(float x, unsigned short& h, unsigned short& m,
+                                       unsigned short& l) {
+  const uint32_t uh = __float_as_uint(x) & 0xFFFF0000u;
+  const float r1 = x - __uint_as_float(uh);
+  const uint32_t um = __float_as_uint(r1) & 0xFFFF0000u;
+  const float r2 = r1 - __uint_as_float(um);
+  h = (unsigned short)(uh >> 16);
+  m = (unsigned short)(um >> 16);
+  l = (unsigned short)(__float_as_uint(r2) >> 16);
+}
+
+__global__ __launch_bounds__(64 * PRED_WAVES) void k_mlp_predict(const uint16_t* __restrict__ wq,
+                                                                 Norm nrm,
+                                                                 const float* __restrict__ x,
+                                                                 float* __restrict__ y, int64_t n,
+                                                                 int64_t groups_per_wave) {
+  // W2^T and W3^T: wt[l][j * HID + k] = W_{l+2}[k][j] (bf16 bits)
+  __shared__ __attribute__((aligned(16))) unsigned short wt[2][HID * HID];
+  __shared__ float w1[4 * HID], bias[3][HID], w4[HID + 1];
+  __shared__ float act[PRED_WAVES][2][16 * LDA];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 2 * HID * HID; e += 64 * PRED_WAVES) {
+    const int l = e / (HID * HID), rem = e % (HID * HID), k = rem / HID, j = rem % HID;
+    wt[l][j * HID + k] = wq[OW[l + 1] + k * HID + j];
   }
+  for (int e = tid; e < 4 * HID; e += 64 * PRED_WAVES) w1[e] = bf16_to_f32(wq[OW1 + e]);
+  for (int e = tid; e < 3 * HID; e += 64 * PRED_WAVES)
+    bias[e / HID][e % HID] = bf16_to_f32(wq[OB[e / HID] + e % HID]);
+  for (int e = tid; e <= HID; e += 64 * PRED_WAVES) w4[e] = bf16_to_f32(wq[OW4 + e]);
   __syncthreads();
-  // layers 2 and 3: K = 64
-  for (int l = 1; l < 3; ++l) {
-    const float* hin = l == 1 ? h0 : h1;
-    float* hout = l == 1 ? h1 : h0;
-    for (int jt = 0; jt < 4; ++jt) {
-      const float bias = bf16_to_f32(wq[OB[l] + 16 * jt + r]);
-      v4f acc = {bias, bias, bias, bias};
-      acc = mfma_tile(
-          HID, [&](int i, int k) { return hin[i * LDA + k]; },
-          [&](int k, int j) { return bf16_to_f32(wq[OW[l] + k * HID + 16 * jt + j]); }, acc);
-      for (int v = 0; v < 4; ++v) hout[(4 * q + v) * LDA + 16 * jt + r] = silu(acc[v]);
+  const int w = tid >> 6, lane = tid & 63, r = lane & 15, q = lane >> 4;
+  float* h0 = act[w][0];
+  float* h1 = act[w][1];
+  const int64_t wave = (int64_t)blockIdx.x * PRED_WAVES + w;
+  const int64_t nwaves = (int64_t)gridDim.x * PRED_WAVES;
+  for (int64_t it = 0; it < groups_per_wave; ++it) {
+    const int64_t row0 = (wave + it * nwaves) * 16;
+    if (row0 >= n) break;  // a wavefront's own loop: no block barrier inside
+    // layer 1: K = 4 features, one FP32 MFMA per 16 x 16 tile
+    {
+      const int64_t row = row0 + r;
+      const float a = row < n ? (x[row * 4 + q] - nrm.mean[q]) * nrm.inv_std[q] : 0.0f;
+      for (int jt = 0; jt < 4; ++jt) {
+        const float b0 = bias[0][16 * jt + r];
+        v4f acc = {b0, b0, b0, b0};
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, w1[q * HID + 16 * jt + r], acc, 0, 0, 0);
+        for (int v = 0; v < 4; ++v) h0[(4 * q + v) * LDA + 16 * jt + r] = silu(acc[v]);
+      }
     }
-    __syncthreads();
+    // layers 2 and 3: K = 64 as two chunks of 32; lane (r, q) supplies
+    // A(r, 32c + 8q .. + 7) and B(32c + 8q .. + 7, r), holds C(4q + v, r)
+    for (int l = 0; l < 2; ++l) {
+      const float* hin = l == 0 ? h0 : h1;
+      float* hout = l == 0 ? h1 : h0;
+      v8u16 ah[2], am[2], al[2];
+      for (int c = 0; c < 2; ++c)
+        for (int e = 0; e < 8; ++e) {
+          unsigned short hh, mm, ll;
+          split3(hin[r * LDA + 32 * c + 8 * q + e], hh, mm, ll);
+          ah[c][e] = hh;
+          am[c][e] = mm;
+          al[c][e] = ll;
+        }
+      for (int jt = 0; jt < 4; ++jt) {
+        const float bj = bias[l + 1][16 * jt + r];
+        v4f acc = {bj, bj, bj, bj};
+        for (int c = 0; c < 2; ++c) {
+          const v8u16 bw =
+              *reinterpret_cast<const v8u16*>(&wt[l][(16 * jt + r) * HID + 32 * c + 8 * q]);
+          const v8bf b = __builtin_bit_cast(v8bf, bw);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, ah[c]), b, acc,
+                                                        0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, am[c]), b, acc,
+                                                        0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, al[c]), b, acc,
+                                                        0, 0, 0);
+        }
+        for (int v = 0; v < 4; ++v) hout[(4 * q + v) * LDA + 16 * jt + r] = silu(acc[v]);
+      }
+    }
+    // output layer: lanes (r, q) sum k in [16q, 16q + 16), then across q
+    float p = 0.0f;
+    for (int k = 16 * q; k < 16 * q + 16; ++k) p += h0[r * LDA + k] * w4[k];
+    p += __shfl_xor(p, 16, 64);
+    p += __shfl_xor(p, 32, 64);
+    const int64_t row = row0 + r;
+    if (q == 0 && row < n) y[row] = p + w4[HID];
   }
-  // output layer: lanes (r, q) sum k in [16q, 16q + 16), then across q
-  float p = 0.0f;
-  for (int k = 16 * q; k < 16 * q + 16; ++k) p += h0[r * LDA + k] * bf16_to_f32(wq[OW4 + k]);
-  p += __shfl_xor(p, 16, 64);
-  p += __shfl_xor(p, 32, 64);
-  const int64_t row = row0 + r;
-  if (q == 0 && row < n) y[row] = p + bf16_to_f32(wq[OB4]);
 }
 
 // ---------------------------------------------------------------------------
@@ -360,10 +426,12 @@ int sdpdem_mlp_create(const sdpdem_mlp_config* cfg, const float* init_params, vo
 int sdpdem_mlp_predict(sdpdem_mlp* m, const float* d_x, float* d_y, int64_t n, void* hip_stream) {
   if (!m || n < 0 || (n > 0 && (!d_x || !d_y))) return SDPDEM_E_INVALID_ARG;
   if (n == 0) return SDPDEM_OK;
-  const int64_t blocks = (n + 63) / 64;
-  if (blocks > 0x7fffffff) return SDPDEM_E_INVALID_ARG;
-  k_mlp_predict<<<(unsigned)blocks, 256, 0, (hipStream_t)hip_stream>>>(m->T.wq, m->nrm, d_x, d_y,
-                                                                      n);
+  // enough blocks to fill the chip; each wavefront walks its 16-row groups
+  const int64_t groups = (n + 15) / 16;
+  const int64_t blocks = std::min<int64_t>((groups + PRED_WAVES - 1) / PRED_WAVES, 2048);
+  const int64_t per_wave = (groups + blocks * PRED_WAVES - 1) / (blocks * PRED_WAVES);
+  k_mlp_predict<<<(unsigned)blocks, 64 * PRED_WAVES, 0, (hipStream_t)hip_stream>>>(
+      m->T.wq, m->nrm, d_x, d_y, n, per_wave);
   return hipGetLastError() == hipSuccess ? SDPDEM_OK : SDPDEM_E_HIP;
 }
 
