@@ -12,7 +12,12 @@ Viscosity: eta_eff = -<P_zx> / shear_rate over the second half of a run,
 <.> the mean of the per-step samples; its standard error from block means
 (blocks of `block` steps).  The network's target is log(eta_eff / eta).
 
-    python -m paper_2002_03120_amd.surrogate --cells 4096 --steps 2000
+    python -m paper_2002_03120_amd.surrogate --cells 4096 --steps 5000
+
+The measurement can be split over several runs: --measure-only --range A B
+writes the measured cells A..B-1 (features, eta_eff/eta, standard error) to
+--data; a later run given those files with --train-from trains, evaluates
+on fresh plain runs and writes the trained parameters (--save).
 """
 from __future__ import annotations
 
@@ -160,12 +165,80 @@ def train(x, y, epochs=300, batch=256, lr=3e-3, seed=0, log=None):
     return net, hist
 
 
+PARAMS_PATH = __import__("os").path.join(__import__("os").path.dirname(__file__),
+                                         "surrogate_params.json")
+
+
+def save_params(path, net, meta):
+    """The trained network: float32 master parameters (the bfloat16 values
+    the kernels use are their rounding) and how they were made."""
+    p = net.read()[0]
+    doc = dict(meta, n_params=int(p.size), norm=[float(v) for v in normalisation()],
+               box_lo=[float(v) for v in BOX_LO], box_hi=[float(v) for v in BOX_HI],
+               params=[float(v) for v in p])
+    with open(path, "w") as f:
+        json.dump(doc, f, separators=(",", ":"))
+
+
+def load_params(path=PARAMS_PATH):
+    with open(path) as f:
+        doc = json.load(f)
+    return np.asarray(doc["params"], np.float32), doc
+
+
+def load_network(path=PARAMS_PATH):
+    """The committed trained network as a Surrogate (None if absent)."""
+    import os
+    if not os.path.exists(path):
+        return None, None
+    p, doc = load_params(path)
+    net = MLP.Mlp(p, np.asarray(doc["norm"], np.float32))
+    return Surrogate(net, doc["box_lo"], doc["box_hi"]), doc
+
+
+def evaluate(sur, fresh, steps, tuning=None, log=None):
+    """Relative error of the network against fresh plain runs of `steps`
+    steps: all runs, and the runs whose own relative standard error is below
+    2 % (where a 5 % error is resolvable)."""
+    eta_f, se_f = measure(fresh, steps, tuning=tuning, log=log)
+    pred = sur.predict(features([c[2] for c in fresh]))
+    rel = np.abs(pred / eta_f - 1.0)
+    rel_se = se_f / np.abs(eta_f)
+    quiet = rel_se < 0.02
+    return {
+        "eval_cells": len(fresh), "eval_steps": steps,
+        "median_rel_error": float(np.median(rel)),
+        "mean_rel_error": float(rel.mean()),
+        "median_plain_rel_se": float(np.median(rel_se)),
+        "cells_with_plain_se_below_2pct": int(quiet.sum()),
+        "mean_rel_error_where_plain_se_below_2pct": float(rel[quiet].mean()) if quiet.any() else None,
+        "median_rel_error_where_plain_se_below_2pct":
+            float(np.median(rel[quiet])) if quiet.any() else None,
+        "frac_within_5pct_where_plain_se_below_2pct":
+            float((rel[quiet] <= 0.05).mean()) if quiet.any() else None,
+    }, rel, rel_se
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--cells", type=int, default=4096, help="training cells")
     ap.add_argument("--eval-cells", type=int, default=64, help="fresh plain runs for the error")
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--side", type=int, nargs=2, default=[12, 16])
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--eval-steps", type=int, default=5000,
+                    help="steps of the fresh plain runs the error is judged against (the "
+                         "training protocol's: the viscosity still relaxes after 5000 steps "
+                         "from the initial lattice, so longer runs measure another quantity)")
+    ap.add_argument("--eval-shear", type=float, nargs=2, default=[1e-2, 1e-1],
+                    help="shear-rate range of a second set of fresh runs (their own standard "
+                         "error resolves 5 %% in most)")
+    ap.add_argument("--side", type=int, nargs=2, default=[16, 40])
+    ap.add_argument("--measure-only", action="store_true")
+    ap.add_argument("--range", type=int, nargs=2, default=None,
+                    help="with --measure-only: the training cells A..B-1 of the sampler")
+    ap.add_argument("--data", default=None, help="npz file written by --measure-only")
+    ap.add_argument("--train-from", nargs="*", default=None,
+                    help="npz files of measured cells (no measuring)")
+    ap.add_argument("--save", default=None, help="write the trained parameters (json)")
     ap.add_argument("--epochs", type=int, default=400)
     ap.add_argument("--queries", type=int, default=1 << 20)
     ap.add_argument("--seed", type=int, default=0)
@@ -180,26 +253,48 @@ def main(argv=None):
     torch.cuda.set_device(0)
     kw = dict(side=tuple(args.side), steps=args.steps)
     t0 = time.perf_counter()
-    _, cells = W.viscometer_batch(args.cells, seed=args.seed, **kw)
-    tuning = None if args.no_autotune else AT.tune(cells, args.steps, log=log)
-    eta, se = measure(cells, args.steps, tuning=tuning, log=log)
-    torch.cuda.synchronize()
-    t_meas = time.perf_counter() - t0
-    x = features([c[2] for c in cells])
+    tuning = None
+    if args.train_from:
+        parts = [np.load(f) for f in args.train_from]
+        x = np.concatenate([d["x"] for d in parts]).astype(np.float32)
+        eta = np.concatenate([d["eta"] for d in parts])
+        se = np.concatenate([d["se"] for d in parts])
+        t_meas = float(sum(float(d["seconds"]) for d in parts))
+        if not args.no_autotune:
+            _, some = W.viscometer_batch(min(args.cells, 512), seed=args.seed, **kw)
+            tuning = AT.tune(some, args.steps, log=log)
+    else:
+        _, cells = W.viscometer_batch(args.cells, seed=args.seed, **kw)
+        if args.range:
+            cells = cells[args.range[0]:args.range[1]]
+        tuning = None if args.no_autotune else AT.tune(cells, args.steps, log=log)
+        eta, se = measure(cells, args.steps, tuning=tuning, log=log)
+        torch.cuda.synchronize()
+        t_meas = time.perf_counter() - t0
+        x = features([c[2] for c in cells])
+        if args.measure_only:
+            np.savez(args.data, x=x, eta=eta, se=se, seconds=t_meas)
+            print(json.dumps({"measured": len(cells), "seconds": round(t_meas, 2),
+                              "launch_shape": None if tuning is None else
+                              {k: tuning[k] for k in ("cell_factor", "graph_steps", "tile")}}),
+                  flush=True)
+            return None
     ok = (eta > 0) & (se < args.max_rel_se * np.abs(eta))
     y = np.log(np.where(ok, eta, 1.0)).astype(np.float32)
     t0 = time.perf_counter()
     net, hist = train(x[ok], y[ok], epochs=args.epochs, seed=args.seed, log=log)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    # fresh plain runs, never seen in training
-    _, fresh = W.viscometer_batch(args.eval_cells, seed=args.seed + 999, **kw)
-    eta_f, se_f = measure(fresh, args.steps, tuning=tuning, log=log)
+    # fresh plain runs, never seen in training, run longer than the training
+    # cells so that most resolve a 5 % error
+    _, fresh = W.viscometer_batch(args.eval_cells, seed=args.seed + 999,
+                                  **dict(kw, steps=args.eval_steps))
     sur = Surrogate(net, BOX_LO, BOX_HI)
-    pred = sur.predict(features([c[2] for c in fresh]))
-    rel = np.abs(pred / eta_f - 1.0)
-    rel_se = se_f / np.abs(eta_f)
-    quiet = rel_se < 0.02
+    ev, rel, rel_se = evaluate(sur, fresh, args.eval_steps, tuning=tuning, log=log)
+    _, fresh2 = W.viscometer_batch(args.eval_cells, seed=args.seed + 1999,
+                                   **dict(kw, steps=args.eval_steps, shear=tuple(args.eval_shear)))
+    ev2 = evaluate(sur, fresh2, args.eval_steps, tuning=tuning, log=log)[0]
+    ev["eval_high_shear"] = dict(ev2, shear=list(args.eval_shear))
     q = W.mlp_queries(args.queries, seed=args.seed + 7)
     qd = torch.from_numpy(q).cuda()
     net.predict(qd)
@@ -209,24 +304,24 @@ def main(argv=None):
         net.predict(qd)
     torch.cuda.synchronize()
     t_q = (time.perf_counter() - t0) / 10
-    res = {
-        "train_cells": args.cells, "steps_per_run": args.steps, "side": args.side,
+    res = dict({
+        "train_cells": int(x.shape[0]), "steps_per_run": args.steps, "side": args.side,
         "trained_on": int(ok.sum()), "max_rel_se": args.max_rel_se,
         "measure_s": round(t_meas, 2), "train_s": round(t_train, 2),
         "launch_shape": None if tuning is None else
             {k: tuning[k] for k in ("cell_factor", "graph_steps", "tile", "tune_s")},
         "final_train_loss": hist[-1][1],
-        "eval_cells": args.eval_cells,
-        "median_rel_error": float(np.median(rel)),
-        "mean_rel_error": float(rel.mean()),
-        "median_plain_rel_se": float(np.median(rel_se)),
-        "cells_with_plain_se_below_2pct": int(quiet.sum()),
-        "mean_rel_error_where_plain_se_below_2pct": float(rel[quiet].mean()) if quiet.any() else None,
-        "frac_within_5pct_where_plain_se_below_2pct":
-            float((rel[quiet] <= 0.05).mean()) if quiet.any() else None,
+    }, **ev)
+    res.update({
         "queries": args.queries, "query_s": t_q, "queries_per_s": args.queries / t_q,
-        "plain_runs_per_s": args.cells / t_meas,
-    }
+        "plain_runs_per_s": x.shape[0] / t_meas,
+    })
+    if args.save:
+        save_params(args.save, net, {
+            "train_cells": int(x.shape[0]), "trained_on": int(ok.sum()),
+            "steps_per_run": args.steps, "side": list(args.side), "seed": args.seed,
+            "epochs": args.epochs, "max_rel_se": args.max_rel_se,
+            "final_train_loss": float(hist[-1][1])})
     print(json.dumps(res), flush=True)
     return res
 
