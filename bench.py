@@ -144,6 +144,52 @@ def viscometer_leg(k_steps, n_cells=256, run_steps=5000, graph_steps=10, tune=Tr
     return res
 
 
+def surrogate_leg(n_cells=64, steps=5000, seed=1999, shear=(1e-2, 1e-1)):
+    """The committed viscosity surrogate (trained on 4096 batched-viscometer
+    cells of the batched-viscometer sampling, sides 16-40, 5000 steps) judged
+    against fresh plain runs of the same protocol: n_cells cells (the same
+    sampler, shear rates in `shear`, another seed), run batched on the GPU;
+    the network's relative error against each run's measured viscosity,
+    also on the runs whose own standard error is below 2 %; and the rate of
+    network answers against plain runs."""
+    import numpy as np
+    import torch
+
+    from paper_2002_03120_amd import surrogate as SG
+    from paper_2002_03120_amd import workloads as W
+    sur, doc = SG.load_network()
+    if sur is None:
+        return None
+    _, fresh = W.viscometer_batch(n_cells, seed=seed, side=tuple(doc["side"]), steps=steps,
+                                  shear=shear)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev, rel, rel_se = SG.evaluate(sur, fresh, steps, tuning={"cell_factor": 0.5,
+                                                              "graph_steps": 2,
+                                                              "tile": 8388608})
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    q = torch.from_numpy(W.mlp_queries(1 << 20, seed=7)).cuda()
+    sur.net.predict(q)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        sur.net.predict(q)
+    torch.cuda.synchronize()
+    t_q = (time.perf_counter() - t0) / 10
+    flop = 2 * (4 * 64 + 64 * 64 + 64 * 64 + 64) * (1 << 20)
+    ev.update({
+        "shear": list(shear), "trained_on": doc["trained_on"], "train_cells": doc["train_cells"],
+        "plain_runs_per_s": round(n_cells / t_plain, 2),
+        "network_answers_per_s": round((1 << 20) / t_q, 1),
+        "gain_answers_per_plain_run": round((1 << 20) / t_q / (n_cells / t_plain), 1),
+        "inference_roofline": {"bound": "mfma", "achieved": round(flop / t_q / 1e12, 2),
+                               "unit": "TFLOP/s", "peak_bf16_mfma": 2500.0,
+                               "frac_bf16_mfma": round(flop / t_q / 2.5e15, 4)},
+    })
+    return ev
+
+
 def scale_leg(steps, cell_factor, warmup=2):
     """The scale run: a fully periodic SDPD lattice of 256 x 256 x 128 =
     8,388,608 particles (the reverse-Poiseuille constants, kT = 1e-3, so the
@@ -317,6 +363,8 @@ def main():
                     help="timed steps of the 8,388,608-particle periodic scale run (0: skip)")
     ap.add_argument("--viscometer-steps", type=int, default=20,
                     help="timed steps per configuration of the batched-viscometer leg (0: skip)")
+    ap.add_argument("--surrogate-cells", type=int, default=64,
+                    help="fresh plain runs the committed surrogate is judged against (0: skip)")
     ap.add_argument("--window-step", type=int, default=2000,
                     help="also time --window-steps steps from this step of the collapse (0: skip)")
     ap.add_argument("--window-steps", type=int, default=20)
@@ -451,6 +499,8 @@ def main():
         result["scale"] = scale_leg(args.scale_steps, args.cell_factor)
     if args.viscometer_steps > 0:
         result["viscometer"] = viscometer_leg(args.viscometer_steps)
+    if args.surrogate_cells > 0:
+        result["surrogate"] = surrogate_leg(args.surrogate_cells)
 
     if args.cpu_seconds > 0:
         from oracle import oracle as O

@@ -65,19 +65,35 @@ def test_outside_the_box_the_plain_simulation_answers(SG, trained):
     assert out[0] == sur.predict(q[:1])[0]
 
 
-def test_network_answers_far_faster_than_the_simulation(SG, trained):
+def test_committed_network_matches_fresh_plain_runs_far_faster(SG):
+    """The committed network (trained on 4096 cells of the batched-viscometer
+    sampler, sides 16-40, 5000 steps) against 12 fresh plain runs of the
+    same protocol at shear rates 1e-2..1e-1: its error is within 5 % where
+    the run itself resolves 5 % (standard error below 2 %), no larger than
+    about twice the plain runs' own statistical error overall -- the gain
+    is at equal error -- and an answer costs a million times less."""
     import torch
-    net = trained[0]
+    sur, doc = SG.load_network()
+    assert doc["n_params"] == 8705 and doc["side"] == [16, 40] and doc["steps_per_run"] == 5000
+    _, fresh = W.viscometer_batch(12, seed=4242, side=(16, 40), steps=5000, shear=(1e-2, 1e-1))
+    print(f"[case] 12 fresh plain runs, {sum(c[2]['n'] for c in fresh)} particles", flush=True)
+    t0 = time.perf_counter()
+    ev, rel, rel_se = SG.evaluate(sur, fresh, 5000,
+                                  tuning={"cell_factor": 0.5, "graph_steps": 2, "tile": 8388608})
+    t_plain = (time.perf_counter() - t0) / len(fresh)
     q = torch.from_numpy(W.mlp_queries(1 << 20, seed=1)).cuda()
-    net.predict(q)
+    sur.net.predict(q)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    net.predict(q)
+    sur.net.predict(q)
     torch.cuda.synchronize()
-    t_net = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    SG.measure([W.shear_cell(12, 0.2, 3.0, seed=5)], 200)
-    t_sim = time.perf_counter() - t0
-    print(f"[case] 2^20 network answers in {t_net * 1e3:.3f} ms; one 200-step plain run "
-          f"{t_sim * 1e3:.1f} ms", flush=True)
-    assert t_net < t_sim
+    t_net = (time.perf_counter() - t0) / (1 << 20)
+    print(f"[case] median error {ev['median_rel_error']:.3f}, plain se {ev['median_plain_rel_se']:.3f}"
+          f"; {ev['cells_with_plain_se_below_2pct']} resolved, mean error there "
+          f"{ev['mean_rel_error_where_plain_se_below_2pct']}; plain run {t_plain:.2f} s, "
+          f"network answer {t_net * 1e9:.2f} ns", flush=True)
+    quiet = rel_se < 0.02
+    assert quiet.sum() >= 4
+    assert rel[quiet].mean() <= 0.05 and (rel[quiet] <= 0.05).mean() >= 0.75
+    assert ev["median_rel_error"] <= 2.0 * ev["median_plain_rel_se"] + 0.01
+    assert t_plain / t_net > 1e6
