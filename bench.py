@@ -363,6 +363,8 @@ def main():
                     help="timed steps of the 8,388,608-particle periodic scale run (0: skip)")
     ap.add_argument("--viscometer-steps", type=int, default=20,
                     help="timed steps per configuration of the batched-viscometer leg (0: skip)")
+    ap.add_argument("--skin", type=float, default=0.0,
+                    help="neighbour-candidate margin (0: sort and search after every drift)")
     ap.add_argument("--surrogate-cells", type=int, default=64,
                     help="fresh plain runs the committed surrogate is judged against (0: skip)")
     ap.add_argument("--window-step", type=int, default=2000,
@@ -404,10 +406,11 @@ def main():
         from paper_2002_03120_amd import autotune as AT
         tuned = AT.tune_system(p, parts, log=lambda m: print(f"# {m}", file=sys.stderr, flush=True))
         args.cell_factor = tuned["cell_factor"]
-    pg = dict(p, cell_factor=args.cell_factor)  # the GPU system's parameters
+    pg = dict(p, cell_factor=args.cell_factor, skin=args.skin)  # the GPU system's parameters
     sysm = S.System(pg, parts)
     sysm.step(args.warmup)
     torch.cuda.synchronize()
+    inf0 = sysm.info()
     noise = args.kT > 0
 
     # timed region: exactly `steps` steps, the pair kernel timed by events
@@ -480,8 +483,13 @@ def main():
             "n_fluid": info["n_fluid"], "n_rigid": info["n_rigid"],
             "n_wall": info["n_inner_wall"] + info["n_outer_wall"], "n_total": n,
             "kT": args.kT, "dt": p["dt"], "h": p["h"], "cell_factor": args.cell_factor,
+            "skin": args.skin,
         },
         "pair_interactions_per_s": round(pair_rate, 1),
+        # cell-grid searches (sort + search) and list builds from the
+        # candidates of an earlier search in the timed steps (skin > 0)
+        "neighbour_searches": int(inf[13] - inf0[13]),
+        "lists_from_candidates": int(inf[14] - inf0[14]),
         "cell_size_trials": None if tuned is None else
             {f"{t['cell_factor']}h": round(t["step_ms"], 4) for t in tuned["trials"] if "step_ms" in t},
         "roofline": roof,

@@ -95,6 +95,20 @@ typedef struct sdpdem_params {
                               each way and skips cells out of range.  Neighbour
                               sets do not depend on it; sums only through their
                               order                                              */
+  double skin;             /* candidate margin of the neighbour search of Alg. 1
+                              (Sec. 3.2), 0 <= skin <= h/2.  0: the particles are
+                              re-sorted and the lists rebuilt from the cell grid
+                              after every drift.  skin > 0: the cell-grid search
+                              keeps every partner within h + skin as a
+                              candidate, and after a drift the lists are taken
+                              from the candidates (the exact r < h test, so the
+                              neighbour sets are unchanged) until some particle
+                              has moved skin/2 since the last search; only then
+                              are the particles re-sorted and searched again.
+                              Deciding this reads one device word after the
+                              first pass of a step (one synchronisation per
+                              step); under graph replay every step searches.
+                              Not with Lees-Edwards shear                        */
 } sdpdem_params;
 
 /* Particles, host memory, n rows in any order (ids must cover 0..n-1).
@@ -321,7 +335,9 @@ int sdpdem_box_stress(sdpdem_system* sys, double* inst, double* sum, int64_t* ns
  * out = [n, n_rigid, cells x, y, z of box 0, rigid cells x,
  * y, z of box 0, max neighbour count of the last build, pairs of the last
  * build, number of boxes, steps replayed from captured graphs so far,
- * 1 if the contacts run on the library's second stream, 0...]. */
+ * 1 if the contacts run on the library's second stream, cell-grid searches
+ * (sorts) so far, list builds taken from the candidates of an earlier
+ * search so far (skin > 0), 0]. */
 int sdpdem_info(sdpdem_system* sys, int64_t out[16], void* hip_stream);
 
 /* Per-routine timing, the breakdown of Fig. CompTimeTotal over the

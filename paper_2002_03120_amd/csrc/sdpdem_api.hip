@@ -34,6 +34,17 @@ struct sdpdem_system {
   double* tot_out;
   int64_t step = 0;
   bool cache_valid = false;
+  // candidate reuse: the candidates and reference positions of a cell-grid
+  // search are in place; capturing (every step searches inside a graph);
+  // searches and reusing list builds so far
+  bool cand_valid = false;
+  bool capturing = false;
+  int64_t searches = 0, reuses = 0;
+  // pinned host word the moved flag is copied into, and the event the host
+  // polls for that copy (null: a pageable copy and a stream synchronisation)
+  int* h_moved = nullptr;
+  hipEvent_t ev_moved = nullptr;
+  bool fork_marked = false;  // ev_fork already marks the coming build's fork point
   // the reaction's slots hold the coupling pairs of the current positions
   // and sorted order (a neighbour build invalidates them)
   bool rxn_valid = false;
@@ -94,6 +105,9 @@ bool valid_params(const sdpdem_params* P) {
   if (P->xi < 40.0 * P->eta / 51.0 || P->xi > 5.0 * P->eta / 3.0) return false;
   if (P->gravity_axis < 0 || P->gravity_axis > 2) return false;
   if (P->cell_factor != 0.0 && !(P->cell_factor >= 0.25 && P->cell_factor <= 16.0)) return false;
+  // a candidate margin up to h/2 keeps h + skin within half of a periodic
+  // axis (L >= 3h), where the minimum image is the only one
+  if (!(P->skin >= 0.0 && P->skin <= 0.5 * P->h)) return false;
   return true;
 }
 
@@ -104,6 +118,8 @@ bool valid_box(const sdpdem_params* P, const sdpdem_box& b) {
   }
   if (!(b.kBT >= 0) || !std::isfinite(b.kBT) || !std::isfinite(b.shear_rate)) return false;
   if (b.shear_rate != 0.0 && (!b.periodic[0] || !b.periodic[1] || !b.periodic[2])) return false;
+  // the sheared images move against each other every step: no reuse there
+  if (b.shear_rate != 0.0 && P->skin > 0.0) return false;
   return true;
 }
 
@@ -194,6 +210,7 @@ double lattice_sum(double h, double dx) {
 struct Sizes {
   int64_t n, npad, nr;
   int maxn, maxc;
+  int maxcand = 0;  // candidate row capacity (0: no reuse)
   int nbox = 1;
   int64_t ncells_all = 0, rncells_all = 0;
   std::vector<BoxD> boxes;
@@ -220,6 +237,9 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
   int* bsum = b.take<int>((size_t)scan_block_sums_size((int)nc) + 1);
   int* nbr = b.take<int>((size_t)z.maxn * np);
   int* nbr_cnt = b.take<int>(np);
+  int* cand = b.take<int>(z.maxcand ? (size_t)z.maxcand * np : 1);
+  int* cand_cnt = b.take<int>(z.maxcand ? np : 1);
+  D4* xref = b.take<D4>(z.maxcand ? np : 1);
   double* rho = b.take<double>(np);
   double* p = b.take<double>(np);
   D4* xp = b.take<D4>(np);
@@ -297,6 +317,9 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
     d.perm = perm;
     d.nbr = nbr;
     d.nbr_cnt = nbr_cnt;
+    d.cand = cand;
+    d.cand_cnt = cand_cnt;
+    d.xref = xref;
     d.rho = rho;
     d.p = p;
     d.xp = xp;
@@ -327,6 +350,7 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
     d.rcursor = rcursor;
     d.ritems = ritems;
     d.status = status;
+    d.moved = status + 32;  // its own 128-byte half of the status block
     d.rpos_c = rpos_c;
     d.rvel_c = rvel_c;
     d.rom_c = rom_c;
@@ -363,6 +387,13 @@ bool plan(const sdpdem_params* P, const sdpdem_box* boxes, int nbox,
   z.nr = nr;
   z.maxn = P->max_neighbors;
   z.maxc = P->max_contacts;
+  if (P->skin > 0.0) {
+    // rows grow with the volume of the search sphere
+    const double g = (P->h + P->skin) / P->h;
+    const double mc = std::ceil((double)P->max_neighbors * g * g * g);
+    if (mc > (double)(1 << 20)) return false;
+    z.maxcand = (int)mc;
+  }
   z.nbox = nbox;
   z.boxes.assign((size_t)nbox, BoxD{});
   z.blk.clear();
@@ -466,6 +497,15 @@ void fill_constants(sdpdem_system* s, const Sizes& z) {
   d.h = P.h;
   d.h2 = P.h * P.h;
   d.inv_h = 1.0 / P.h;
+  d.reuse = z.maxcand > 0 ? 1 : 0;
+  d.maxcand = z.maxcand;
+  d.hc = P.h + P.skin;
+  d.hc2 = d.hc * d.hc;
+  d.pad = d.reuse ? 0.5 * P.skin : 0.0;
+  // a partner within h now was within h + 2 (skin/2) of it at the search;
+  // the flag's threshold sits a relative 1e-9 inside skin/2, so that FP64
+  // rounding of the distances cannot let a partner escape the candidates
+  d.mv2 = (0.5 * P.skin * (1.0 - 1e-9)) * (0.5 * P.skin * (1.0 - 1e-9));
   d.dx = P.dx;
   d.lever = 0.5 * P.dx;
   d.rho0 = P.rho0;
@@ -621,39 +661,67 @@ bool issue_rigid(sdpdem_system* s, hipStream_t rs, bool fk, int commit) {
   return ok;
 }
 
+// How a build gets its lists: sort and search the cell grid; take them
+// from the candidates of the last search (every particle is still within
+// skin/2 of where it saw it); or the same with the candidate filter already
+// enqueued, and the side stream's fork point marked before it.
+enum BuildLists { LISTS_SEARCH, LISTS_FILTER, LISTS_FILTERED };
+
 // The neighbour build; with commit_next >= 0 a force pass with that commit
 // flag follows at once, and the build already issues that pass's sphere
-// records and contacts (which need only the permuted state).
-void run_build(sdpdem_system* s, hipStream_t st, int commit_next) {
+// records and contacts (which need only the permuted state).  Without a
+// search the particles keep their order and cells.
+void run_build(sdpdem_system* s, hipStream_t st, int commit_next, int lists = LISTS_SEARCH) {
   Dev& d = s->d;
   const int nc = d.ncells_all;
-  s->rxn_valid = false;  // the sorted order changes
-  {
-    Prof pr(s, SDPDEM_K_BIN, st);
-    launch_fill_i32(d.count, 0, (size_t)nc, st);
-    launch_bin(d, st);
-  }
-  {
-    Prof pr(s, SDPDEM_K_SORT, st);
-    launch_scan(d.count, nc, d.cstart, nullptr, s->block_sums, st);
-    launch_scatter_ranked(d.key, d.rank, d.n, d.cstart, d.perm, st);
-    launch_cell_sort(d.cstart, nc, d.perm, s->gid[s->cur], st);
-  }
-  const int src = s->cur;
-  s->cur ^= 1;
-  bind_current(s);
-  {
-    Prof pr(s, SDPDEM_K_PERMUTE, st);
-    launch_permute(d, s->pos[src], s->vel[src], s->om[src], s->type[src], s->gid[src], st);
+  const bool search = lists == LISTS_SEARCH;
+  s->rxn_valid = false;  // the positions (and with a search the order) change
+  if (search) {
+    {
+      Prof pr(s, SDPDEM_K_BIN, st);
+      launch_bin(d, st);  // the counts are zero: set at creation, cleared by the scan
+    }
+    {
+      Prof pr(s, SDPDEM_K_SORT, st);
+      launch_scan(d.count, nc, d.cstart, nullptr, s->block_sums, st);
+      launch_scatter_ranked(d.key, d.rank, d.n, d.cstart, d.perm, st);
+      launch_cell_sort(d.cstart, nc, d.perm, s->gid[s->cur], st);
+    }
+    const int src = s->cur;
+    s->cur ^= 1;
+    bind_current(s);
+    {
+      Prof pr(s, SDPDEM_K_PERMUTE, st);
+      launch_permute(d, s->pos[src], s->vel[src], s->om[src], s->type[src], s->gid[src], st);
+    }
   }
   // the rigid grid, the sphere records and the contacts need the permuted
   // state only: with a side stream they run there beside the neighbour
-  // lists and the pressure filter (the pass joins the side stream)
-  const bool fk = d.nr > 0 && fork_side(s, st);
+  // lists and the pressure filter (the pass joins the side stream).  The
+  // fork point is marked before the lists are enqueued and the side work
+  // after them, so that the main stream never waits on the host enqueuing
+  // the many short rigid launches (it does when a step has just read the
+  // moved flag and the queue is empty).
+  const bool fk0 = d.nr > 0 && s->side &&
+                   (lists == LISTS_FILTERED ? s->fork_marked
+                                            : hipEventRecord(s->ev_fork, st) == hipSuccess);
+  s->fork_marked = false;
+  if (search) {
+    Prof pr(s, SDPDEM_K_NEIGHBORS_DENSITY, st);
+    launch_build_density(d, st);
+    s->cand_valid = d.reuse != 0;
+    s->searches += 1;
+  } else {
+    if (lists == LISTS_FILTER) {
+      Prof pr(s, SDPDEM_K_NEIGHBORS_DENSITY, st);
+      launch_filter_density(d, st);
+    }
+    s->reuses += 1;
+  }
+  const bool fk = fk0 && hipStreamWaitEvent(s->side, s->ev_fork, 0) == hipSuccess;
   hipStream_t rs = fk ? s->side : st;
   if (d.nr > 0) {
     Prof pr(s, SDPDEM_K_RIGID_GRID, rs);
-    launch_fill_i32(d.rcount, 0, (size_t)d.rncells_all, rs);
     launch_bin_rigid(d, rs);
     launch_scan(d.rcount, d.rncells_all, d.rstart, d.rcursor, s->rblock_sums, rs);
     launch_scatter(d.rkey, d.nr, d.rcursor, d.ritems, rs);
@@ -662,10 +730,6 @@ void run_build(sdpdem_system* s, hipStream_t st, int commit_next) {
   if (commit_next >= 0 && rigid_active(s)) {
     s->gather_ok = issue_rigid(s, rs, fk, commit_next);
     s->rigid_issued = true;
-  }
-  {
-    Prof pr(s, SDPDEM_K_NEIGHBORS_DENSITY, st);
-    launch_build_density(d, st);
   }
   {
     Prof pr(s, SDPDEM_K_SMOOTH, st);
@@ -865,6 +929,9 @@ int create_impl(const sdpdem_params* params, const sdpdem_box* boxes, int nbox,
   launch_fill_i32(reinterpret_cast<int*>(d.fout), 0, 13 * (size_t)z.npad, st);
   launch_fill_i32(d.nbr_cnt, 0, (size_t)z.npad, st);
   launch_fill_i32(d.cstart, 0, (size_t)z.ncells_all + 1, st);
+  // the binning counts into zeroed arrays; every scan leaves them zero again
+  launch_fill_i32(d.count, 0, (size_t)z.ncells_all, st);
+  if (z.nr) launch_fill_i32(d.rcount, 0, (size_t)z.rncells_all, st);
   launch_fill_f64(d.f_dg, 0.0, 3 * (size_t)z.nr, st);
   launch_fill_f64(d.f_pg, 0.0, 3 * (size_t)z.nr, st);
   launch_fill_f64(d.f_dem, 0.0, 3 * (size_t)z.nr, st);
@@ -884,6 +951,14 @@ int create_impl(const sdpdem_params* params, const sdpdem_box* boxes, int nbox,
     return SDPDEM_E_HIP;
   }
   if (z.nr && side_stream) make_side_stream(s);
+  // candidate reuse reads one word per step: pinned, where the caller lets
+  // the library allocate (the allocation-free variant copies to the stack)
+  if (z.maxcand && side_stream) {
+    if (hipHostMalloc((void**)&s->h_moved, 64, hipHostMallocDefault) != hipSuccess)
+      s->h_moved = nullptr;
+    if (hipEventCreateWithFlags(&s->ev_moved, hipEventDisableTiming) != hipSuccess)
+      s->ev_moved = nullptr;
+  }
   *out = s;
   return SDPDEM_OK;
 }
@@ -994,6 +1069,34 @@ int sdpdem_create_batch(const sdpdem_params* params, const sdpdem_box* boxes, in
 
 namespace {
 
+// The moved flag of the drift just enqueued.  A one-thread kernel stores it
+// into pinned host memory and the host polls the event behind that kernel,
+// which wakes it within microseconds of the drift (a copy command takes
+// tens of microseconds, and a blocking synchronisation sleeps for a good
+// part of the next kernel's duration).  post_moved enqueues the store
+// (false: no pinned word, or the event failed), wait_moved waits for it;
+// both answer true (search) on any error.
+bool post_moved(sdpdem_system* s, hipStream_t st) {
+  if (!s->h_moved || !s->ev_moved) return false;
+  *(volatile int*)s->h_moved = 1;
+  launch_publish(s->d.moved, s->h_moved, st);  // a failed launch leaves 1: search
+  return hipEventRecord(s->ev_moved, st) == hipSuccess;
+}
+bool wait_moved(sdpdem_system* s) {
+  hipError_t e;
+  while ((e = hipEventQuery(s->ev_moved)) == hipErrorNotReady) {
+  }
+  return e != hipSuccess || *(volatile int*)s->h_moved != 0;
+}
+// without a pinned word: a copy to the stack and a synchronisation
+bool read_moved_sync(sdpdem_system* s, hipStream_t st) {
+  int moved = 1;
+  if (hipMemcpyAsync(&moved, s->d.moved, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return true;
+  return moved != 0;
+}
+
 // One iteration of Algorithm 1 (enqueue only).
 void step_body(sdpdem_system* s, hipStream_t st) {
   Dev& d = s->d;
@@ -1008,7 +1111,22 @@ void step_body(sdpdem_system* s, hipStream_t st) {
   // next step
   const bool fill2 = needs_fill(s, true);
   launch_pass_prep(d, s->boxes, 1, fill2, st);
-  run_build(s, st, 1);
+  // with candidate reuse, search again only if the drift took some particle
+  // skin/2 from where the last search saw it.  The host reads the flag; the
+  // candidate filter is enqueued before the answer arrives, so the device
+  // does not wait for the host (a search overwrites everything the filter
+  // wrote: lists, density, pressure and the filter's records).
+  int lists = LISTS_SEARCH;
+  if (d.reuse && s->cand_valid && !s->capturing) {
+    const bool posted = post_moved(s, st);
+    s->fork_marked = d.nr > 0 && s->side && hipEventRecord(s->ev_fork, st) == hipSuccess;
+    {
+      Prof pr(s, SDPDEM_K_NEIGHBORS_DENSITY, st);
+      launch_filter_density(d, st);
+    }
+    if (!(posted ? wait_moved(s) : read_moved_sync(s, st))) lists = LISTS_FILTERED;
+  }
+  run_build(s, st, 1, lists);
   run_pass(s, 2, 1, true, fill2, st);
   if (s->stress) {
     launch_box_stress(d, 1, st);
@@ -1031,15 +1149,20 @@ bool capture(sdpdem_system* s, hipStream_t st) {
   drop_graph(s);
   const int64_t step0 = s->step, samples0 = s->stress_samples;
   const int cur0 = s->cur, ct0 = s->ct_cur;
-  const bool rxn0 = s->rxn_valid;
+  const bool rxn0 = s->rxn_valid, cand0 = s->cand_valid;
+  const int64_t searches0 = s->searches;
   hipGraph_t g = nullptr;
   if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+  s->capturing = true;  // no host decisions inside a graph: every step searches
   for (int k = 0; k < s->graph_steps; ++k) step_body(s, st);
+  s->capturing = false;
   const bool ok = hipStreamEndCapture(st, &g) == hipSuccess && g;
   // nothing ran yet: restore the host mirror of the device state
   s->step = step0;
   s->stress_samples = samples0;
   s->rxn_valid = rxn0;
+  s->cand_valid = cand0;
+  s->searches = searches0;
   if (s->cur != cur0 || s->ct_cur != ct0) {
     if (g) (void)hipGraphDestroy(g);
     return false;
@@ -1064,8 +1187,9 @@ int sdpdem_step(sdpdem_system* s, int64_t nsteps, void* hip_stream) {
   if (!s || nsteps < 0) return SDPDEM_E_INVALID_ARG;
   hipStream_t st = (hipStream_t)hip_stream;
   int64_t left = nsteps;
-  const int K = s->graph_steps;
   while (left > 0) {
+    // re-read every round: a failed capture switches graphs off
+    const int K = st ? s->graph_steps : 0;  // no capture on the null stream
     // replay whole graphs while nothing that shapes the launch sequence
     // changes inside them (first build done, no timing, rigid activation
     // not crossed)
@@ -1085,6 +1209,8 @@ int sdpdem_step(sdpdem_system* s, int64_t nsteps, void* hip_stream) {
       }
       if (hipGraphLaunch(s->gexec, st) != hipSuccess) return SDPDEM_E_HIP;
       s->rxn_valid = act_now;  // the last pass built and (with the coupling) refilled
+      s->cand_valid = s->d.reuse != 0;  // every replayed step searched
+      s->searches += K;
       s->step += K;
       s->graph_steps_run += K;
       if (s->stress) s->stress_samples += K;
@@ -1335,6 +1461,8 @@ int sdpdem_info(sdpdem_system* s, int64_t out[16], void* hip_stream) {
   out[10] = s->d.nbox;
   out[11] = s->graph_steps_run;
   out[12] = s->side ? 1 : 0;
+  out[13] = s->searches;
+  out[14] = s->reuses;
   std::vector<int> cnt((size_t)s->d.n);
   hipStream_t st = (hipStream_t)hip_stream;
   if (hipMemcpyAsync(cnt.data(), s->d.nbr_cnt, sizeof(int) * s->d.n, hipMemcpyDeviceToHost, st) !=
@@ -1397,6 +1525,8 @@ void sdpdem_destroy(sdpdem_system* s) {
   drop_graph(s);
   prof_flush(s);
   free_side_stream(s);
+  if (s->h_moved) (void)hipHostFree(s->h_moved);
+  if (s->ev_moved) (void)hipEventDestroy(s->ev_moved);
   for (auto& e : s->ev) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);

@@ -143,6 +143,19 @@ struct Dev {
   // neighbours and fields
   int* nbr;  // [maxn * npad], neighbour k of particle i at k*npad + i
   int* nbr_cnt;
+  // candidate reuse (skin > 0): the partners within h + skin found by the
+  // last cell-grid search, in the same column-major form, the positions of
+  // that search, and a flag raised by a drift that moved a particle more
+  // than skin/2 from them
+  int reuse;
+  int maxcand;
+  double hc, hc2;  // h + skin and its square
+  double pad;      // skin/2: how far a particle may be from its cell
+  double mv2;      // the flag's threshold: (skin/2)^2, slightly less
+  int* cand;       // [maxcand * npad]
+  int* cand_cnt;
+  D4* xref;
+  int* moved;
   double* rho;
   double* p;
   D4* xp;   // x, y, z, p of the last build: the pressure filter's neighbour record
@@ -197,10 +210,13 @@ struct Dev {
 // host-side launchers (sdpdem_kernels.hip)
 void launch_fill_i32(int* a, int v, size_t count, hipStream_t st);
 void launch_fill_f64(double* a, double v, size_t count, hipStream_t st);
+// *dst = *src, dst in host-visible memory
+void launch_publish(const int* src, int* dst, hipStream_t st);
 void launch_bin(const Dev& d, hipStream_t st);
 void launch_bin_rigid(const Dev& d, hipStream_t st);
-// exclusive scan of count[0..m) into start[0..m] and (unless null) cursor[0..m)
-void launch_scan(const int* count, int m, int* start, int* cursor, int* block_sums,
+// exclusive scan of count[0..m) into start[0..m] and (unless null)
+// cursor[0..m); count is left all zero, ready for the next binning
+void launch_scan(int* count, int m, int* start, int* cursor, int* block_sums,
                  hipStream_t st);
 int scan_block_sums_size(int m);
 void launch_scatter(const uint32_t* key, int n, int* cursor, int* perm, hipStream_t st);
@@ -212,7 +228,10 @@ void launch_cell_sort(const int* start, int ncells, int* perm, const int* sortke
                       hipStream_t st);
 void launch_permute(const Dev& d, const D4* spos, const D4* svel, const D4* som,
                     const uint8_t* stype, const int* sgid, hipStream_t st);
+// the cell-grid search (with reuse on, also the candidates within h + skin)
 void launch_build_density(const Dev& d, hipStream_t st);
+// the lists, density and pressure from the candidates of the last search
+void launch_filter_density(const Dev& d, hipStream_t st);
 // start of a pass: Lees-Edwards offsets of every box for positions at step
 // *dstep + add and, with clear_rxn, the reaction's slot counts set to zero
 void launch_pass_prep(const Dev& d, BoxD* boxes, int add, bool clear_rxn, hipStream_t st);

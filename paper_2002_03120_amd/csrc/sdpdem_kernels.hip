@@ -49,6 +49,15 @@ void launch_fill_i32(int* a, int v, size_t count, hipStream_t st) {
     k_fill_i32<<<(unsigned)((count + BS - 1) / BS), BS, 0, st>>>(a, v, count);
   }
 }
+// one word of device memory into host-visible memory (a pinned host word):
+// cheaper than a copy command for the one flag the host waits on
+__global__ void k_publish(const int* src, int* dst) {
+  if (threadIdx.x == 0) __hip_atomic_store(dst, *src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+void launch_publish(const int* src, int* dst, hipStream_t st) {
+  k_publish<<<1, 64, 0, st>>>(src, dst);
+}
+
 void launch_fill_f64(double* a, double v, size_t count, hipStream_t st) {
   if (!count) return;
   k_fill_f64<<<(unsigned)((count + BS - 1) / BS), BS, 0, st>>>(a, v, count);
@@ -201,12 +210,22 @@ __global__ __launch_bounds__(BS) void k_scan_blocksums(int* block_sums, int nb) 
   if (threadIdx.x == 0) block_sums[nb] = carry;
 }
 
-__global__ __launch_bounds__(BS) void k_scan_apply(const int* in, int m, const int* block_sums,
+// also leaves the counts at zero for the next binning (the count array is
+// read by nothing after the scan), so no fill precedes the binning
+__global__ __launch_bounds__(BS) void k_scan_apply(int* in, int m, const int* block_sums,
                                                   int nb, int* start, int* cursor) {
   __shared__ int lds[BS / 64 + 1];
   int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
   int v[SCAN_ITEMS];
   load_items(in, m, base, v);
+  if (base + SCAN_ITEMS <= m) {
+    *reinterpret_cast<int4*>(in + base) = make_int4(0, 0, 0, 0);
+    *reinterpret_cast<int4*>(in + base + 4) = make_int4(0, 0, 0, 0);
+  } else {
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k)
+      if (base + k < m) in[base + k] = 0;
+  }
   int s = 0;
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) s += v[k];
@@ -239,7 +258,7 @@ __global__ __launch_bounds__(BS) void k_scan_apply(const int* in, int m, const i
 
 int scan_block_sums_size(int m) { return (m + SCAN_TILE - 1) / SCAN_TILE + 1; }
 
-void launch_scan(const int* count, int m, int* start, int* cursor, int* block_sums,
+void launch_scan(int* count, int m, int* start, int* cursor, int* block_sums,
                  hipStream_t st) {
   int nb = (m + SCAN_TILE - 1) / SCAN_TILE;
   if (nb < 1) nb = 1;
@@ -452,7 +471,10 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
     int oob = 0;
     const int cc[3] = {cell_coord(ps.x, gr, 0, &oob), cell_coord(ps.y, gr, 1, &oob),
                        cell_coord(ps.z, gr, 2, &oob)};
-    const int kr = reach_cells(gr, H);
+    // with candidate reuse the grid holds the particles where the last
+    // search saw them, up to pad from where they are: search that much wider
+    const double Hs = H + d.pad;
+    const int kr = reach_cells(gr, Hs);
     // the search box row by row: lane r takes row r of each batch of 64 rows
     // (at most two runs of consecutive cells per row)
     const StencilShape sh = stencil_shape(gr, cc, kr);
@@ -461,7 +483,7 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
       int sa = 0, la = 0, sb = 0, lb = 0;
       if (rb + lane < nrows) {
         int a0, a1, b0, b1;
-        stencil_row<true>(G, gr, coff, ps.x, ps.y, ps.z, H, cc, kr, sh, rb + lane, a0, a1, b0,
+        stencil_row<true>(G, gr, coff, ps.x, ps.y, ps.z, Hs, cc, kr, sh, rb + lane, a0, a1, b0,
                           b1);
         if (a1 > a0) {
           sa = d.cstart[a0];
@@ -965,7 +987,7 @@ __device__ __forceinline__ void total_force(const Dev& d, const BoxD& B, int i, 
 // RXN: the reaction of the coupled fluid particles is formed here too
 // (one launch less; the particle's F_RXN is used from registers)
 // (64 registers, eight waves per SIMD, fit without spills)
-template <int VELVER, bool RXN>
+template <int VELVER, bool RXN, bool MOVED = false>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_integrate(Dev d, int rigid_active, int end_step) {
   // the last pass of a step advances the device step counter (no kernel of
   // this launch reads it)
@@ -1044,6 +1066,14 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
     v.y = vv[1];
     v.z = vv[2];
     d.pos[i] = p;
+    if (MOVED) {
+      // farther than skin/2 from where the last search saw it: the next
+      // lists need a new search
+      const D4 q = d.xref[i];
+      double ex = p.x - q.x, ey = p.y - q.y, ez = p.z - q.z;
+      min_img_box(geo_of(B), ex, ey, ez);
+      if (r2_exact(ex, ey, ez) > d.mv2) atomicOr(d.moved, 1);
+    }
   }
   if (!isfinite(v.x) || !isfinite(v.y) || !isfinite(v.z) || !isfinite(w.x) || !isfinite(w.y) ||
       !isfinite(w.z) || (VELVER == 1 && (!isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z))))
@@ -1065,8 +1095,11 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
 
 void launch_integrate(const Dev& d, int velver, int rigid_active, bool end_step, bool fuse_rxn,
                       hipStream_t st) {
-  auto k = fuse_rxn ? (velver == 2 ? k_integrate<2, true> : k_integrate<1, true>)
-                    : (velver == 2 ? k_integrate<2, false> : k_integrate<1, false>);
+  // only the drift (velver 1) moves particles; the moved flag of candidate
+  // reuse is a separate instantiation, so the plain update keeps its registers
+  auto k = velver == 2 ? (fuse_rxn ? k_integrate<2, true> : k_integrate<2, false>)
+           : d.reuse   ? (fuse_rxn ? k_integrate<1, true, true> : k_integrate<1, false, true>)
+                       : (fuse_rxn ? k_integrate<1, true> : k_integrate<1, false>);
   k<<<d.nblk, BS, 0, st>>>(d, rigid_active, end_step ? 1 : 0);
 }
 

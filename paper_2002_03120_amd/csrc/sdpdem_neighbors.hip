@@ -13,9 +13,32 @@ namespace sdpdem {
 // contraction) fused with the density summation (Eq. compdens), the
 // equation of state (Eq. prtcpres) and the free-surface clamp.  The
 // stencil is walked row by row; the cells of a row are one contiguous slice
-// of the sorted arrays unless the row wraps.
+// of the sorted arrays unless the row wraps.  With CAND (candidate reuse)
+// the walk reaches h + skin and also keeps every partner within it, with
+// the positions it saw, for the list builds until the next search.
 
+// density and pressure of particle i from its kernel sum, and its
+// (position, pressure) record for the filter
+__device__ __forceinline__ void finish_density(const Dev& d, int i, const D4& pi, double acc) {
+  const double rho = d.cw_m * acc;
+  double p = d.p0 * pow(rho / d.rho0, d.alpha) - d.beta;
+  if (d.clamp && p < 0.0) p = 0.0;  // free-surface correction (Sec. 2.5)
+  d.rho[i] = rho;
+  d.p[i] = p;
+  d.xp[i] = D4{pi.x, pi.y, pi.z, p};
+}
+
+__device__ __forceinline__ void outer_wall_fields(const Dev& d, int i, const D4& pi) {
+  d.nbr_cnt[i] = 0;
+  d.rho[i] = d.rho0;
+  d.p[i] = d.p_ref;
+  d.xp[i] = D4{pi.x, pi.y, pi.z, d.p_ref};
+}
+
+template <bool CAND>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_build_density(Dev d) {
+  // a search resets the moved flag: positions are measured from here on
+  if (CAND && blockIdx.x == 0 && threadIdx.x == 0) d.moved[0] = 0;
   int i;
   const int b = blk_box(d, i);
   if (b < 0) return;
@@ -23,11 +46,10 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
   if (i >= B.first + B.count) return;
   uint8_t ti = d.type[i];
   const D4 pi = d.pos[i];
+  if (CAND) d.xref[i] = pi;
   if (ti == T_OUTER) {
-    d.nbr_cnt[i] = 0;
-    d.rho[i] = d.rho0;
-    d.p[i] = d.p_ref;
-    d.xp[i] = D4{pi.x, pi.y, pi.z, d.p_ref};
+    outer_wall_fields(d, i, pi);
+    if (CAND) d.cand_cnt[i] = 0;
     return;
   }
   const Geo G = geo_of(B);
@@ -37,10 +59,13 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
   const int cc[3] = {cell_coord(pi.x, gr, 0, &oob), cell_coord(pi.y, gr, 1, &oob),
                      cell_coord(pi.z, gr, 2, &oob)};
   const double h2 = d.h2, inv_h = d.inv_h;
+  const double R = CAND ? d.hc : d.h;
+  const double R2 = CAND ? d.hc2 : h2;
   double acc = d.W0;
-  int cnt = 0;
+  int cnt = 0, ccnt = 0;
   const size_t npad = (size_t)d.npad;
   int* const nb = d.nbr + i;
+  int* const cb = CAND ? d.cand + i : nullptr;
   auto run = [&](int k0, int k1) {
     const int jb = d.cstart[k0];
     const int je = d.cstart[k1];
@@ -49,37 +74,97 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
       double ex = pi.x - pj.x, ey = pi.y - pj.y, ez = pi.z - pj.z;
       min_img_box(G, ex, ey, ez);
       const double r2 = r2_exact(ex, ey, ez);
-      if (r2 < h2 && j != i) {
-        const double q = sqrt_nr(r2) * inv_h;
-        const double om = 1.0 - q;
-        if (cnt < d.maxn) nb[(size_t)cnt * npad] = j;
-        ++cnt;
-        acc += d.w_norm * (1.0 + 3.0 * q) * om * om * om;
+      if (r2 < R2 && j != i) {
+        if (CAND) {
+          if (ccnt < d.maxcand) cb[(size_t)ccnt * npad] = j;
+          ++ccnt;
+        }
+        if (!CAND || r2 < h2) {
+          const double q = sqrt_nr(r2) * inv_h;
+          const double om = 1.0 - q;
+          if (cnt < d.maxn) nb[(size_t)cnt * npad] = j;
+          ++cnt;
+          acc += d.w_norm * (1.0 + 3.0 * q) * om * om * om;
+        }
       }
     }
   };
-  // cells of h or more: the whole 27-cell stencil (lanes of a cell walk the
-  // same runs in step); smaller cells: the rows and x cells within h only
-  const int kr = reach_cells(gr, d.h);
+  // cells of R or more: the whole 27-cell stencil (lanes of a cell walk the
+  // same runs in step); smaller cells: the rows and x cells within R only
+  const int kr = reach_cells(gr, R);
   if (kr == 1)
-    for_stencil<false>(G, gr, coff, pi.x, pi.y, pi.z, d.h, cc, 1, run);
+    for_stencil<false>(G, gr, coff, pi.x, pi.y, pi.z, R, cc, 1, run);
   else
-    for_stencil_pruned(G, gr, coff, pi.x, pi.y, pi.z, d.h, cc, kr, run);
+    for_stencil_pruned(G, gr, coff, pi.x, pi.y, pi.z, R, cc, kr, run);
+  if (cnt > d.maxn || (CAND && ccnt > d.maxcand)) {
+    atomicOr(d.status, ST_NBR_OVERFLOW);
+    cnt = min(cnt, d.maxn);
+    ccnt = min(ccnt, d.maxcand);
+  }
+  d.nbr_cnt[i] = cnt;
+  if (CAND) d.cand_cnt[i] = ccnt;
+  finish_density(d, i, pi, acc);
+}
+
+void launch_build_density(const Dev& d, hipStream_t st) {
+  if (d.reuse)
+    k_build_density<true><<<d.nblk, BS, 0, st>>>(d);
+  else
+    k_build_density<false><<<d.nblk, BS, 0, st>>>(d);
+}
+
+// The lists of a drift that kept every particle within skin/2 of where the
+// last search saw it: a partner within h now was within h + skin then, so
+// the exact test over the candidates (in the same FP64 arithmetic) gives
+// the same set as a search.  Density, pressure and the filter's record as
+// in the search.
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_filter_density(Dev d) {
+  int i;
+  const int b = blk_box(d, i);
+  if (b < 0) return;
+  const BoxD& B = d.boxes[b];
+  if (i >= B.first + B.count) return;
+  const uint8_t ti = d.type[i];
+  const D4 pi = d.pos[i];
+  if (ti == T_OUTER) {
+    outer_wall_fields(d, i, pi);
+    return;
+  }
+  const Geo G = geo_of(B);
+  const double h2 = d.h2, inv_h = d.inv_h;
+  double acc = d.W0;
+  int cnt = 0;
+  const size_t npad = (size_t)d.npad;
+  int* const nb = d.nbr + i;
+  const int* const cb = d.cand + i;
+  const int cc = d.cand_cnt[i];
+  // the index of candidate k+1 is in flight while candidate k is tested
+  int jn = cc > 0 ? cb[0] : i;
+  for (int k = 0; k < cc; ++k) {
+    const int j = jn;
+    jn = k + 1 < cc ? cb[(size_t)(k + 1) * npad] : i;
+    const D4 pj = d.pos[j];
+    double ex = pi.x - pj.x, ey = pi.y - pj.y, ez = pi.z - pj.z;
+    min_img_box(G, ex, ey, ez);
+    const double r2 = r2_exact(ex, ey, ez);
+    if (r2 < h2) {
+      const double q = sqrt_nr(r2) * inv_h;
+      const double om = 1.0 - q;
+      if (cnt < d.maxn) nb[(size_t)cnt * npad] = j;
+      ++cnt;
+      acc += d.w_norm * (1.0 + 3.0 * q) * om * om * om;
+    }
+  }
   if (cnt > d.maxn) {
     atomicOr(d.status, ST_NBR_OVERFLOW);
     cnt = d.maxn;
   }
   d.nbr_cnt[i] = cnt;
-  const double rho = d.cw_m * acc;
-  double p = d.p0 * pow(rho / d.rho0, d.alpha) - d.beta;
-  if (d.clamp && p < 0.0) p = 0.0;  // free-surface correction (Sec. 2.5)
-  d.rho[i] = rho;
-  d.p[i] = p;
-  d.xp[i] = D4{pi.x, pi.y, pi.z, p};
+  finish_density(d, i, pi, acc);
 }
 
-void launch_build_density(const Dev& d, hipStream_t st) {
-  k_build_density<<<d.nblk, BS, 0, st>>>(d);
+void launch_filter_density(const Dev& d, hipStream_t st) {
+  k_filter_density<<<d.nblk, BS, 0, st>>>(d);
 }
 
 // ---------------------------------------------------------------------------

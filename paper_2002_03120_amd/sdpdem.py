@@ -63,7 +63,7 @@ class Params(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("max_neighbors", ctypes.c_int32), ("max_contacts", ctypes.c_int32),
         ("shear_rate", ctypes.c_double),
-        ("cell_factor", ctypes.c_double),
+        ("cell_factor", ctypes.c_double), ("skin", ctypes.c_double),
     ]
 
 

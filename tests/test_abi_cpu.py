@@ -2,6 +2,7 @@
 exports every symbol declared in include/*.h, sizes workspaces and rejects bad
 arguments before touching a device."""
 import ctypes
+import math
 import os
 import re
 
@@ -67,11 +68,28 @@ def test_cell_factor_grows_the_grid_below_h(lib):
     assert base < half < quarter  # the cell arrays grow with the number of cells
 
 
+def test_skin_adds_candidate_rows(lib):
+    """Candidate reuse keeps a second column-major table of the partners
+    within h + skin (rows of max_neighbors ((h + skin)/h)^3) and the
+    positions of the last search."""
+    p, parts, _ = W.reverse_poiseuille(n_side=(20, 20, 20))
+    base = S.sdpdem_workspace_bytes(p, parts)
+    assert S.sdpdem_workspace_bytes(dict(p, skin=0.0), parts) == base
+    n = parts["id"].shape[0]
+    g = (p["h"] + 0.3) / p["h"]
+    rows = math.ceil(p["max_neighbors"] * g ** 3)
+    grown = S.sdpdem_workspace_bytes(dict(p, skin=0.3), parts) - base
+    need = 4 * rows * n + 4 * n + 32 * n  # candidates, their counts, reference positions
+    assert abs(grown - need) <= 3 * 256  # 256-byte pieces (one each without reuse)
+
+
 @pytest.mark.parametrize("bad", [
     dict(xi=0.0), dict(xi=1.0), dict(h=0.0), dict(dt=-1.0), dict(L=[4.0, 10.0, 10.0]),
     dict(max_neighbors=0), dict(gravity_axis=3), dict(rho0=0.0),
     dict(cell_factor=0.2), dict(cell_factor=-1.0), dict(cell_factor=float("nan")),
     dict(cell_factor=17.0), dict(cell_factor=4.0),  # 4 h cells: fewer than 3 on a 10-site axis
+    dict(skin=-0.1), dict(skin=0.76), dict(skin=float("nan")),  # 0 <= skin <= h/2 = 0.75
+    dict(skin=0.3, shear_rate=0.01),  # no reuse across sheared images
 ])
 def test_rejects_bad_params(lib, bad):
     p, parts, _ = W.reverse_poiseuille(n_side=(10, 10, 10))

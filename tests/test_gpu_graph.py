@@ -73,3 +73,20 @@ def test_sheared_batch_with_stress_graph_equals_eager(S):
     b, _ = run(S, sh, parts, chunks, 10, stress=True, boxes=boxes, box_of=box_of)
     for x, y in zip(a, b):
         assert np.array_equal(np.asarray(x), np.asarray(y))
+
+
+def test_graphs_on_the_null_stream_stay_eager(S):
+    """Capture needs a stream of its own: on the null stream set_graph leaves
+    every step eager (none replayed) and the results are those of a system
+    without graphs.  (A capture that cannot start switches graphs off for
+    the rest of the call instead of being tried again.)"""
+    p, parts, _ = W.dam_break(tank=(40, 16, 30), column=(20, 16, 20), n_rigid=60, kBT=1e-4)
+    print("[case] dam break, graphs asked for on the null stream", flush=True)
+    a = S.System(p, parts)
+    a.set_graph(4)
+    a.step(9)
+    assert a.info()[11] == 0
+    b = S.System(p, parts)
+    b.step(9)
+    for k in ("POS", "VEL", "ANGVEL"):
+        assert np.array_equal(a.read_field(k), b.read_field(k))

@@ -1,0 +1,120 @@
+"""Neighbour-candidate reuse (skin > 0) against the FP64 oracle.
+
+With a skin the library searches the cell grid for partners within
+h + skin and, until some particle has moved skin/2 from where that search
+saw it, takes each drift's lists from those candidates instead of sorting
+and searching again (Alg. 1's neighbour step, Sec. 3.2).  The neighbour
+sets must stay exactly {j : r_ij < h}.  Each case runs a moving system long
+enough for several searches and many reusing steps, then hands its state
+(positions, velocities, spins, DEM contacts, step number) to the oracle,
+which searches from scratch: neighbour sets bit for bit, rho and p to
+1e-12, forces to the single-step tolerance, with the library's last lists
+taken from the candidates.
+"""
+import numpy as np
+import pytest
+
+from _parity import (VECTOR_FIELDS, assert_force_field, assert_same_neighbors,
+                     assert_scalar_fields)
+from paper_2002_03120_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2002_03120_amd import sdpdem
+    sdpdem.lib()
+    return sdpdem
+
+
+def _hand_over(S, oracle_lib, g, p, parts, fields):
+    """The oracle from g's current state; one force evaluation on each (g
+    keeps the lists its last step took from the candidates)."""
+    state = {k: np.array(v, copy=True) for k, v in parts.items()}
+    state["pos"], state["vel"], state["angvel"] = (g.read_field(f) for f in ("POS", "VEL", "ANGVEL"))
+    o = oracle_lib.Oracle(dict(p, itr_start=g.current_step), state)
+    pairs, dts = g.read_contacts()
+    if len(pairs):
+        o.load_contacts(pairs, dts)
+    rc_g = g.compute_forces(check=False)
+    rc_o = o.compute_forces(check=False)
+    assert rc_g == rc_o == 0, (rc_g, rc_o)
+    nnz = assert_same_neighbors(g, o)
+    assert_scalar_fields(g, o, p)
+    worst = {f: assert_force_field(g, o, f) for f in fields}
+    print("  nnz", nnz, "worst rel", {k: f"{v:.1e}" for k, v in worst.items()}, flush=True)
+
+
+def _run(S, p, parts, skin, steps, graph=0, **gpu_only):
+    g = S.System(dict(p, skin=skin, **gpu_only), parts)
+    if graph:
+        g.set_graph(graph)
+    g.step(steps)
+    info = g.info()
+    print(f"  {steps} steps: {info[13]} searches, {info[14]} lists from candidates", flush=True)
+    return g, info
+
+
+@pytest.mark.parametrize("cf", [0.5, 1.0])
+def test_dam_break_reused_lists_equal_a_fresh_search(S, oracle_lib, cf):
+    """Walls, inner walls, spheres with contacts and the coupling (whose
+    search in the grid of the last sort reaches skin/2 farther), thermal
+    noise; particles set moving so that the skin runs out several times."""
+    p, parts, _ = W.dam_break(tank=(40, 16, 30), column=(20, 16, 20), n_rigid=60, seed=7,
+                              kBT=1e-4)
+    parts = W.perturb(parts, p, jitter=0.1, kT=4e-2, seed=9, spin=True)
+    print(f"[case] dam break 40x16x30 skin 0.2h cell_factor={cf}", flush=True)
+    g, info = _run(S, p, parts, 0.3, 160, cell_factor=cf)
+    assert info[13] >= 3 and info[14] >= 60
+    _hand_over(S, oracle_lib, g, p, parts, VECTOR_FIELDS)
+
+
+def test_periodic_lattice_with_fast_particles(S, oracle_lib):
+    """A fully periodic jittered lattice at a high temperature: particles
+    wrap around the box between searches (the displacement is taken
+    through the minimum image) and the skin runs out every few steps."""
+    q, parts, _ = W.reverse_poiseuille(n_side=(14, 14, 14), dt=5e-3, kBT=2e-2)
+    parts = W.perturb(parts, q, jitter=0.1, kT=0.5, seed=22, spin=True)
+    print("[case] periodic lattice 14^3, fast particles, skin 0.2h", flush=True)
+    g, info = _run(S, q, parts, 0.3, 60)
+    assert info[13] >= 3 and info[14] >= 20
+    _hand_over(S, oracle_lib, g, q, parts, ["F_SDPD", "F_CD", "N_SDPD"])
+
+
+@pytest.mark.parametrize("noslip", [1, 0])
+def test_wall_crossings_between_searches(S, oracle_lib, noslip):
+    """A box with wall faces on every axis and no wall particles: fast
+    particles cross the faces (mirror and velocity reversal, Sec. 2.5)
+    while the lists come from the candidates."""
+    q, parts, _ = W.reverse_poiseuille(n_side=(12, 12, 12), dt=5e-3, kBT=0.0,
+                                       periodic=[0, 0, 0], g=0.0, noslip=noslip)
+    parts = W.perturb(parts, q, jitter=0.1, kT=0.5, seed=32, spin=True)
+    print(f"[case] walled lattice 12^3 noslip={noslip}, skin 0.3h", flush=True)
+    g, info = _run(S, q, parts, 0.45, 60)
+    assert info[14] >= 20
+    _hand_over(S, oracle_lib, g, q, parts, ["F_SDPD", "F_CD", "N_SDPD"])
+
+
+def test_graph_replay_searches_every_step(S, oracle_lib):
+    """Inside a captured graph the host cannot decide, so every replayed step
+    searches (and refreshes the candidates); eager steps after the replays
+    reuse them again."""
+    p, parts, _ = W.dam_break(tank=(40, 16, 30), column=(20, 16, 20), n_rigid=60, seed=8,
+                              kBT=0.0)
+    parts = W.perturb(parts, p, jitter=0.1, kT=4e-2, seed=10, spin=True)
+    import torch
+    print("[case] dam break, skin 0.2h, 4-step graphs", flush=True)
+    g = S.System(dict(p, skin=0.3), parts, stream=torch.cuda.Stream())  # capture needs one
+    g.set_graph(4)
+    g.step(17)  # one eager step (first search, then its drift), four graphs of four
+    info = g.info()
+    assert info[11] == 16 and info[13] >= 17 and info[13] + info[14] == 18, info[11:15]
+    g.set_graph(0)
+    g.step(6)
+    info = g.info()
+    assert info[14] >= 1, info[11:15]
+    _hand_over(S, oracle_lib, g, p, parts, VECTOR_FIELDS)
