@@ -707,9 +707,11 @@ void run_build(sdpdem_system* s, hipStream_t st, int commit_next, int lists = LI
                                             : hipEventRecord(s->ev_fork, st) == hipSuccess);
   s->fork_marked = false;
   if (search) {
+    // inside a graph no step can reuse candidates: the plain search there
+    const bool cand = d.reuse && !s->capturing;
     Prof pr(s, SDPDEM_K_NEIGHBORS_DENSITY, st);
-    launch_build_density(d, st);
-    s->cand_valid = d.reuse != 0;
+    launch_build_density(d, cand, st);
+    s->cand_valid = cand;
     s->searches += 1;
   } else {
     if (lists == LISTS_FILTER) {
@@ -797,7 +799,8 @@ void run_pass(sdpdem_system* s, int velver, int commit, bool integrate, bool fil
   if (integrate) {
     Prof pr(s, SDPDEM_K_INTEGRATE, st);
     // the second pass of a step also advances the device step counter
-    launch_integrate(d, velver, act ? 1 : 0, velver == 2, act, st);
+    // a captured graph never reads the moved flag: no need to raise it
+    launch_integrate(d, velver, act ? 1 : 0, velver == 2, act, d.reuse && !s->capturing, st);
   }
 }
 
@@ -1209,7 +1212,7 @@ int sdpdem_step(sdpdem_system* s, int64_t nsteps, void* hip_stream) {
       }
       if (hipGraphLaunch(s->gexec, st) != hipSuccess) return SDPDEM_E_HIP;
       s->rxn_valid = act_now;  // the last pass built and (with the coupling) refilled
-      s->cand_valid = s->d.reuse != 0;  // every replayed step searched
+      s->cand_valid = false;  // every replayed step searched, without candidates
       s->searches += K;
       s->step += K;
       s->graph_steps_run += K;

@@ -228,8 +228,9 @@ void launch_cell_sort(const int* start, int ncells, int* perm, const int* sortke
                       hipStream_t st);
 void launch_permute(const Dev& d, const D4* spos, const D4* svel, const D4* som,
                     const uint8_t* stype, const int* sgid, hipStream_t st);
-// the cell-grid search (with reuse on, also the candidates within h + skin)
-void launch_build_density(const Dev& d, hipStream_t st);
+// the cell-grid search; with cand (reuse on) also the candidates within
+// h + skin and the positions they were found at
+void launch_build_density(const Dev& d, bool cand, hipStream_t st);
 // the lists, density and pressure from the candidates of the last search
 void launch_filter_density(const Dev& d, hipStream_t st);
 // start of a pass: Lees-Edwards offsets of every box for positions at step
@@ -251,9 +252,10 @@ void launch_dem(const Dev& d, int commit, int* nxt_cnt, int* nxt_partner, double
                 hipStream_t st);
 // with end_step, block 0 also advances the device step counter; with
 // fuse_rxn the launch also forms the drag reaction (launch_fpi_reaction's
-// work) of the coupled fluid particles
+// work) of the coupled fluid particles; with track_moved the drift raises
+// the moved flag of candidate reuse
 void launch_integrate(const Dev& d, int velver, int rigid_active, bool end_step, bool fuse_rxn,
-                      hipStream_t st);
+                      bool track_moved, hipStream_t st);
 void launch_read_field(const Dev& d, int field, int rigid_active, double* out, hipStream_t st);
 int totals_partial_blocks(int n);
 void launch_totals(const Dev& d, double* partial, double* out, hipStream_t st);

@@ -1068,11 +1068,13 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
     d.pos[i] = p;
     if (MOVED) {
       // farther than skin/2 from where the last search saw it: the next
-      // lists need a new search
+      // lists need a new search (one atomic per wave, not per particle)
       const D4 q = d.xref[i];
       double ex = p.x - q.x, ey = p.y - q.y, ez = p.z - q.z;
       min_img_box(geo_of(B), ex, ey, ez);
-      if (r2_exact(ex, ey, ez) > d.mv2) atomicOr(d.moved, 1);
+      const bool far = r2_exact(ex, ey, ez) > d.mv2;
+      const unsigned long long m = __ballot(far);
+      if (m && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)m) - 1)) atomicOr(d.moved, 1);
     }
   }
   if (!isfinite(v.x) || !isfinite(v.y) || !isfinite(v.z) || !isfinite(w.x) || !isfinite(w.y) ||
@@ -1094,11 +1096,11 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
 }
 
 void launch_integrate(const Dev& d, int velver, int rigid_active, bool end_step, bool fuse_rxn,
-                      hipStream_t st) {
+                      bool track_moved, hipStream_t st) {
   // only the drift (velver 1) moves particles; the moved flag of candidate
   // reuse is a separate instantiation, so the plain update keeps its registers
   auto k = velver == 2 ? (fuse_rxn ? k_integrate<2, true> : k_integrate<2, false>)
-           : d.reuse   ? (fuse_rxn ? k_integrate<1, true, true> : k_integrate<1, false, true>)
+           : track_moved ? (fuse_rxn ? k_integrate<1, true, true> : k_integrate<1, false, true>)
                        : (fuse_rxn ? k_integrate<1, true> : k_integrate<1, false>);
   k<<<d.nblk, BS, 0, st>>>(d, rigid_active, end_step ? 1 : 0);
 }

@@ -36,7 +36,7 @@ __device__ __forceinline__ void outer_wall_fields(const Dev& d, int i, const D4&
 }
 
 template <bool CAND>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_build_density(Dev d) {
+__device__ __forceinline__ void build_density(const Dev& d) {
   // a search resets the moved flag: positions are measured from here on
   if (CAND && blockIdx.x == 0 && threadIdx.x == 0) d.moved[0] = 0;
   int i;
@@ -106,11 +106,20 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
   finish_density(d, i, pi, acc);
 }
 
-void launch_build_density(const Dev& d, hipStream_t st) {
-  if (d.reuse)
-    k_build_density<true><<<d.nblk, BS, 0, st>>>(d);
+// eight waves per SIMD for the plain search; the candidate search holds
+// more state and spills below 96 registers, so it takes five
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_build_density(Dev d) {
+  build_density<false>(d);
+}
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(5))) void k_build_candidates(Dev d) {
+  build_density<true>(d);
+}
+
+void launch_build_density(const Dev& d, bool cand, hipStream_t st) {
+  if (cand)
+    k_build_candidates<<<d.nblk, BS, 0, st>>>(d);
   else
-    k_build_density<false><<<d.nblk, BS, 0, st>>>(d);
+    k_build_density<<<d.nblk, BS, 0, st>>>(d);
 }
 
 // The lists of a drift that kept every particle within skin/2 of where the
@@ -138,12 +147,18 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
   int* const nb = d.nbr + i;
   const int* const cb = d.cand + i;
   const int cc = d.cand_cnt[i];
-  // the index of candidate k+1 is in flight while candidate k is tested
+  // software pipeline: the position of candidate k+1 and the index of
+  // candidate k+2 are in flight while candidate k is tested (past the end
+  // the loads fetch the particle's own, unused, entries)
   int jn = cc > 0 ? cb[0] : i;
+  D4 pn = d.pos[jn];
+  int jnn = cc > 1 ? cb[npad] : i;
   for (int k = 0; k < cc; ++k) {
     const int j = jn;
-    jn = k + 1 < cc ? cb[(size_t)(k + 1) * npad] : i;
-    const D4 pj = d.pos[j];
+    const D4 pj = pn;
+    jn = jnn;
+    pn = d.pos[jn];
+    jnn = k + 2 < cc ? cb[(size_t)(k + 2) * npad] : i;
     double ex = pi.x - pj.x, ey = pi.y - pj.y, ez = pi.z - pj.z;
     min_img_box(G, ex, ey, ez);
     const double r2 = r2_exact(ex, ey, ez);
