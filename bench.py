@@ -305,13 +305,20 @@ def window_leg(sysm, p, start_step, steps, n_moving):
 
 
 def cpu_model():
-    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    """The host CPU's model name (lscpu, else /proc/cpuinfo), with lscpu's
+    family / model / stepping numbers (a virtual machine may report only a
+    generic name)."""
     import subprocess
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        f = {}
         for ln in out.splitlines():
-            if ln.strip().startswith("Model name:"):
-                return ln.split(":", 1)[1].strip()
+            if ":" in ln:
+                k, v = ln.split(":", 1)
+                f.setdefault(k.strip(), v.strip())
+        if "Model name" in f:
+            ids = ", ".join(f"{k.lower()} {f[k]}" for k in ("CPU family", "Model", "Stepping") if k in f)
+            return f["Model name"] + (f" ({ids})" if ids else "")
     except (OSError, subprocess.SubprocessError):
         pass
     try:
