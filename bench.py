@@ -382,18 +382,20 @@ def main():
     ap.add_argument("--small", action="store_true", help="a small tank, for quick checks")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration)")
-    ap.add_argument("--cell-factor", type=float, default=0.5,
-                    help="fluid cell size in units of h; the default is the autotuner's "
-                         "pick for the dam break, 0 runs the tuner before the timed region")
+    ap.add_argument("--cell-factor", type=float, default=0.55,
+                    help="fluid cell size in units of h; the default is the fastest of a sweep "
+                         "over 0.5-0.75 h with candidate reuse at the default skin, 0 runs the "
+                         "tuner (without reuse) before the timed region")
     ap.add_argument("--graph-steps", type=int, default=10,
                     help="steps per captured graph for the graph-replay figure (0: skip)")
     ap.add_argument("--scale-steps", type=int, default=20,
                     help="timed steps of the 8,388,608-particle periodic scale run (0: skip)")
     ap.add_argument("--viscometer-steps", type=int, default=20,
                     help="timed steps per configuration of the batched-viscometer leg (0: skip)")
-    ap.add_argument("--skin", type=float, default=0.15,
+    ap.add_argument("--skin", type=float, default=0.1,
                     help="neighbour-candidate margin (0: sort and search after every drift); "
-                         "the default, 0.1 h, is the fastest of 0, 0.1 h, 0.15 h, 0.2 h here")
+                         "the default, h/15, is the fastest of 0.05 h, h/15, 0.1 h, 0.15 h, "
+                         "0.2 h here")
     ap.add_argument("--surrogate-cells", type=int, default=64,
                     help="fresh plain runs the committed surrogate is judged against (0: skip)")
     ap.add_argument("--window-step", type=int, default=2000,

@@ -32,7 +32,7 @@ import time
 from . import sdpdem as S
 from . import workloads as W
 
-CELL_FACTORS = (0.34, 0.5, 0.75, 1.0, 1.25)
+CELL_FACTORS = (0.34, 0.5, 0.55, 0.67, 0.75, 1.0, 1.25)
 GRAPH_STEPS = (10, 2, 20)  # the first is used while the cell size is tuned
 TILES = (1 << 20, 1 << 21, 1 << 22, 1 << 23)
 

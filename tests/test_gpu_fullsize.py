@@ -1,9 +1,10 @@
 """Parity at the full sizes of the measured workloads, in the launch
-configuration the benchmark uses (fluid cells of h/2) and at cells of h:
-the sedimentation box (101,080 particles), the dam break (1,534,168
-particles, 2^20 moving) and the periodic scale box (8,388,608 particles).
-The oracle evaluates every particle here; neighbour sets must match bit
-for bit."""
+configurations the benchmark uses (dam break: fluid cells of 0.55 h and
+neighbour-candidate reuse with skin h/15; scale box and viscometer: cells
+of h/2) and at cells of h: the sedimentation box (101,080 particles), the
+dam break (1,534,168 particles, 2^20 moving) and the periodic scale box
+(8,388,608 particles).  The oracle evaluates every particle here; neighbour
+sets must match bit for bit."""
 import numpy as np
 import pytest
 
@@ -24,7 +25,7 @@ def S():
 
 
 @pytest.mark.parametrize("name,cf", [("sedimentation", 0.5), ("sedimentation", 1.0),
-                                     ("dam_break", 0.5), ("dam_break", 1.0),
+                                     ("dam_break", 0.55), ("dam_break", 1.0),
                                      ("periodic_scale", 0.5)])
 def test_full_size_single_step(S, oracle_lib, name, cf):
     p, parts, info = W.CONFIGS[name]()
@@ -38,6 +39,21 @@ def test_full_size_single_step(S, oracle_lib, name, cf):
     assert_scalar_fields(g, o, p)
     worst = {f: assert_force_field(g, o, f) for f in VECTOR_FIELDS}
     print("  nnz", nnz, {k: f"{v:.1e}" for k, v in worst.items()}, flush=True)
+
+
+def test_full_dam_break_after_steps_with_reuse(S, oracle_lib):
+    """The bench's headline system (cells of 0.55 h, skin 0.1 = h/15) after
+    60 steps, its lists taken from the candidates since the last search:
+    the oracle, made from its state, searches from scratch."""
+    from test_gpu_reuse import _hand_over
+    p, parts, info = W.CONFIGS["dam_break"]()
+    print(f"[case] full-size dam break, 60 steps with reuse: n={info['n']}", flush=True)
+    g = S.System(dict(p, cell_factor=0.55, skin=0.1), parts)
+    g.step(60)
+    inf = g.info()
+    print(f"  {inf[13]} searches, {inf[14]} lists from candidates", flush=True)
+    assert inf[14] >= 30
+    _hand_over(S, oracle_lib, g, p, parts, VECTOR_FIELDS)
 
 
 def test_full_viscometer_batch_sampled_boxes(S, oracle_lib):

@@ -96,7 +96,7 @@ def test_ragged_and_tiny_sizes(S, oracle_lib):
         _check_all(g, o, p, fields=["F_SDPD", "F_CD", "N_SDPD"])
 
 
-@pytest.mark.parametrize("cf", [0.25, 0.34, 0.5, 0.75, 1.37, 2.0])
+@pytest.mark.parametrize("cf", [0.25, 0.34, 0.5, 0.55, 0.67, 0.75, 1.37, 2.0])
 def test_cell_size_leaves_neighbors_and_forces_unchanged(S, oracle_lib, cf):
     """The autotuner's cell-size knob: cells of cf x h change only which
     cells are searched (a reach of ceil(1/cf) cells with distance pruning

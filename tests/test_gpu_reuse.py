@@ -59,7 +59,7 @@ def _run(S, p, parts, skin, steps, graph=0, **gpu_only):
     return g, info
 
 
-@pytest.mark.parametrize("cf", [0.5, 1.0])
+@pytest.mark.parametrize("cf", [0.5, 0.55, 1.0])
 def test_dam_break_reused_lists_equal_a_fresh_search(S, oracle_lib, cf):
     """Walls, inner walls, spheres with contacts and the coupling (whose
     search in the grid of the last sort reaches skin/2 farther), thermal
