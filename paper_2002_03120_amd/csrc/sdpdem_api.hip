@@ -38,6 +38,9 @@ struct sdpdem_system {
   // search are in place; capturing (every step searches inside a graph);
   // searches and reusing list builds so far
   bool cand_valid = false;
+  // the coupling action's per-sphere records hold the partners of every
+  // sphere (within H_s + skin) at the current sorted order
+  bool rec_valid = false;
   bool capturing = false;
   int64_t searches = 0, reuses = 0;
   // pinned host word the moved flag is copied into, and the event the host
@@ -54,7 +57,7 @@ struct sdpdem_system {
   // captured step loop (graph_steps steps, an even number, per launch)
   int graph_steps = 0;
   hipGraphExec_t gexec = nullptr;
-  bool g_act = false, g_stress = false, g_rxn = false;
+  bool g_act = false, g_stress = false, g_rxn = false, g_rec = false;
   // a second stream of the library's own for work that does not depend on
   // what runs beside it (the rigid grid, the sphere records, the contacts),
   // forked from the caller's stream and joined back into it within the
@@ -676,6 +679,7 @@ void run_build(sdpdem_system* s, hipStream_t st, int commit_next, int lists = LI
   const int nc = d.ncells_all;
   const bool search = lists == LISTS_SEARCH;
   s->rxn_valid = false;  // the positions (and with a search the order) change
+  if (search) s->rec_valid = false;  // the coupling records hold old indices
   if (search) {
     {
       Prof pr(s, SDPDEM_K_BIN, st);
@@ -776,8 +780,14 @@ void run_pass(sdpdem_system* s, int velver, int commit, bool integrate, bool fil
       (void)hipStreamSynchronize(s->side);  // no device-side wait: wait here
     {
       Prof pr(s, SDPDEM_K_FPI_ACTION, st);
-      launch_fpi_action(d, fill, st);
-      if (fill) s->rxn_valid = true;
+      // a filling pass reads the coupling records when the particles kept
+      // the order of the sort the records were made at
+      const bool use_rec = fill && s->rec_valid;
+      launch_fpi_action(d, fill, use_rec, st);
+      if (fill) {
+        s->rxn_valid = true;
+        s->rec_valid = true;  // a search-based fill records every sphere
+      }
     }
     // the reaction of an updating pass is formed inside the update
     if (!integrate) {
@@ -1152,7 +1162,7 @@ bool capture(sdpdem_system* s, hipStream_t st) {
   drop_graph(s);
   const int64_t step0 = s->step, samples0 = s->stress_samples;
   const int cur0 = s->cur, ct0 = s->ct_cur;
-  const bool rxn0 = s->rxn_valid, cand0 = s->cand_valid;
+  const bool rxn0 = s->rxn_valid, cand0 = s->cand_valid, rec0 = s->rec_valid;
   const int64_t searches0 = s->searches;
   hipGraph_t g = nullptr;
   if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
@@ -1165,6 +1175,7 @@ bool capture(sdpdem_system* s, hipStream_t st) {
   s->stress_samples = samples0;
   s->rxn_valid = rxn0;
   s->cand_valid = cand0;
+  s->rec_valid = rec0;
   s->searches = searches0;
   if (s->cur != cur0 || s->ct_cur != ct0) {
     if (g) (void)hipGraphDestroy(g);
@@ -1178,6 +1189,7 @@ bool capture(sdpdem_system* s, hipStream_t st) {
   s->gexec = ex;
   s->g_act = rigid_active(s);
   s->g_rxn = rxn0;
+  s->g_rec = rec0;
   s->g_stress = s->stress;
   s->g_cur = s->cur;
   s->g_ct = s->ct_cur;
@@ -1204,7 +1216,7 @@ int sdpdem_step(sdpdem_system* s, int64_t nsteps, void* hip_stream) {
       // eager steps since the capture swaps them) and whether its first
       // pass refills the coupling slots: capture again when either differs
       if (!s->gexec || s->g_act != act_now || s->g_stress != s->stress || s->g_cur != s->cur ||
-          s->g_ct != s->ct_cur || s->g_rxn != s->rxn_valid) {
+          s->g_ct != s->ct_cur || s->g_rxn != s->rxn_valid || s->g_rec != s->rec_valid) {
         if (!capture(s, st)) {
           s->graph_steps = 0;  // capture unavailable: stay eager
           continue;
@@ -1213,6 +1225,7 @@ int sdpdem_step(sdpdem_system* s, int64_t nsteps, void* hip_stream) {
       if (hipGraphLaunch(s->gexec, st) != hipSuccess) return SDPDEM_E_HIP;
       s->rxn_valid = act_now;  // the last pass built and (with the coupling) refilled
       s->cand_valid = false;  // every replayed step searched, without candidates
+      s->rec_valid = act_now;  // and (with the coupling) filled by a search
       s->searches += K;
       s->step += K;
       s->graph_steps_run += K;

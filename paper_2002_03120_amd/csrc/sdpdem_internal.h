@@ -245,8 +245,10 @@ void launch_fluid_forces(const Dev& d, bool noise, hipStream_t st, hipEvent_t t0
 void launch_rigid_gather(const Dev& d, hipStream_t st);
 // the coupling action (the per-sphere gather, then the per-sphere drag and
 // pressure-gradient algebra); with fill it also refills the reaction's
-// slots (counts cleared) and the candidate lists
-void launch_fpi_action(const Dev& d, bool fill, hipStream_t st);
+// slots (counts cleared) and, unless use_rec, searches and records every
+// sphere's partners; use_rec: the partners come from the records of the
+// last sort (every particle within skin/2 of where that sort saw it)
+void launch_fpi_action(const Dev& d, bool fill, bool use_rec, hipStream_t st);
 void launch_fpi_reaction(const Dev& d, hipStream_t st);
 void launch_dem(const Dev& d, int commit, int* nxt_cnt, int* nxt_partner, double* nxt_dt,
                 hipStream_t st);

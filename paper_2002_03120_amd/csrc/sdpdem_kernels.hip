@@ -402,8 +402,17 @@ __device__ __forceinline__ int wave_sum_i(int v) {
   return v;
 }
 
+// The record of a sphere (keyed by its rigid slot, so that it survives the
+// rigid grid's re-sort every step): per round and lane the partner a
+// search visited within H_s + skin, fluid j as j, rigid k as -2 - k, none as
+// -1.  Passes at the same sorted order read it instead of searching: the
+// same partners in the same lanes and rounds, each tested against H_s
+// again, so a pass at the search's positions gives the search's bits and a
+// pass after a drift of less than skin/2 finds every partner within H_s.
+// With use_rec a filling pass also reads it (the candidates of a build
+// that kept the sorted order).
 template <bool STRESS, bool FILL>
-__global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
+__global__ __launch_bounds__(BS) void k_fpi_action(Dev d, int use_rec) {
   const int wave = xcd_wave();
   const int lane = threadIdx.x & 63;
   if (wave >= d.nr) return;
@@ -416,7 +425,7 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
   const double R = ps.w, H = R + d.h, H2 = H * H;
   const double invH = 1.0 / H, wnorm = 105.0 / (16.0 * PI * H * H * H);  // Eq. kernel
   const size_t np = (size_t)d.npad;
-  int* const list = d.act_list + (size_t)wave * (ACT_ROUNDS * 64);
+  int* const list = d.act_list + (size_t)s * (ACT_ROUNDS * 64);
   double om = 0, v0 = 0, v1 = 0, v2 = 0, f0 = 0, f1 = 0, f2 = 0, l2 = 0;
   int nrig = 0;
   // the pair geometry of fluid candidate j: image separation, its z image
@@ -450,30 +459,36 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
     f2 += w * (double)d.fout[8 * np + j];
     if (STRESS) l2 += w * ez;  // the coupling's lever (z part)
   };
-  const int2 meta = FILL ? make_int2(-1, 0) : d.act_meta[wave];
+  const int2 meta = FILL && !use_rec ? make_int2(-1, 0) : d.act_meta[s];
   const int stored = __builtin_amdgcn_readfirstlane(meta.x);
   int rounds = 0;  // candidate rounds of the cell search
-  if (!FILL && stored >= 0) {
-    // the pass after the fill: the same candidates in the same lanes and
-    // rounds, read from the list (no cell search, no rejections)
+  if (stored >= 0) {
+    rounds = stored;
     for (int r = 0; r < stored; ++r) {
-      const int j = list[r * 64 + lane];
-      if (j < 0) continue;
+      const int e = list[r * 64 + lane];
+      if (e == -1) continue;
+      const int j = e >= 0 ? e : -2 - e;
       double ez;
       int kz;
       const double r2 = geom(j, ez, kz);
-      couple(j, r2, ez, kz);
+      if (r2 < H2) {
+        if (e >= 0)
+          couple(j, r2, ez, kz);
+        else
+          ++nrig;
+      }
     }
-    nrig = lane == 0 ? meta.y : 0;
   } else {
     const Grid gr = B.g;
     const int coff = B.cell_off;
     int oob = 0;
     const int cc[3] = {cell_coord(ps.x, gr, 0, &oob), cell_coord(ps.y, gr, 1, &oob),
                        cell_coord(ps.z, gr, 2, &oob)};
-    // with candidate reuse the grid holds the particles where the last
-    // search saw them, up to pad from where they are: search that much wider
-    const double Hs = H + d.pad;
+    // the record keeps the partners within H_s + skin; with candidate
+    // reuse the grid holds the particles where the last search saw them, up
+    // to pad from where they are: search that much wider
+    const double Hr = H + 2.0 * d.pad, Hr2 = Hr * Hr;
+    const double Hs = Hr + d.pad;
     const int kr = reach_cells(gr, Hs);
     // the search box row by row: lane r takes row r of each batch of 64 rows
     // (at most two runs of consecutive cells per row)
@@ -518,7 +533,7 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
         const int sar = __shfl(sa, r, 64);
         const int lar = __shfl(la, r, 64);
         const int sbr = __shfl(sb, r, 64);
-        int rec = -1;  // the fluid particle this lane couples to in this round
+        int rec = -1;  // this lane's partner of this round within H_s + skin
         if (t < total) {
           const int q = t - offr;
           const int j = q < lar ? sar + q : sbr + (q - lar);
@@ -528,13 +543,12 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
             double ez;
             int kz;
             const double r2 = geom(j, ez, kz);
+            if (r2 < Hr2) rec = tj == T_RIGID ? -2 - j : j;
             if (r2 < H2) {
-              if (tj == T_RIGID) {
+              if (tj == T_RIGID)
                 ++nrig;
-              } else {
+              else
                 couple(j, r2, ez, kz);
-                rec = j;
-              }
             }
           }
         }
@@ -552,8 +566,15 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d) {
   if (STRESS) l2 = wave_sum(l2);
   nrig = wave_sum_i(nrig);
   if (lane != 0) return;
-  // the list of this fill (-1: more rounds than it holds, search again)
-  if (FILL) d.act_meta[wave] = make_int2(rounds <= ACT_ROUNDS ? rounds : -1, nrig);
+  // the record of this search (-1: more rounds than it holds, search
+  // again) and the rigid count of this pass, for the finishing kernel
+  // (a sphere that had to search although the pass reads records keeps no
+  // record: a record must hold the partners around the reference
+  // positions of the last sort, which such a search no longer sees)
+  if (stored >= 0)
+    d.act_meta[s] = make_int2(stored, nrig);
+  else
+    d.act_meta[s] = make_int2(rounds <= ACT_ROUNDS && !use_rec ? rounds : -1, nrig);
   double* out = d.act_sum + 8 * (size_t)wave;
   out[0] = om;
   out[1] = v0;
@@ -579,7 +600,7 @@ __global__ __launch_bounds__(BS) void k_fpi_finish(Dev d) {
   const double invH = 1.0 / H, wnorm = 105.0 / (16.0 * PI * H * H * H);  // Eq. kernel
   const double* a = d.act_sum + 8 * (size_t)t;
   const double om = a[0], v0 = a[1], v1 = a[2], v2 = a[3], f0 = a[4], f1 = a[5], f2 = a[6];
-  const int nrig = d.act_meta[t].y;
+  const int nrig = d.act_meta[s].y;
   const double Vs = 4.0 / 3.0 * PI * R * R * R;
   const double VH = 4.0 / 3.0 * PI * H * H * H;
   double eps = 1.0 - Vs * (double)nrig / VH;
@@ -615,11 +636,11 @@ __global__ __launch_bounds__(BS) void k_fpi_finish(Dev d) {
   d.rdg_c[t] = rc;
 }
 
-void launch_fpi_action(const Dev& d, bool fill, hipStream_t st) {
+void launch_fpi_action(const Dev& d, bool fill, bool use_rec, hipStream_t st) {
   if (d.nr == 0) return;
   auto k = d.stress ? (fill ? k_fpi_action<true, true> : k_fpi_action<true, false>)
                     : (fill ? k_fpi_action<false, true> : k_fpi_action<false, false>);
-  k<<<nblocks((size_t)d.nr * 64), BS, 0, st>>>(d);
+  k<<<nblocks((size_t)d.nr * 64), BS, 0, st>>>(d, use_rec ? 1 : 0);
   // one wavefront per block: the few thousand threads of the finish spread
   // over as many CUs as possible (its FP64 divisions and powers are latency)
   auto f = d.stress ? k_fpi_finish<true> : k_fpi_finish<false>;
