@@ -42,16 +42,23 @@ def pair_kernel_bytes(n, n_act, nnz_act, noise):
     return n * (1 + 36) + n_act * (32 + 16 + 16 + 4 + (4 if noise else 0)) + 4 * nnz_act
 
 
-PAIR_KERNEL_SOURCES = ("paper_2002_03120_amd/csrc/sdpdem_neighbors.hip",
-                       "paper_2002_03120_amd/csrc/sdpdem_device.h",
-                       "paper_2002_03120_amd/csrc/sdpdem_internal.h")
-
-
 def pair_kernel_sha256():
+    """Hash of what the pair kernel is made of: its own source (the pair-force
+    section of sdpdem_neighbors.hip to the end of its launcher), the device
+    helpers it calls (sdpdem_device.h) and the pair record it loads.  Counter
+    figures taken with other sources are not used."""
     import hashlib
+    csrc = os.path.join(ROOT, "paper_2002_03120_amd", "csrc")
+    nb = open(os.path.join(csrc, "sdpdem_neighbors.hip")).read()
+    a = nb.index("// (a5) SDPD+a pair forces")
+    b = nb.index("}  // namespace sdpdem", a)
+    internal = open(os.path.join(csrc, "sdpdem_internal.h")).read()
+    c = internal.index("struct __align__(64) PR {")
+    e = internal.index("static_assert(sizeof(PR)", c)
     h = hashlib.sha256()
-    for f in PAIR_KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
+    h.update(nb[a:b].encode())
+    h.update(open(os.path.join(csrc, "sdpdem_device.h"), "rb").read())
+    h.update(internal[c:e].encode())
     return h.hexdigest()
 
 

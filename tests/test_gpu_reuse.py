@@ -118,3 +118,39 @@ def test_graph_replay_searches_every_step(S, oracle_lib):
     info = g.info()
     assert info[14] >= 1, info[11:15]
     _hand_over(S, oracle_lib, g, p, parts, VECTOR_FIELDS)
+
+
+def test_batch_of_boxes_with_reuse(S, oracle_lib):
+    """A batch of three unsheared periodic cells with spheres (the batched
+    viscometer's boxes at zero shear rate), run with a skin: any box's
+    drift past skin/2 makes the whole batch search again.  Each box's
+    state afterwards goes to an oracle of its own."""
+    cells = [W.shear_cell(n_side=n, phi=0.2, d=3.0, kBT=0.05, shear_rate=0.0, seed=40 + n)
+             for n in (10, 12, 11)]
+    parts, boxes, box_of = W.stack_cells(cells)
+    print(f"[case] batch of 3 unsheared cells, skin 0.3: n={parts['id'].shape[0]}", flush=True)
+    g = S.System(dict(cells[0][0], skin=0.3), parts, boxes=boxes, box_of=box_of)
+    g.step(80)
+    inf = g.info()
+    print(f"  80 steps: {inf[13]} searches, {inf[14]} lists from candidates", flush=True)
+    assert inf[14] >= 20
+    g.compute_forces()
+    pos, vel, ang = (g.read_field(f) for f in ("POS", "VEL", "ANGVEL"))
+    rows, cols = g.read_neighbors()
+    rho = g.read_field("DENS")
+    fs = g.read_field("F_SDPD")
+    off = 0
+    for p, pp, info in cells:
+        n = pp["id"].shape[0]
+        st = {k: np.array(v, copy=True) for k, v in pp.items()}
+        st["pos"], st["vel"], st["angvel"] = pos[off:off + n], vel[off:off + n], ang[off:off + n]
+        o = oracle_lib.Oracle(dict(p, itr_start=g.current_step), st)
+        assert o.compute_forces(check=False) == 0
+        ro, co = o.read_neighbors()
+        assert np.array_equal(rows[off:off + n + 1] - rows[off], ro)
+        assert np.array_equal(cols[rows[off]:rows[off + n]] - off, co)
+        assert np.allclose(rho[off:off + n], o.read_field("DENS"), rtol=1e-12, atol=0)
+        sc = o.read_field("F_SDPD_ABS")
+        err = np.linalg.norm(fs[off:off + n] - o.read_field("F_SDPD"), axis=1)
+        assert np.all(err <= 1e-5 * sc + 1e-30)
+        off += n
