@@ -568,13 +568,14 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d, int use_rec) {
   if (lane != 0) return;
   // the record of this search (-1: more rounds than it holds, search
   // again) and the rigid count of this pass, for the finishing kernel
-  // (a sphere that had to search although the pass reads records keeps no
-  // record: a record must hold the partners around the reference
-  // positions of the last sort, which such a search no longer sees)
+  // Only a filling search that does not read records writes one (a pass
+  // that does not fill writes no list; and a sphere that had to search
+  // although the pass reads records keeps none, since a record must hold
+  // the partners around where the last sort saw the particles).
   if (stored >= 0)
     d.act_meta[s] = make_int2(stored, nrig);
   else
-    d.act_meta[s] = make_int2(rounds <= ACT_ROUNDS && !use_rec ? rounds : -1, nrig);
+    d.act_meta[s] = make_int2(FILL && !use_rec && rounds <= ACT_ROUNDS ? rounds : -1, nrig);
   double* out = d.act_sum + 8 * (size_t)wave;
   out[0] = om;
   out[1] = v0;
