@@ -292,7 +292,7 @@ def philox4x32_10(ctr, key):
 
 
 def pair_normals(seed, id_a, id_b, step):
-    z = np.zeros(6, dtype=np.float64)
+    z = np.zeros(4, dtype=np.float64)
     lib().oracle_pair_normals(int(seed), int(id_a), int(id_b), int(step), _dp(z))
     return z
 

@@ -182,24 +182,21 @@ void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2],
   out[3] = x3;
 }
 
-/* Six standard normals for the unordered pair {a, b} at a step (R7): the
- * independent entries of the symmetric part of dW (R6).  Uniforms
- * u = ((x >> 8) + 1) 2^-24 in (0, 1] from two Philox blocks; Box-Muller
- * (1958) on consecutive pairs (u0,u1), (u2,u3), (u4,u5).                 */
+/* Four standard normals for the unordered pair {a, b} at a step (R6, R7).
+ * Uniforms u = ((x >> 8) + 1) 2^-24 in (0, 1] from one Philox block with
+ * counter (min id, max id, step, 0); Box-Muller (1958) on (u0,u1) and
+ * (u2,u3).                                                               */
 void oracle_pair_normals(uint64_t seed, int64_t id_a, int64_t id_b,
-                         int64_t step, double z[6]) {
+                         int64_t step, double z[4]) {
   int64_t lo = id_a < id_b ? id_a : id_b;
   int64_t hi = id_a < id_b ? id_b : id_a;
   uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
-  double u[8];
-  for (uint32_t blk = 0; blk < 2; ++blk) {
-    uint32_t ctr[4] = {(uint32_t)lo, (uint32_t)hi, (uint32_t)step, blk};
-    uint32_t x[4];
-    oracle_philox4x32_10(ctr, key, x);
-    for (int k = 0; k < 4; ++k)
-      u[4 * blk + k] = ((double)(x[k] >> 8) + 1.0) * (1.0 / 16777216.0);
-  }
-  for (int m = 0; m < 3; ++m) {
+  uint32_t ctr[4] = {(uint32_t)lo, (uint32_t)hi, (uint32_t)step, 0u};
+  uint32_t x[4];
+  oracle_philox4x32_10(ctr, key, x);
+  double u[4];
+  for (int k = 0; k < 4; ++k) u[k] = ((double)(x[k] >> 8) + 1.0) * (1.0 / 16777216.0);
+  for (int m = 0; m < 2; ++m) {
     double rad = sqrt(-2.0 * log(u[2 * m]));
     double ang = 2.0 * M_PI * u[2 * m + 1];
     z[2 * m] = rad * cos(ang);
@@ -244,18 +241,23 @@ void oracle_pair_force(const oracle_params* P, const double rij[3],
   if (P->kBT > 0.0 && P->coeff_t != 0.0) {
     double sa = 2.0 * sqrt(P->kBT * ga);
     double sb = 2.0 * sqrt(P->kBT * gb);
-    /* sym(dW)/sqrt(dt): diagonal entries z0..z2 ~ N(0,1), off-diagonal
-     * entries (01, 02, 12) = z3..z5 / sqrt(2) ~ N(0,1/2), the law of
-     * (zeta_ab + zeta_ba)/2 for independent standard zeta (R6)          */
-    double z[6];
+    /* Eq. FijT needs dW only as (sa dW^S + sb tr(dW)/3 1) e.  For a matrix
+     * of independent standard increments (per sqrt(dt)) that vector is
+     * Gaussian with variance 1/2 in each direction across e and
+     * sa^2 2/3 + sb^2 1/3 along e (the traceless part's e-e entry has
+     * variance 2/3, tr/3 has 1/3, and the three are independent): drawn
+     * as s_ij P_perp xi / sqrt(2) with xi = (z0, z1, z2) and
+     * P_perp = 1 - e e^T, plus z3 along e (R6).  s_ij = +1 if id_i < id_j,
+     * else -1, keeps F^T_ji = -F^T_ij for the shared draw.               */
+    double z[4];
     oracle_pair_normals(P->seed, idi, idj, step, z);
-    double tr3 = (z[0] + z[1] + z[2]) / 3.0;
-    double h01 = z[3] / sqrt(2.0), h02 = z[4] / sqrt(2.0), h12 = z[5] / sqrt(2.0);
-    double S[3][3] = {{z[0] - tr3, h01, h02}, {h01, z[1] - tr3, h12}, {h02, h12, z[2] - tr3}};
+    double xe = z[0] * e[0] + z[1] * e[1] + z[2] * e[2];
+    double s = idi < idj ? 1.0 : -1.0;
+    double cpar = sqrt(sa * sa * (2.0 / 3.0) + sb * sb * (1.0 / 3.0));
     double sq = sqrt(P->dt);
     for (int a = 0; a < 3; ++a) {
-      double se = S[a][0] * e[0] + S[a][1] * e[1] + S[a][2] * e[2];
-      ft[a] = P->coeff_t * (sa * se + sb * tr3 * e[a]) / sq;
+      double perp = z[a] - xe * e[a];
+      ft[a] = P->coeff_t * (sa * s * perp / sqrt(2.0) + cpar * z[3] * e[a]) / sq;
     }
   }
 }

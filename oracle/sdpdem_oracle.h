@@ -125,11 +125,10 @@ double oracle_lucy_f(double r, double h);   /* Eq. F = -W'(r)/r           */
 double oracle_lattice_w_sum(double h, double dx); /* sum_k W(|k| dx)     */
 void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2],
                           uint32_t out[4]);
-/* the six standard normals of the pair (a,b) at a given step: the
- * independent entries of sym(dW) (diagonal, then 01, 02, 12 scaled by
- * sqrt 2) */
+/* the four standard normals of the pair (a,b) at a given step: three for
+ * the thermal force across e_ij, one along it */
 void oracle_pair_normals(uint64_t seed, int64_t id_a, int64_t id_b,
-                         int64_t step, double z[6]);
+                         int64_t step, double z[4]);
 /* F^C, F^D, F^R, F^T of one pair, r_ij = xi - xj (already minimum image);
  * d_i, d_j are number densities rho/m_f; ps_* smoothed pressures */
 void oracle_pair_force(const oracle_params* p, const double rij[3],

@@ -443,24 +443,16 @@ __device__ __forceinline__ float u01(uint32_t x) {
   return (float)((x >> 8) + 1u) * 5.9604644775390625e-8f;  // (0, 1], exact
 }
 
-// six standard normals of the unordered pair {a, b} at a step (two Philox
-// blocks, Box-Muller on three pairs of uniforms): the independent entries
-// of the symmetric part of the Wiener matrix of Eq. FijT
+// four standard normals of the unordered pair {a, b} at a step (one Philox
+// block, Box-Muller on two pairs of uniforms): three across e_ij and one
+// along it, the thermal force of Eq. FijT in its pair frame
 __device__ __forceinline__ void pair_normals(uint32_t a, uint32_t b, uint32_t step, uint32_t k0,
-                                             uint32_t k1, float z[6]) {
-  uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
-  float u[8];
+                                             uint32_t k1, float z[4]) {
+  uint32_t c0 = a < b ? a : b, c1 = a < b ? b : a, c2 = step, c3 = 0u;
+  philox10(c0, c1, c2, c3, k0, k1);
+  const float u[4] = {u01(c0), u01(c1), u01(c2), u01(c3)};
 #pragma unroll
-  for (uint32_t blk = 0; blk < 2; ++blk) {
-    uint32_t c0 = lo, c1 = hi, c2 = step, c3 = blk;
-    philox10(c0, c1, c2, c3, k0, k1);
-    u[4 * blk + 0] = u01(c0);
-    u[4 * blk + 1] = u01(c1);
-    u[4 * blk + 2] = u01(c2);
-    u[4 * blk + 3] = u01(c3);
-  }
-#pragma unroll
-  for (int m = 0; m < 3; ++m) {
+  for (int m = 0; m < 2; ++m) {
     float rad = sqrtf(-2.0f * logf(u[2 * m]));
     // sin and cos of 2 pi u by the hardware units, whose argument is in
     // revolutions (largest error 1.3e-7 over every u this generator makes)

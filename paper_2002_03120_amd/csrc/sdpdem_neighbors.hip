@@ -322,27 +322,27 @@ __global__ __launch_bounds__(BS) void k_fluid_forces(Dev d) {
       ty += rry;
       tz += rrz;
       if (noise) {
-        // thermal force, Eq. FijT with dW^S = sym(dW) - tr(dW)/3: sym(dW)
-        // has diagonal entries z0..z2 ~ N(0,1) and off-diagonal entries
-        // z3..z5 / sqrt 2 ~ N(0,1/2), the law of (zeta_ab + zeta_ba)/2
-        float z[6];
-        pair_normals(gi, (uint32_t)rj.gid - ib, step, key0, key1, z);
-        const float sa = 2.0f * sqrtf(kT * d.CAf * fdd);
-        const float sb = 2.0f * sqrtf(kT * d.CBf * fdd);
-        const float tr3 = (z[0] + z[1] + z[2]) * (1.0f / 3.0f);
-        const float s01 = z[3] * 0.70710678118654752f, s02 = z[4] * 0.70710678118654752f,
-                    s12 = z[5] * 0.70710678118654752f;
-        const float se0 = (z[0] - tr3) * ex + s01 * ey + s02 * ez;
-        const float se1 = s01 * ex + (z[1] - tr3) * ey + s12 * ez;
-        const float se2 = s02 * ex + s12 * ey + (z[2] - tr3) * ez;
-        const float ca = d.cT * d.inv_sqrt_dtf * sa;
-        const float cb = d.cT * d.inv_sqrt_dtf * sb * tr3;
-        fx += ca * se0 + cb * ex;
-        fy += ca * se1 + cb * ey;
-        fz += ca * se2 + cb * ez;
-        tx += ca * se0;
-        ty += ca * se1;
-        tz += ca * se2;
+        // thermal force, Eq. FijT: (sa dW^S + sb tr(dW)/3 1) e for a matrix
+        // of independent increments is Gaussian with variance 1/2 across e
+        // and sa^2 2/3 + sb^2 1/3 along it (in units of sa^2 and dt), the
+        // two parts independent: s_ij P_perp z / sqrt 2 with z = (z0, z1,
+        // z2) plus z3 along e, s_ij = +1 for gid_i < gid_j (F_ji = -F_ij)
+        float z[4];
+        const uint32_t gj = (uint32_t)rj.gid - ib;
+        pair_normals(gi, gj, step, key0, key1, z);
+        const float sa2 = 4.0f * kT * d.CAf * fdd, sb2 = 4.0f * kT * d.CBf * fdd;
+        const float ze = z[0] * ex + z[1] * ey + z[2] * ez;
+        const float px = z[0] - ze * ex, py = z[1] - ze * ey, pz = z[2] - ze * ez;
+        const float cn = d.cT * d.inv_sqrt_dtf;
+        const float cp = cn * sqrtf(sa2) * (gi < gj ? 0.70710678118654752f : -0.70710678118654752f);
+        const float cq = cn * sqrtf(sa2 * (2.0f / 3.0f) + sb2 * (1.0f / 3.0f)) * z[3];
+        fx += cp * px + cq * ex;
+        fy += cp * py + cq * ey;
+        fz += cp * pz + cq * ez;
+        // the torque takes the part across e (e x e = 0)
+        tx += cp * px;
+        ty += cp * py;
+        tz += cp * pz;
       }
       F0 += fx;
       F1 += fy;

@@ -228,7 +228,7 @@ int main(void) {
   {
     uint32_t c[4] = {1, 2, 3, 4}, k[2] = {5, 6}, o[4];
     oracle_philox4x32_10(c, k, o);
-    double z[6];
+    double z[4];
     oracle_pair_normals(7, 3, 9, 11, z);
     CHECK(oracle_lattice_w_sum(1.5, 1.0) > 0.0);
     CHECK(oracle_drag_b(0.5, 0.1, 1.0, 1.0, 0.1) > 0.0);

@@ -99,3 +99,40 @@ def test_fluctuation_dissipation(oracle_lib, xi_frac):
     tol = 5.0 * np.sqrt(2.0 / n) * scale
     assert np.all(np.abs(cov - target) < tol + 1e-3 * scale.max())
     assert np.abs(samples.mean(axis=0)).max() < 5.0 * np.sqrt(np.diag(target).max() / n)
+
+
+@pytest.mark.parametrize("xi_frac", [20.0 / 21.0, 1.4])
+def test_thermal_force_has_the_law_of_the_matrix_form(oracle_lib, xi_frac):
+    """The thermal force the oracle draws from four normals against Eq. FijT
+    written out with a full matrix of independent standard increments
+    (numpy draws Z, forms (sa (sym Z - tr Z/3 1) + sb tr Z/3 1) e / sqrt dt
+    with the sigma coefficients of Sec. 2.1): the same mean and the same
+    covariance matrix, component by component."""
+    eta, kT, dt, h = 0.1, 2e-3, 1e-3, 1.5
+    xi = xi_frac * eta
+    p = _params(eta=eta, xi=xi, kBT=kT, dt=dt)
+    rng = np.random.default_rng(11)
+    e = rng.standard_normal(3)
+    e /= np.linalg.norm(e)
+    r = 0.7
+    F = oracle_lib.lucy_f(r, h)
+    ga = (20.0 * eta / 3.0 - 4.0 * xi) * F
+    gb = (17.0 * xi - 40.0 * eta / 3.0) * F
+    sa, sb = 2.0 * np.sqrt(kT * ga), 2.0 * np.sqrt(kT * gb)
+    z3 = np.zeros(3)
+    n = 40000
+    drawn = np.array([oracle_lib.pair_force(p, r * e, z3, z3, z3, z3, 1.0, 1.0, 0.0, 0.0, 8, 3, k)[3]
+                      for k in range(n)])
+    Z = rng.standard_normal((n, 3, 3))
+    S = 0.5 * (Z + np.transpose(Z, (0, 2, 1)))
+    t = np.trace(Z, axis1=1, axis2=2) / 3.0
+    D = S - t[:, None, None] * np.eye(3)
+    ref = (sa * (D @ e) + sb * t[:, None] * e) / np.sqrt(dt)
+    ca, cr = drawn.T @ drawn / n, ref.T @ ref / n
+    scale = np.sqrt(np.outer(np.diag(cr), np.diag(cr)))
+    tol = 7.0 * np.sqrt(2.0 / n) * scale  # two independent estimates
+    assert np.all(np.abs(ca - cr) < tol)
+    assert np.abs(drawn.mean(axis=0)).max() < 5.0 * np.sqrt(np.diag(cr).max() / n)
+    # the part along e carries sa^2 2/3 + sb^2 1/3, each direction across e sa^2/2
+    par = drawn @ e
+    assert abs(par.var() * dt / (sa * sa * 2.0 / 3.0 + sb * sb / 3.0) - 1.0) < 5.0 * np.sqrt(2.0 / n)
