@@ -262,7 +262,14 @@ __device__ __forceinline__ void stencil_row_zy(const Geo& B, const Grid& G, int 
         x0 = 0;
         xn = nx;
       } else {
-        x0 = ((x0 % nx) + nx) % nx;
+        // x0 lies within two box lengths of the box (a sheared image row
+        // starts at most one length away): wrap by additions, which cost a
+        // fraction of an integer modulo; the modulo stays for anything else
+        if (x0 < 0) x0 += nx;
+        if (x0 < 0) x0 += nx;
+        if (x0 >= nx) x0 -= nx;
+        if (x0 >= nx) x0 -= nx;
+        if (x0 < 0 || x0 >= nx) x0 = ((x0 % nx) + nx) % nx;
       }
     }
   }
