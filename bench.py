@@ -42,22 +42,49 @@ def pair_kernel_bytes(n, n_act, nnz_act, noise):
     return n * (1 + 36) + n_act * (32 + 16 + 16 + 4 + (4 if noise else 0)) + 4 * nnz_act
 
 
+# device helpers the pair kernel calls (hashed with it; the rest of their
+# header does not change the kernel)
+PAIR_KERNEL_HELPERS = ("xcd_tid", "blk_box", "geo_of", "min_img_box", "load_pr", "philox10",
+                       "u01", "pair_normals")
+
+
+def _function_text(src, name):
+    """The definition of a __device__ function `name` in `src`, from its
+    declaration line to the brace that closes its body."""
+    import re
+    m = re.search(r"^__device__[^\n]*\b" + re.escape(name) + r"\(", src, flags=re.M)
+    if not m:
+        raise KeyError(name)
+    i = src.index("{", m.end())
+    depth = 0
+    for k in range(i, len(src)):
+        if src[k] == "{":
+            depth += 1
+        elif src[k] == "}":
+            depth -= 1
+            if depth == 0:
+                return src[m.start():k + 1]
+    raise KeyError(name)
+
+
 def pair_kernel_sha256():
     """Hash of what the pair kernel is made of: its own source (the pair-force
     section of sdpdem_neighbors.hip to the end of its launcher), the device
-    helpers it calls (sdpdem_device.h) and the pair record it loads.  Counter
-    figures taken with other sources are not used."""
+    helpers it calls and the pair record it loads.  Counter figures taken
+    with other sources are not used."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2002_03120_amd", "csrc")
     nb = open(os.path.join(csrc, "sdpdem_neighbors.hip")).read()
     a = nb.index("// (a5) SDPD+a pair forces")
     b = nb.index("}  // namespace sdpdem", a)
+    dev = open(os.path.join(csrc, "sdpdem_device.h")).read()
     internal = open(os.path.join(csrc, "sdpdem_internal.h")).read()
     c = internal.index("struct __align__(64) PR {")
     e = internal.index("static_assert(sizeof(PR)", c)
     h = hashlib.sha256()
     h.update(nb[a:b].encode())
-    h.update(open(os.path.join(csrc, "sdpdem_device.h"), "rb").read())
+    for name in PAIR_KERNEL_HELPERS:
+        h.update(_function_text(dev, name).encode())
     h.update(internal[c:e].encode())
     return h.hexdigest()
 
