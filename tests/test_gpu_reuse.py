@@ -154,3 +154,13 @@ def test_batch_of_boxes_with_reuse(S, oracle_lib):
         err = np.linalg.norm(fs[off:off + n] - o.read_field("F_SDPD"), axis=1)
         assert np.all(err <= 1e-5 * sc + 1e-30)
         off += n
+
+
+def test_candidate_overflow_is_reported(S):
+    """Rows too short for the partners (18 within h on this lattice) and for
+    the candidates within h + skin (56): the candidate search reports the
+    neighbour overflow instead of writing past a row."""
+    p, parts, _ = W.reverse_poiseuille(n_side=(10, 10, 10), kBT=1e-3)
+    print("[case] candidate rows of max_neighbors 8 x ((h + skin)/h)^3", flush=True)
+    g = S.System(dict(p, skin=0.75, max_neighbors=8), parts)
+    assert g.step(1, check=False) == S.E_NBR_OVERFLOW

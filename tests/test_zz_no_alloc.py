@@ -55,6 +55,16 @@ def test_static_matches_workspace_twice_second_smaller(S):
     _compare(S, p2, parts2, 3, "reverse Poiseuille 9^3 (smaller)")
 
 
+def test_static_with_candidate_reuse(S):
+    """With a skin the allocation-free system reads the moved flag through a
+    synchronised copy instead of a pinned word; it searches at the same
+    steps and matches the workspace system bit for bit."""
+    p, parts, _ = W.dam_break(tank=(24, 12, 20), column=(12, 12, 12), n_rigid=12, seed=4,
+                              kBT=1e-4)
+    parts = W.perturb(parts, p, jitter=0.1, kT=4e-2, seed=5, spin=True)
+    _compare(S, dict(p, skin=0.3), parts, 40, "dam break 24x12x20 with skin 0.3, 40 steps")
+
+
 def test_static_refuses_oversize(S):
     p, parts, _ = W.reverse_poiseuille(n_side=(64, 64, 64), kBT=0.0)
     need = S.sdpdem_workspace_bytes(p, parts)
