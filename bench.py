@@ -273,6 +273,8 @@ def scale_leg(steps, cell_factor, warmup=2):
             "instr_per_slot": prof["valu_lane_instr_per_slot"],
             # measured HBM bytes per launch (FETCH_SIZE, WRITE_SIZE), profiles/
             "traffic": round(prof["traffic_bytes_per_launch"]),
+            "hbm_frac_from_traffic": round(prof["traffic_bytes_per_launch"] / k_avg_s / 1e9
+                                           / HBM_PEAK_GBS, 4),
             "slots_per_launch": nnz, "avg_launch_ms": round(k_avg_s * 1e3, 4),
             "valu_busy_counter": prof.get("valu_busy"),
         }
@@ -519,6 +521,12 @@ def main():
     if prof:
         roof["valu_busy"] = prof["valu_busy"]
         roof["valu_lane_use"] = prof["lane_use"]
+    if prof:
+        # the same fraction from the measured HBM bytes of the counter
+        # profile (re-fetched partner records included) instead of the
+        # algorithmic ones
+        roof["frac_from_traffic"] = round(prof["traffic_bytes_per_launch"] / k_avg_s / 1e9
+                                          / HBM_PEAK_GBS, 4)
     if peaks and peaks["copy_bytes_per_s"] > 0:
         roof["frac_of_measured_copy"] = round(achieved * 1e9 / peaks["copy_bytes_per_s"], 4)
     tot = sysm.totals()
