@@ -1,7 +1,7 @@
 """Parity at the full sizes of the measured workloads, in the launch
-configurations the benchmark uses (dam break: fluid cells of 0.55 h and
-neighbour-candidate reuse with skin h/15; scale box and viscometer: cells
-of h/2) and at cells of h: the sedimentation box (101,080 particles), the
+configurations the benchmark uses (fluid cells of 0.55 h, the dam break
+also with neighbour-candidate reuse at skin h/15; the viscometer batch at
+0.67 h, its tuner's pick) and at cells of h: the sedimentation box (101,080 particles), the
 dam break (1,534,168 particles, 2^20 moving) and the periodic scale box
 (8,388,608 particles).  The oracle evaluates every particle here; neighbour
 sets must match bit for bit."""
@@ -26,7 +26,7 @@ def S():
 
 @pytest.mark.parametrize("name,cf", [("sedimentation", 0.5), ("sedimentation", 1.0),
                                      ("dam_break", 0.55), ("dam_break", 1.0),
-                                     ("periodic_scale", 0.5)])
+                                     ("periodic_scale", 0.55)])
 def test_full_size_single_step(S, oracle_lib, name, cf):
     p, parts, info = W.CONFIGS[name]()
     parts = W.perturb(parts, p, jitter=0.05, kT=1e-4, seed=7)
@@ -58,14 +58,14 @@ def test_full_dam_break_after_steps_with_reuse(S, oracle_lib):
 
 def test_full_viscometer_batch_sampled_boxes(S, oracle_lib):
     """The bench's batched viscometer (256 Lees-Edwards cells, 7,272,566
-    particles, cells of h/2): one force evaluation of the whole batch, and
+    particles, cells of 0.67 h): one force evaluation of the whole batch, and
     six of its boxes (the smallest, the largest and four drawn at random)
     evaluated one by one by the oracle; their rows must match the oracle's
     neighbours bit for bit and its force fields within the tolerances."""
     shared, cells = W.viscometer_batch(256, seed=0, steps=5000)
     parts, boxes, box_of = W.stack_cells(cells)
     print(f"[case] full viscometer batch n={parts['id'].shape[0]}", flush=True)
-    g = S.System(dict(shared, cell_factor=0.5), parts, boxes=boxes, box_of=box_of)
+    g = S.System(dict(shared, cell_factor=0.67), parts, boxes=boxes, box_of=box_of)
     assert g.compute_forces(check=False) == 0
     rows, cols = g.read_neighbors()  # CSR: row starts (n + 1) and columns
     fields = {f: g.read_field(f) for f in VECTOR_FIELDS}
