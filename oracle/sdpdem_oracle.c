@@ -25,12 +25,13 @@
  *      that makes the ideal cubic lattice give rho0 exactly.
  *  R5  Pressure filtering = Shepard (W-weighted) mean, self included.
  *  R6  dW^S = (dW + dW^T)/2 - tr(dW)/3 * 1 (Eq. reldWij is garbled), the
- *      trace term of Eq. FijT multiplies the identity; dW = sqrt(dt) zeta.
- *      Only sym(dW) enters, so its six independent entries are drawn
- *      directly: diagonal N(0,1), off-diagonal N(0,1/2) (the law of
- *      (zeta_ab + zeta_ba)/2 for independent standard zeta).
+ *      trace term of Eq. FijT multiplies the identity; dW = sqrt(dt) zeta
+ *      with zeta a matrix of independent standard normals.  The matrix
+ *      enters only through (sa dW^S + sb tr(dW)/3 1) e, a Gaussian vector
+ *      whose law depends on e alone, so that vector is drawn from four
+ *      normals (see oracle_pair_force).
  *  R7  Noise comes from Philox4x32-10 keyed by the seed with counter
- *      (min id, max id, step, block); one draw per pair per step, used by
+ *      (min id, max id, step, 0); one block per pair per step, used by
  *      both velocity-Verlet passes, so the per-step variance is sigma^2 dt.
  *  R8  Torque lever: dx/2 for fluid, R for rigid, along -e_ij (Sec. 2.6).
  *  R9  Inner walls: position fixed, velocity and spin updated like fluid.
@@ -69,6 +70,12 @@
  *      (fluid on rigid or outer wall) counted once; the fluid-particle
  *      coupling of sphere s counts M_s,a (F^DG_s + F^PG_s)_b with the lever
  *      M_s = sum_j w_sj r_sj / Omega_s.  Body forces are external.
+ *
+ * Parity unpinned (nothing outside this file fixes them): the Shepard mean
+ * of R5 beyond its own properties (a weighted mean of the neighbours'
+ * pressures that reproduces a constant field); the history rules of R11
+ * beyond the stick and slide cases; the lubrication of R12 between spheres
+ * of unequal radii (only the equal-sphere squeeze film is pinned).
  */
 #include "sdpdem_oracle.h"
 

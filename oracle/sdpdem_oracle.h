@@ -18,6 +18,12 @@
  * Every reading taken where the paper is silent or garbled is stated
  * beside the code that implements it.
  *
+ * Parity unpinned: the pressure filter (a Shepard mean, pinned only by its
+ * own properties, since the paper gives no formula), the tangential
+ * history rules beyond the stick and slide cases, and lubrication between
+ * spheres of unequal radii.  Everything else is checked by the tests
+ * against closed forms, brute force, invariants or the paper's values.
+ *
  * Conventions: host memory only, synchronous, every array in id order
  * (the ids must be a permutation of 0..n-1).  Return 0 on success and a
  * negative ORACLE_E_* code on failure.
