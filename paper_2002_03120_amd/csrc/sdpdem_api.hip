@@ -218,6 +218,7 @@ struct Sizes {
   int64_t ncells_all = 0, rncells_all = 0;
   std::vector<BoxD> boxes;
   std::vector<int2> blk;       // launch blocks (box, first sorted index)
+  int blk_per = 1;             // launch blocks per chunk (logical_block)
   std::vector<int> rbox;       // box of every rigid slot
   std::vector<int64_t> order;  // initial sorted position -> input row
 };
@@ -460,7 +461,15 @@ bool plan(const sdpdem_params* P, const sdpdem_box* boxes, int nbox,
       z.blk.push_back(make_int2(b, B.first + c * BS));
     for (int64_t k : r) z.order.push_back(k);
   }
-  while (z.blk.size() < 8 || z.blk.size() % 8) z.blk.push_back(make_int2(-1, 0));
+  // XCD x runs launch blocks x, x + 8, x + 16, ...; they take chunks x,
+  // x + 8, ... of about a dozen consecutive table entries (logical_block),
+  // so that every XCD gets a share of each region of the sorted order (a
+  // region without work, such as the walls above a dam break's water, no
+  // longer leaves one XCD idle) while a chunk's neighbourhood stays in its
+  // XCD's L2.  The table is padded to whole rounds of chunks.
+  const size_t m = std::max<size_t>(1, std::min<size_t>(64, z.blk.size() / (8 * 12)));
+  while (z.blk.size() < 8 * m || z.blk.size() % (8 * m)) z.blk.push_back(make_int2(-1, 0));
+  z.blk_per = (int)(z.blk.size() / (8 * m));
   z.ncells_all = coff;
   z.rncells_all = rcoff;
   if (slot_of) *slot_of = slots;
@@ -491,6 +500,7 @@ void fill_constants(sdpdem_system* s, const Sizes& z) {
   d.maxc = z.maxc;
   d.nbox = z.nbox;
   d.nblk = (int)z.blk.size();
+  d.blk_per = z.blk_per;
   d.ncells_all = (int)z.ncells_all;
   d.rncells_all = (int)z.rncells_all;
   d.have_rxn = 0;

@@ -29,12 +29,22 @@ __device__ __forceinline__ int xcd_wave() {
   return (int)((lb * blockDim.x + threadIdx.x) >> 6);
 }
 
+// The launch-table entry of this block.  Block b runs on XCD b % 8 as that
+// XCD's (b / 8)-th block; the XCD takes chunks x, x + 8, x + 16, ... of
+// blk_per consecutive entries: a chunk's particles (and most of their
+// neighbours) share an L2, and each XCD's chunks spread over the whole
+// sorted order, so that uneven work (walls without pair work in one region
+// of the box) lands on every XCD alike.
+__device__ __forceinline__ unsigned logical_block(const Dev& d) {
+  const unsigned b = blockIdx.x, per = (unsigned)d.blk_per;
+  const unsigned k = b / 8u;
+  return ((k / per) * 8u + b % 8u) * per + k % per;
+}
+
 // Launch block -> (box, first sorted particle): the box is uniform over a
-// block, so its constants are scalar loads.  Blocks are taken in XCD order
-// (block b runs on XCD b % 8; each XCD gets a contiguous run of the table).
+// block, so its constants are scalar loads.
 __device__ __forceinline__ int blk_box(const Dev& d, int& i) {
-  unsigned nb = gridDim.x, b = blockIdx.x;
-  unsigned lb = (nb % 8u == 0u) ? (b % 8u) * (nb / 8u) + (b / 8u) : b;
+  const unsigned lb = logical_block(d);
   const int2 e = d.blk[lb];
   i = e.y + (int)threadIdx.x;
   return __builtin_amdgcn_readfirstlane(e.x);

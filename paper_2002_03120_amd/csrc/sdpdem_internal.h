@@ -126,7 +126,8 @@ struct Dev {
   int ncells_all, rncells_all;  // cells of all boxes
   const BoxD* boxes;
   const int2* blk;   // per launch block: (box, first sorted index); box -1 = idle
-  int nblk;          // a multiple of 8
+  int nblk;          // launch blocks: 8 x whole numbers of chunks
+  int blk_per;       // launch blocks per chunk
   const int* rbox;   // box of every rigid slot
   // particles (current buffer)
   D4* pos;  // x, y, z, radius (lever for fluid and walls)

@@ -1141,8 +1141,7 @@ void launch_integrate(const Dev& d, int velver, int rigid_active, bool end_step,
 // so a box gives the same bits alone or in a batch.
 __global__ __launch_bounds__(BS) void k_box_stress_part(Dev d, int rigid_active) {
   __shared__ double sh[BS];
-  const unsigned nb = gridDim.x, bb = blockIdx.x;
-  const unsigned lb = (nb % 8u == 0u) ? (bb % 8u) * (nb / 8u) + (bb / 8u) : bb;
+  const unsigned lb = logical_block(d);
   int i;
   const int b = blk_box(d, i);
   double q = 0.0;
