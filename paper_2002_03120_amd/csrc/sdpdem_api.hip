@@ -219,6 +219,8 @@ struct Sizes {
   std::vector<BoxD> boxes;
   std::vector<int2> blk;       // launch blocks (box, first sorted index)
   int blk_per = 1;             // launch blocks per chunk (logical_block)
+  std::vector<int2> ablk;      // the same over the boxes' active parts
+  int ablk_per = 1;
   std::vector<int> rbox;       // box of every rigid slot
   std::vector<int64_t> order;  // initial sorted position -> input row
 };
@@ -263,6 +265,7 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
   double* wzx_r = b.take<double>(2 * nr);
   BoxD* boxes = b.take<BoxD>((size_t)z.nbox);
   int2* blk = b.take<int2>(z.blk.size());
+  int2* ablk = b.take<int2>(z.ablk.size());
   int* rbox = b.take<int>(nr);
   double* st_inst = b.take<double>((size_t)z.nbox);
   double* st_part = b.take<double>(z.blk.size());
@@ -344,6 +347,7 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
     s->boxes = boxes;
     d.boxes = boxes;
     d.blk = blk;
+    d.ablk = ablk;
     d.rbox = rbox;
     d.st_inst = st_inst;
     d.st_part = st_part;
@@ -367,6 +371,17 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
     d.dstep = dstep;
   }
   return total;
+}
+
+// XCD x runs launch blocks x, x + 8, x + 16, ...; logical_block gives it
+// chunks x, x + 8, ... of about a dozen consecutive table entries, so that
+// every XCD gets a share of each region of the sorted order while a
+// chunk's neighbourhood stays in its XCD's L2.  Pads the table with idle
+// entries to whole rounds of chunks; returns the chunk length.
+int pad_chunks(std::vector<int2>& t) {
+  const size_t m = std::max<size_t>(1, std::min<size_t>(64, t.size() / (8 * 12)));
+  while (t.size() < 8 * m || t.size() % (8 * m)) t.push_back(make_int2(-1, 0));
+  return (int)(t.size() / (8 * m));
 }
 
 bool plan(const sdpdem_params* P, const sdpdem_box* boxes, int nbox,
@@ -401,6 +416,7 @@ bool plan(const sdpdem_params* P, const sdpdem_box* boxes, int nbox,
   z.nbox = nbox;
   z.boxes.assign((size_t)nbox, BoxD{});
   z.blk.clear();
+  z.ablk.clear();
   z.rbox.assign((size_t)nr, 0);
   z.order.clear();
   z.order.reserve((size_t)n);
@@ -408,8 +424,13 @@ bool plan(const sdpdem_params* P, const sdpdem_box* boxes, int nbox,
   for (int b = 0; b < nbox; ++b) {
     const sdpdem_box& hb = boxes[b];
     auto& r = rows[(size_t)b];
-    // ids ascending inside a box: the initial order before the first sort
-    std::sort(r.begin(), r.end(), [&](int64_t a, int64_t c) { return q->id[a] < q->id[c]; });
+    // the initial order before the first sort: the particles that move or
+    // feel forces, then the outer walls, ids ascending in each part (the
+    // sort keeps the outer walls behind, in cells of their own)
+    std::sort(r.begin(), r.end(), [&](int64_t a, int64_t c) {
+      const bool wa = q->type[a] == SDPDEM_OUTER_WALL, wc = q->type[c] == SDPDEM_OUTER_WALL;
+      return wa != wc ? wc : q->id[a] < q->id[c];
+    });
     double rmax = 0.0;
     for (int64_t k : r)
       if (q->type[k] == SDPDEM_RIGID) {
@@ -441,9 +462,13 @@ bool plan(const sdpdem_params* P, const sdpdem_box* boxes, int nbox,
     B.dem_reach = std::max(1, (int)std::ceil((2.0 * rmax + P->h) / mincs * (1.0 + 1e-9)));
     B.couple_R = rmax + P->h;
     B.dem_R = 2.0 * rmax + P->h;
+    int64_t nact = 0;
+    for (int64_t k : r) nact += q->type[k] != SDPDEM_OUTER_WALL;
+    B.nact = (int)nact;
+    B.wall_off = nact < (int64_t)r.size() ? B.g.ncells : 0;
     B.cell_off = (int)coff;
     B.rcell_off = (int)rcoff;
-    coff += B.g.ncells;
+    coff += B.g.ncells + B.wall_off;
     rcoff += B.rg.ncells;
     if (coff > (int64_t)1 << 30 || rcoff > (int64_t)1 << 30) return false;
     B.first = (int)first;
@@ -459,17 +484,12 @@ bool plan(const sdpdem_params* P, const sdpdem_box* boxes, int nbox,
     B.blk_first = (int)z.blk.size();
     for (int c = 0; c < (B.count + BS - 1) / BS; ++c)
       z.blk.push_back(make_int2(b, B.first + c * BS));
+    for (int c = 0; c < (B.nact + BS - 1) / BS; ++c)
+      z.ablk.push_back(make_int2(b, B.first + c * BS));
     for (int64_t k : r) z.order.push_back(k);
   }
-  // XCD x runs launch blocks x, x + 8, x + 16, ...; they take chunks x,
-  // x + 8, ... of about a dozen consecutive table entries (logical_block),
-  // so that every XCD gets a share of each region of the sorted order (a
-  // region without work, such as the walls above a dam break's water, no
-  // longer leaves one XCD idle) while a chunk's neighbourhood stays in its
-  // XCD's L2.  The table is padded to whole rounds of chunks.
-  const size_t m = std::max<size_t>(1, std::min<size_t>(64, z.blk.size() / (8 * 12)));
-  while (z.blk.size() < 8 * m || z.blk.size() % (8 * m)) z.blk.push_back(make_int2(-1, 0));
-  z.blk_per = (int)(z.blk.size() / (8 * m));
+  z.blk_per = pad_chunks(z.blk);
+  z.ablk_per = pad_chunks(z.ablk);
   z.ncells_all = coff;
   z.rncells_all = rcoff;
   if (slot_of) *slot_of = slots;
@@ -501,6 +521,8 @@ void fill_constants(sdpdem_system* s, const Sizes& z) {
   d.nbox = z.nbox;
   d.nblk = (int)z.blk.size();
   d.blk_per = z.blk_per;
+  d.nablk = (int)z.ablk.size();
+  d.ablk_per = z.ablk_per;
   d.ncells_all = (int)z.ncells_all;
   d.rncells_all = (int)z.rncells_all;
   d.have_rxn = 0;
@@ -749,7 +771,7 @@ void run_build(sdpdem_system* s, hipStream_t st, int commit_next, int lists = LI
   }
   {
     Prof pr(s, SDPDEM_K_SMOOTH, st);
-    launch_smooth(d, st);
+    launch_smooth(d, search, st);
   }
   if (fk) {
     if (s->rigid_issued)
@@ -931,6 +953,8 @@ int create_impl(const sdpdem_params* params, const sdpdem_box* boxes, int nbox,
   ok &= hipMemcpyAsync(d.gid2slot, slot_of.data(), sizeof(int) * n, hipMemcpyHostToDevice, st) == hipSuccess;
   ok &= hipMemcpyAsync(s->boxes, z.boxes.data(), sizeof(BoxD) * z.nbox, hipMemcpyHostToDevice, st) == hipSuccess;
   ok &= hipMemcpyAsync(const_cast<int2*>(d.blk), z.blk.data(), sizeof(int2) * z.blk.size(),
+                       hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipMemcpyAsync(const_cast<int2*>(d.ablk), z.ablk.data(), sizeof(int2) * z.ablk.size(),
                        hipMemcpyHostToDevice, st) == hipSuccess;
   {
     const int64_t step0 = params->itr_start;

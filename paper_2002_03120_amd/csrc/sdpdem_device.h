@@ -35,17 +35,22 @@ __device__ __forceinline__ int xcd_wave() {
 // neighbours) share an L2, and each XCD's chunks spread over the whole
 // sorted order, so that uneven work (walls without pair work in one region
 // of the box) lands on every XCD alike.
+template <bool ACT = false>
 __device__ __forceinline__ unsigned logical_block(const Dev& d) {
-  const unsigned b = blockIdx.x, per = (unsigned)d.blk_per;
+  const unsigned b = blockIdx.x, per = (unsigned)(ACT ? d.ablk_per : d.blk_per);
   const unsigned k = b / 8u;
   return ((k / per) * 8u + b % 8u) * per + k % per;
 }
 
 // Launch block -> (box, first sorted particle): the box is uniform over a
-// block, so its constants are scalar loads.
+// block, so its constants are scalar loads.  ACT: the table of the boxes'
+// active parts (launched with nablk blocks); its last block of a box may
+// reach into the box's outer walls, which every kernel skips or gives
+// their fixed values.
+template <bool ACT = false>
 __device__ __forceinline__ int blk_box(const Dev& d, int& i) {
-  const unsigned lb = logical_block(d);
-  const int2 e = d.blk[lb];
+  const unsigned lb = logical_block<ACT>(d);
+  const int2 e = ACT ? d.ablk[lb] : d.blk[lb];
   i = e.y + (int)threadIdx.x;
   return __builtin_amdgcn_readfirstlane(e.x);
 }

@@ -78,6 +78,8 @@ struct BoxD {
   int le;             // shear != 0
   int cell_off, rcell_off;
   int first, count;   // sorted particle range
+  int nact;           // its first nact particles move or feel forces; the rest are outer walls
+  int wall_off;       // outer walls bin into cells cell_off + wall_off + c (0: the box has none)
   int blk_first;      // the box's first entry in the launch-block table
   int dem_reach;      // rigid-grid cells to search for DEM partners
   double couple_R;    // R_max + h: coupling partners lie within it
@@ -128,6 +130,8 @@ struct Dev {
   const int2* blk;   // per launch block: (box, first sorted index); box -1 = idle
   int nblk;          // launch blocks: 8 x whole numbers of chunks
   int blk_per;       // launch blocks per chunk
+  const int2* ablk;  // the same over the boxes' active parts (outer walls left out)
+  int nablk, ablk_per;
   const int* rbox;   // box of every rigid slot
   // particles (current buffer)
   D4* pos;  // x, y, z, radius (lever for fluid and walls)
@@ -239,7 +243,7 @@ void launch_filter_density(const Dev& d, hipStream_t st);
 void launch_pass_prep(const Dev& d, BoxD* boxes, int add, bool clear_rxn, hipStream_t st);
 // per-box sample of P_zx; with accumulate, also added to the running sums
 void launch_box_stress(const Dev& d, int accumulate, hipStream_t st);
-void launch_smooth(const Dev& d, hipStream_t st);
+void launch_smooth(const Dev& d, bool all, hipStream_t st);
 // with t0 and t1, the launch records the two timing events itself
 void launch_fluid_forces(const Dev& d, bool noise, hipStream_t st, hipEvent_t t0 = nullptr,
                          hipEvent_t t1 = nullptr);

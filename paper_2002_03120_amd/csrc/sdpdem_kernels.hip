@@ -78,7 +78,9 @@ __global__ __launch_bounds__(BS) void k_bin(Dev d) {
   int cy = cell_coord(p.y, B.g, 1, &oob);
   int cz = cell_coord(p.z, B.g, 2, &oob);
   if (oob) atomicOr(d.status, ST_OUT_OF_DOMAIN);
-  int c = B.cell_off + cell_index(B.g, cx, cy, cz);
+  // outer walls take the box's second range of cells: the sort then keeps
+  // them after the box's active particles, in a fixed order
+  const int c = B.cell_off + (d.type[i] == T_OUTER ? B.wall_off : 0) + cell_index(B.g, cx, cy, cz);
   d.key[i] = (uint32_t)c;
   // the arrival order in the cell places the particle in the scatter (the
   // cell sort then fixes the order inside the cell)
@@ -724,7 +726,7 @@ __device__ __forceinline__ void reaction_of(const Dev& d, const BoxD& B, int i, 
 
 __global__ __launch_bounds__(BS) void k_fpi_reaction(Dev d) {
   int i;
-  const int b = blk_box(d, i);
+  const int b = blk_box<true>(d, i);
   if (b < 0) return;
   const BoxD& B = d.boxes[b];
   if (i >= B.first + B.count) return;
@@ -737,7 +739,7 @@ __global__ __launch_bounds__(BS) void k_fpi_reaction(Dev d) {
 }
 
 void launch_fpi_reaction(const Dev& d, hipStream_t st) {
-  k_fpi_reaction<<<d.nblk, BS, 0, st>>>(d);
+  k_fpi_reaction<<<d.nablk, BS, 0, st>>>(d);
 }
 
 // ---------------------------------------------------------------------------
@@ -1015,7 +1017,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
   // this launch reads it)
   if (end_step && blockIdx.x == 0 && threadIdx.x == 0) d.dstep[0] += 1;
   int i;
-  const int b = blk_box(d, i);
+  const int b = blk_box<true>(d, i);
   if (b < 0) return;
   const BoxD& B = d.boxes[b];
   if (i >= B.first + B.count) return;
@@ -1124,7 +1126,7 @@ void launch_integrate(const Dev& d, int velver, int rigid_active, bool end_step,
   auto k = velver == 2 ? (fuse_rxn ? k_integrate<2, true> : k_integrate<2, false>)
            : track_moved ? (fuse_rxn ? k_integrate<1, true, true> : k_integrate<1, false, true>)
                        : (fuse_rxn ? k_integrate<1, true> : k_integrate<1, false>);
-  k<<<d.nblk, BS, 0, st>>>(d, rigid_active, end_step ? 1 : 0);
+  k<<<d.nablk, BS, 0, st>>>(d, rigid_active, end_step ? 1 : 0);
 }
 
 // ---------------------------------------------------------------------------

@@ -66,7 +66,7 @@ __device__ __forceinline__ void build_density(const Dev& d) {
   const size_t npad = (size_t)d.npad;
   int* const nb = d.nbr + i;
   int* const cb = CAND ? d.cand + i : nullptr;
-  auto run = [&](int k0, int k1) {
+  auto cells = [&](int k0, int k1) {
     const int jb = d.cstart[k0];
     const int je = d.cstart[k1];
     for (int j = jb; j < je; ++j) {
@@ -88,6 +88,12 @@ __device__ __forceinline__ void build_density(const Dev& d) {
         }
       }
     }
+  };
+  // a run of cells, then the outer walls binned in the same cells
+  const int woff = B.wall_off;
+  auto run = [&](int k0, int k1) {
+    cells(k0, k1);
+    if (woff) cells(k0 + woff, k1 + woff);
   };
   // cells of R or more: the whole 27-cell stencil (lanes of a cell walk the
   // same runs in step); smaller cells: the rows and x cells within R only
@@ -129,7 +135,7 @@ void launch_build_density(const Dev& d, bool cand, hipStream_t st) {
 // in the search.
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_filter_density(Dev d) {
   int i;
-  const int b = blk_box(d, i);
+  const int b = blk_box<true>(d, i);
   if (b < 0) return;
   const BoxD& B = d.boxes[b];
   if (i >= B.first + B.count) return;
@@ -179,16 +185,17 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
 }
 
 void launch_filter_density(const Dev& d, hipStream_t st) {
-  k_filter_density<<<d.nblk, BS, 0, st>>>(d);
+  k_filter_density<<<d.nablk, BS, 0, st>>>(d);
 }
 
 // ---------------------------------------------------------------------------
 // (a4) Shepard filter of the pressure (weights recomputed from the FP64
 // positions) and the pair records of the force pass.
 
+template <bool ACT>
 __global__ __launch_bounds__(BS) void k_smooth(Dev d) {
   int i;
-  const int b = blk_box(d, i);
+  const int b = blk_box<ACT>(d, i);
   if (b < 0) return;
   const BoxD& B = d.boxes[b];
   if (i >= B.first + B.count) return;
@@ -236,8 +243,13 @@ __global__ __launch_bounds__(BS) void k_smooth(Dev d) {
   d.prec[i] = r;
 }
 
-void launch_smooth(const Dev& d, hipStream_t st) {
-  k_smooth<<<d.nblk, BS, 0, st>>>(d);
+// after a search over every particle (the outer walls' records too: the
+// sort may have moved them), after a candidate filter over the active parts
+void launch_smooth(const Dev& d, bool all, hipStream_t st) {
+  if (all)
+    k_smooth<false><<<d.nblk, BS, 0, st>>>(d);
+  else
+    k_smooth<true><<<d.nablk, BS, 0, st>>>(d);
 }
 
 // ---------------------------------------------------------------------------
@@ -248,7 +260,7 @@ void launch_smooth(const Dev& d, hipStream_t st) {
 template <bool NOISE, bool STRESS>
 __global__ __launch_bounds__(BS) void k_fluid_forces(Dev d) {
   int i;
-  const int b = blk_box(d, i);
+  const int b = blk_box<true>(d, i);
   if (b < 0) return;
   const BoxD& B = d.boxes[b];
   if (i >= B.first + B.count) return;
@@ -385,11 +397,11 @@ void launch_fluid_forces(const Dev& d, bool noise, hipStream_t st, hipEvent_t t0
     // the kernel, which would stall the stream)
     Dev arg = d;
     void* args[] = {&arg};
-    if (hipExtLaunchKernel(reinterpret_cast<const void*>(k), dim3(d.nblk), dim3(BS), args, 0, st,
+    if (hipExtLaunchKernel(reinterpret_cast<const void*>(k), dim3(d.nablk), dim3(BS), args, 0, st,
                            t0, t1, 0) == hipSuccess)
       return;
   }
-  k<<<d.nblk, BS, 0, st>>>(d);
+  k<<<d.nablk, BS, 0, st>>>(d);
 }
 
 // neighbour columns k0..k0+kn-1 as ids (-1 past a row's end), for export
