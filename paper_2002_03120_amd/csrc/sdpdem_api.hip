@@ -374,12 +374,11 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
 }
 
 // XCD x runs launch blocks x, x + 8, x + 16, ...; logical_block gives it
-// chunks x, x + 8, ... of about a dozen consecutive table entries, so that
-// every XCD gets a share of each region of the sorted order while a
-// chunk's neighbourhood stays in its XCD's L2.  Pads the table with idle
+// chunks x, x + 8, ... of consecutive table entries, at most max_chunks per
+// XCD and at least about a dozen entries long.  Pads the table with idle
 // entries to whole rounds of chunks; returns the chunk length.
-int pad_chunks(std::vector<int2>& t) {
-  const size_t m = std::max<size_t>(1, std::min<size_t>(64, t.size() / (8 * 12)));
+int pad_chunks(std::vector<int2>& t, size_t max_chunks) {
+  const size_t m = std::max<size_t>(1, std::min<size_t>(max_chunks, t.size() / (8 * 12)));
   while (t.size() < 8 * m || t.size() % (8 * m)) t.push_back(make_int2(-1, 0));
   return (int)(t.size() / (8 * m));
 }
@@ -488,8 +487,12 @@ bool plan(const sdpdem_params* P, const sdpdem_box* boxes, int nbox,
       z.ablk.push_back(make_int2(b, B.first + c * BS));
     for (int64_t k : r) z.order.push_back(k);
   }
-  z.blk_per = pad_chunks(z.blk);
-  z.ablk_per = pad_chunks(z.ablk);
+  // The full table (searches, binning) holds regions without work, such as
+  // the outer walls above a dam break's water: interleaved chunks give
+  // every XCD a share of each.  The active table has work everywhere: one
+  // contiguous eighth per XCD keeps each neighbourhood in one L2.
+  z.blk_per = pad_chunks(z.blk, 64);
+  z.ablk_per = pad_chunks(z.ablk, 1);
   z.ncells_all = coff;
   z.rncells_all = rcoff;
   if (slot_of) *slot_of = slots;
