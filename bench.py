@@ -44,8 +44,8 @@ def pair_kernel_bytes(n, n_act, nnz_act, noise):
 
 # device helpers the pair kernel calls (hashed with it; the rest of their
 # header does not change the kernel)
-PAIR_KERNEL_HELPERS = ("xcd_tid", "logical_block", "blk_box", "geo_of", "min_img_box", "load_pr",
-                       "philox10", "u01", "pair_normals")
+PAIR_KERNEL_HELPERS = ("xcd_tid", "logical_block", "blk_box", "geo_of", "min_img_box",
+                       "min_img_fast", "load_pr", "philox10", "u01", "pair_normals")
 
 
 def _function_text(src, name):

@@ -85,6 +85,7 @@ __device__ __forceinline__ Geo geo_of(const BoxD& B) {
   for (int a = 0; a < 3; ++a) {
     g.L[a] = B.L[a];
     g.halfL[a] = B.halfL[a];
+    g.lim[a] = B.per[a] ? B.halfL[a] : __builtin_inf();
     g.per[a] = B.per[a];
   }
   g.inv_Lx = 1.0 / B.L[0];
@@ -118,6 +119,22 @@ __device__ __forceinline__ int min_img_box(const Geo& B, double& ex, double& ey,
   }
   ey = min_img(ey, B.per[1], B.L[1], B.halfL[1]);
   return kz;
+}
+
+// min_img_box with a shortcut.  Within half the box on every periodic axis
+// a separation is already its minimum image, with no z image: min_img_box
+// would return it bit for bit (its x rint at exactly half the box could
+// pick the other, equally near image, which lies beyond every cut-off).
+// That holds for all pairs away from the periodic seams, and three
+// compares replace the image arithmetic there; boxes without a periodic
+// axis skip both (a test uniform over the launch block).  Used where the
+// image arithmetic costs issue slots (the searches and filters, the
+// thermal pair kernel); in the gather-bound deterministic pair loop the
+// plain form schedules its loads better.
+__device__ __forceinline__ int min_img_fast(const Geo& B, double& ex, double& ey, double& ez) {
+  if (!(B.per[0] | B.per[1] | B.per[2])) return 0;
+  if (fabs(ex) <= B.lim[0] && fabs(ey) <= B.lim[1] && fabs(ez) <= B.lim[2]) return 0;
+  return min_img_box(B, ex, ey, ez);
 }
 
 __device__ __forceinline__ int cell_coord(double x, const Grid& g, int a, int* oob) {

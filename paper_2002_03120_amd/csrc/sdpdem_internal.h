@@ -94,6 +94,7 @@ struct BoxD {
 // thread (the box table itself could alias the loops' stores).
 struct Geo {
   double L[3], halfL[3];
+  double lim[3];  // halfL on a periodic axis, infinite on a wall axis
   double inv_Lx;  // 1 / L_x: the sheared x image without a division
   double le_shift, le_jump;
   int per[3];

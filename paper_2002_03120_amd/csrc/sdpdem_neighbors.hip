@@ -72,7 +72,7 @@ __device__ __forceinline__ void build_density(const Dev& d) {
     for (int j = jb; j < je; ++j) {
       const D4 pj = d.pos[j];
       double ex = pi.x - pj.x, ey = pi.y - pj.y, ez = pi.z - pj.z;
-      min_img_box(G, ex, ey, ez);
+      min_img_fast(G, ex, ey, ez);
       const double r2 = r2_exact(ex, ey, ez);
       if (r2 < R2 && j != i) {
         if (CAND) {
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
     pn = d.pos[jn];
     jnn = k + 2 < cc ? cb[(size_t)(k + 2) * npad] : i;
     double ex = pi.x - pj.x, ey = pi.y - pj.y, ez = pi.z - pj.z;
-    min_img_box(G, ex, ey, ez);
+    min_img_fast(G, ex, ey, ez);
     const double r2 = r2_exact(ex, ey, ez);
     if (r2 < h2) {
       const double q = sqrt_nr(r2) * inv_h;
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(BS) void k_smooth(Dev d) {
       const int j = nb[(size_t)k * npad];
       const D4 xj = d.xp[j];  // one 32-byte record: position and pressure
       double ex = x.x - xj.x, ey = x.y - xj.y, ez = x.z - xj.z;
-      min_img_box(G, ex, ey, ez);
+      min_img_fast(G, ex, ey, ez);
       const double q = sqrt_nr(r2_exact(ex, ey, ez)) * inv_h;
       const double om = fmax(1.0 - q, 0.0);
       const double w = d.w_norm * (1.0 + 3.0 * q) * om * om * om;
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(BS) void k_fluid_forces(Dev d) {
       const PR rj = load_pr(d.prec, jn);
       jn = k + 1 < cnt ? nb[(size_t)(k + 1) * npad] : i;
       double dx_ = ri.x - rj.x, dy_ = ri.y - rj.y, dz_ = ri.z - rj.z;
-      const int kz = min_img_box(G, dx_, dy_, dz_);
+      const int kz = NOISE ? min_img_fast(G, dx_, dy_, dz_) : min_img_box(G, dx_, dy_, dz_);
       const double r2d = dx_ * dx_ + dy_ * dy_ + dz_ * dz_;
       const float rx = (float)dx_, ry = (float)dy_, rz = (float)dz_;
       const float inv_r = __builtin_amdgcn_rsqf((float)r2d);
