@@ -32,9 +32,10 @@ __device__ __forceinline__ int xcd_wave() {
 // The launch-table entry of this block.  Block b runs on XCD b % 8 as that
 // XCD's (b / 8)-th block; the XCD takes chunks x, x + 8, x + 16, ... of
 // blk_per consecutive entries: a chunk's particles (and most of their
-// neighbours) share an L2, and each XCD's chunks spread over the whole
-// sorted order, so that uneven work (walls without pair work in one region
-// of the box) lands on every XCD alike.
+// neighbours) share an L2.  With many chunks per XCD each XCD's share
+// spreads over the whole sorted order, so that uneven work (outer walls
+// in one region of the box) lands on every XCD alike; with one chunk per
+// XCD each takes one contiguous eighth.
 template <bool ACT = false>
 __device__ __forceinline__ unsigned logical_block(const Dev& d) {
   const unsigned b = blockIdx.x, per = (unsigned)(ACT ? d.ablk_per : d.blk_per);
