@@ -1180,8 +1180,20 @@ __global__ void k_box_stress_final(Dev d, int accumulate) {
   if (b >= d.nbox) return;
   const BoxD& B = d.boxes[b];
   const int nb = (B.count + BS - 1) / BS;
+  const double* part = d.st_part + B.blk_first;
+  // the partials in block order; eight loads in flight at a time (one
+  // thread per box would otherwise wait a memory latency per block), the
+  // sum itself in the same order
   double acc = 0.0;
-  for (int c = 0; c < nb; ++c) acc += d.st_part[B.blk_first + c];
+  int c = 0;
+  for (; c + 8 <= nb; c += 8) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = part[c + k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc += v[k];
+  }
+  for (; c < nb; ++c) acc += part[c];
   const double pzx = acc / B.vol;
   d.st_inst[b] = pzx;
   if (accumulate) d.st_sum[b] += pzx;
