@@ -99,6 +99,20 @@ def test_wall_crossings_between_searches(S, oracle_lib, noslip):
     _hand_over(S, oracle_lib, g, q, parts, ["F_SDPD", "F_CD", "N_SDPD"])
 
 
+def test_wall_periodic_slurry_at_the_papers_units(S, oracle_lib):
+    """The slurry channel of Sec. 4.3 at the paper's constants (rho0 = 3,
+    m_f = 0.375, h = 2 dx, kT = 1): periodic in x and y, wall faces on z
+    (outer walls sorted behind the active particles, seams on two axes),
+    interleaved spheres with contacts; the thermal motion runs the skin out
+    several times."""
+    p, parts, _ = W.slurry_channel(5, walls=True, L=(11.0, 11.0, 10.0))
+    parts = W.perturb(parts, p, jitter=0.05, kT=p["kBT"], seed=31, spin=True)
+    print(f"[case] wall-periodic slurry, n={parts['id'].shape[0]}, skin 0.3h", flush=True)
+    g, info = _run(S, p, parts, 0.3 * p["h"], 80)
+    assert info[13] >= 2 and info[14] >= 20
+    _hand_over(S, oracle_lib, g, p, parts, VECTOR_FIELDS)
+
+
 def test_graph_replay_searches_every_step(S, oracle_lib):
     """Inside a captured graph the host cannot decide, so every replayed step
     searches (and refreshes the candidates); eager steps after the replays
