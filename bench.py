@@ -113,7 +113,9 @@ def viscometer_leg(k_steps, n_cells=256, run_steps=5000, graph_steps=10, tune=Tr
     warm-up that includes the capture; runs/hr extrapolates to run_steps
     steps per run.  The batched figure is taken twice: at the default launch
     shape (cell = h, graph_steps steps per graph, all cells in one batch) and
-    at the shape the autotuner picks (its own trials are not timed here)."""
+    at the shape the autotuner picks (its own trials are not timed here;
+    graph length 0 there means eager steps with neighbour-candidate reuse,
+    timed over 3 k_steps steps)."""
     import torch
 
     from paper_2002_03120_amd import autotune as AT
@@ -123,8 +125,10 @@ def viscometer_leg(k_steps, n_cells=256, run_steps=5000, graph_steps=10, tune=Tr
     st = torch.cuda.Stream()
 
     def timed(p, parts, cell_factor=1.0, gs=graph_steps, **kw):
-        k = max(gs, (k_steps // gs) * gs)
-        p = dict(p, cell_factor=float(cell_factor))
+        # eager steps with candidate reuse (graph length 0) search every few
+        # dozen steps: they are timed over three times as many steps
+        k = AT.steps_per_call(gs, k_steps if gs else 3 * k_steps)
+        p = AT.launch_params(p, cell_factor, gs)
         g = S.System(p, parts, stream=st, **kw)
         g.set_stress(True)
         g.set_graph(gs)
@@ -153,6 +157,7 @@ def viscometer_leg(k_steps, n_cells=256, run_steps=5000, graph_steps=10, tune=Tr
                       for a, b, _n in AT.split(cells, tun["tile"]))
         out["autotuned"] = {
             "cell_factor": tun["cell_factor"], "graph_steps": tun["graph_steps"],
+            "skin": round(tun["skin"], 4),
             "tile_particles": tun["tile"], "tune_s": round(tun["tune_s"], 2),
             "trials": len(tun["trials"]),
             "batched_ms_per_step": round(t_tuned * 1e3, 3),

@@ -105,10 +105,14 @@ typedef struct sdpdem_params {
                               neighbour sets are unchanged) until some particle
                               has moved skin/2 since the last search; only then
                               are the particles re-sorted and searched again.
-                              Deciding this reads one device word after the
-                              first pass of a step (one synchronisation per
-                              step); under graph replay every step searches.
-                              Not with Lees-Edwards shear                        */
+                              In a sheared box a particle's drift is measured
+                              against the flow's, and the limit shrinks by
+                              (R_max + h + skin) |shear rate| t / 2 with the
+                              time t since the search (the flow's part of two
+                              partners' approach).  Deciding this reads one
+                              device word after the first pass of a step (one
+                              synchronisation per step); under graph replay
+                              every step searches                                */
 } sdpdem_params;
 
 /* Particles, host memory, n rows in any order (ids must cover 0..n-1).

@@ -11,7 +11,9 @@ the cut-off h, so results move only by FP32 summation order):
 * the batch tile, the number of particles advanced together by one batched
   system (cells are packed in order up to it): one big batch fills the chip
   best, smaller ones keep the working set in the L2 caches;
-* the steps captured per HIP graph (the launch overhead per step).
+* the steps captured per HIP graph (the launch overhead per step), or
+  none: eager steps with neighbour-candidate reuse (a skin of h/15; the
+  host decides each step whether to search, which a captured graph cannot).
 
 Every candidate is created and timed on the GPU itself over a short sample
 of the same cells (graph capture in the warm-up, `sample_steps` timed
@@ -33,7 +35,10 @@ from . import sdpdem as S
 from . import workloads as W
 
 CELL_FACTORS = (0.34, 0.5, 0.55, 0.67, 0.75, 1.0, 1.25)
-GRAPH_STEPS = (10, 2, 20)  # the first is used while the cell size is tuned
+# the first is used while the cell size is tuned; 0: eager steps with
+# neighbour-candidate reuse
+GRAPH_STEPS = (10, 2, 20, 0)
+REUSE_SKIN_H = 1.0 / 15.0  # the skin of the eager shape, as a fraction of h
 TILES = (1 << 20, 1 << 21, 1 << 22, 1 << 23)
 
 
@@ -62,13 +67,27 @@ def fits(cells, cell_factor):
     return True
 
 
+def launch_params(p, cell_factor, graph_steps):
+    """The parameters of a system at a launch shape: the cell size, and
+    for eager steps (graph_steps 0) the candidate skin."""
+    skin = REUSE_SKIN_H * p["h"] if graph_steps == 0 else 0.0
+    return dict(p, cell_factor=float(cell_factor), skin=skin)
+
+
+def steps_per_call(graph_steps, steps):
+    """The largest whole number of graphs within `steps` (at least one),
+    or `steps` itself for eager stepping."""
+    if graph_steps == 0:
+        return max(1, steps)
+    return max(graph_steps, (steps // graph_steps) * graph_steps)
+
+
 def time_batch(cells, cell_factor, graph_steps, sample_steps, stream):
     """(create seconds, seconds per step) of one batched system of `cells`
     at this cell size and graph length, stress sampling on."""
     import torch
     parts, boxes, box_of = W.stack_cells(cells)
-    p = dict(cells[0][0])
-    p["cell_factor"] = float(cell_factor)
+    p = launch_params(cells[0][0], cell_factor, graph_steps)
     stream.synchronize()
     t0 = time.perf_counter()
     g = S.System(p, parts, stream=stream, boxes=boxes, box_of=box_of)
@@ -78,7 +97,7 @@ def time_batch(cells, cell_factor, graph_steps, sample_steps, stream):
     stream.synchronize()
     t_create = time.perf_counter() - t0
     g.step(graph_steps)  # capture and first replay
-    k = max(graph_steps, (sample_steps // graph_steps) * graph_steps)
+    k = steps_per_call(graph_steps, sample_steps)
     stream.synchronize()
     t0 = time.perf_counter()
     g.step(k)
@@ -141,6 +160,7 @@ def tune(cells, run_steps, sample_steps=40, cell_factors=CELL_FACTORS,
                     and t.get("graph_steps") == 10 and t.get("tile") == big), None)
     return {
         "cell_factor": best[1], "graph_steps": best[2], "tile": best[3],
+        "skin": launch_params(cells[0][0], best[1], best[2])["skin"],
         "predicted_s": best[0], "default_predicted_s": default,
         "tune_s": time.perf_counter() - t_start, "trials": trials,
     }

@@ -121,8 +121,6 @@ bool valid_box(const sdpdem_params* P, const sdpdem_box& b) {
   }
   if (!(b.kBT >= 0) || !std::isfinite(b.kBT) || !std::isfinite(b.shear_rate)) return false;
   if (b.shear_rate != 0.0 && (!b.periodic[0] || !b.periodic[1] || !b.periodic[2])) return false;
-  // the sheared images move against each other every step: no reuse there
-  if (b.shear_rate != 0.0 && P->skin > 0.0) return false;
   return true;
 }
 
@@ -359,6 +357,7 @@ size_t layout(const Sizes& z, char* base, sdpdem_system* s) {
     d.ritems = ritems;
     d.status = status;
     d.moved = status + 32;  // its own 128-byte half of the status block
+    d.sstep = reinterpret_cast<int64_t*>(status + 34);
     d.rpos_c = rpos_c;
     d.rvel_c = rvel_c;
     d.rom_c = rom_c;
@@ -460,6 +459,13 @@ bool plan(const sdpdem_params* P, const sdpdem_box* boxes, int nbox,
     double mincs = std::min(B.rg.cs[0], std::min(B.rg.cs[1], B.rg.cs[2]));
     B.dem_reach = std::max(1, (int)std::ceil((2.0 * rmax + P->h) / mincs * (1.0 + 1e-9)));
     B.couple_R = rmax + P->h;
+    // under shear every partner within H_s <= R_max + h now was within
+    // H_s + skin at the search while 2 D + (R_max + h + skin) |shear| t <
+    // skin (D: the largest drift less the flow's, t: time since the search)
+    B.shear_reach = std::fabs(hb.shear_rate) * (rmax + P->h + P->skin);
+    B.act_margin = (hb.shear_rate != 0.0 && P->skin > 0.0)
+                       ? 0.5 * hb.L[2] * P->skin / (rmax + P->h + P->skin)
+                       : 0.0;
     B.dem_R = 2.0 * rmax + P->h;
     int64_t nact = 0;
     for (int64_t k : r) nact += q->type[k] != SDPDEM_OUTER_WALL;
@@ -536,6 +542,8 @@ void fill_constants(sdpdem_system* s, const Sizes& z) {
   d.h2 = P.h * P.h;
   d.inv_h = 1.0 / P.h;
   d.reuse = z.maxcand > 0 ? 1 : 0;
+  d.any_le = 0;
+  for (const BoxD& B : z.boxes) d.any_le |= B.le;
   d.maxcand = z.maxcand;
   d.hc = P.h + P.skin;
   d.hc2 = d.hc * d.hc;

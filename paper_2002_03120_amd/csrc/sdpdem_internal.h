@@ -83,6 +83,10 @@ struct BoxD {
   int blk_first;      // the box's first entry in the launch-block table
   int dem_reach;      // rigid-grid cells to search for DEM partners
   double couple_R;    // R_max + h: coupling partners lie within it
+  // candidate reuse under shear: the flow brings two particles at most
+  // shear_reach t closer (|shear| (R_max + h + skin)); the coupling search
+  // reaches act_margin farther, the flow's largest drift before a search
+  double shear_reach, act_margin;
   double dem_R;       // 2 R_max + h: DEM and lubrication partners lie within it
   int noise;          // thermal forces on
   float kTf;
@@ -154,6 +158,7 @@ struct Dev {
   // that search, and a flag raised by a drift that moved a particle more
   // than skin/2 from them
   int reuse;
+  int any_le;      // some box is sheared
   int maxcand;
   double hc, hc2;  // h + skin and its square
   double pad;      // skin/2: how far a particle may be from its cell
@@ -162,6 +167,7 @@ struct Dev {
   int* cand_cnt;
   D4* xref;
   int* moved;
+  int64_t* sstep;  // the step of the last search (candidate reuse under shear)
   double* rho;
   double* p;
   D4* xp;   // x, y, z, p of the last build: the pressure filter's neighbour record

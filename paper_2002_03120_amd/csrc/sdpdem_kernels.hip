@@ -490,7 +490,8 @@ __global__ __launch_bounds__(BS) void k_fpi_action(Dev d, int use_rec) {
     // reuse the grid holds the particles where the last search saw them, up
     // to pad from where they are: search that much wider
     const double Hr = H + 2.0 * d.pad, Hr2 = Hr * Hr;
-    const double Hs = Hr + d.pad;
+    // (and, in a sheared box, as far again as the flow can carry them)
+    const double Hs = Hr + d.pad + B.act_margin;
     const int kr = reach_cells(gr, Hs);
     // the search box row by row: lane r takes row r of each batch of 64 rows
     // (at most two runs of consecutive cells per row)
@@ -1011,7 +1012,10 @@ __device__ __forceinline__ void total_force(const Dev& d, const BoxD& B, int i, 
 // RXN: the reaction of the coupled fluid particles is formed here too
 // (one launch less; the particle's F_RXN is used from registers)
 // (64 registers, eight waves per SIMD, fit without spills)
-template <int VELVER, bool RXN, bool MOVED = false>
+// MOVED: 1 raises the flag of candidate reuse for a drift of skin/2; 2 also
+// handles sheared boxes (the drift less the flow's, a limit shrinking with
+// the time since the search)
+template <int VELVER, bool RXN, int MOVED = 0>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_integrate(Dev d, int rigid_active, int end_step) {
   // the last pass of a step advances the device step counter (no kernel of
   // this launch reads it)
@@ -1095,8 +1099,23 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
       // lists need a new search (one atomic per wave, not per particle)
       const D4 q = d.xref[i];
       double ex = p.x - q.x, ey = p.y - q.y, ez = p.z - q.z;
-      min_img_box(geo_of(B), ex, ey, ez);
-      const bool far = r2_exact(ex, ey, ez) > d.mv2;
+      bool far;
+      if (MOVED == 2 && B.le) {
+        // sheared: the displacement through the images of the drifted
+        // positions, less the flow's x displacement since the search at
+        // the reference height; two partners' separations then change by
+        // at most twice that plus shear_reach t, which must stay below skin
+        Geo G = geo_of(B);
+        G.le_shift = B.le_next;
+        min_img_box(G, ex, ey, ez);
+        const double t = (double)(d.dstep[0] - d.sstep[0]) * d.dt;
+        ex -= B.shear * (q.z - (B.org[2] + 0.5 * B.L[2])) * t;
+        const double lim = (d.pad - 0.5 * B.shear_reach * t) * (1.0 - 1e-9);
+        far = !(lim > 0.0) || r2_exact(ex, ey, ez) > lim * lim;
+      } else {
+        min_img_box(geo_of(B), ex, ey, ez);
+        far = r2_exact(ex, ey, ez) > d.mv2;
+      }
       const unsigned long long m = __ballot(far);
       if (m && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)m) - 1)) atomicOr(d.moved, 1);
     }
@@ -1124,8 +1143,10 @@ void launch_integrate(const Dev& d, int velver, int rigid_active, bool end_step,
   // only the drift (velver 1) moves particles; the moved flag of candidate
   // reuse is a separate instantiation, so the plain update keeps its registers
   auto k = velver == 2 ? (fuse_rxn ? k_integrate<2, true> : k_integrate<2, false>)
-           : track_moved ? (fuse_rxn ? k_integrate<1, true, true> : k_integrate<1, false, true>)
-                       : (fuse_rxn ? k_integrate<1, true> : k_integrate<1, false>);
+           : track_moved
+               ? (d.any_le ? (fuse_rxn ? k_integrate<1, true, 2> : k_integrate<1, false, 2>)
+                           : (fuse_rxn ? k_integrate<1, true, 1> : k_integrate<1, false, 1>))
+               : (fuse_rxn ? k_integrate<1, true> : k_integrate<1, false>);
   k<<<d.nablk, BS, 0, st>>>(d, rigid_active, end_step ? 1 : 0);
 }
 

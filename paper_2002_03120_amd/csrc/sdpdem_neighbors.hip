@@ -38,7 +38,10 @@ __device__ __forceinline__ void outer_wall_fields(const Dev& d, int i, const D4&
 template <bool CAND>
 __device__ __forceinline__ void build_density(const Dev& d) {
   // a search resets the moved flag: positions are measured from here on
-  if (CAND && blockIdx.x == 0 && threadIdx.x == 0) d.moved[0] = 0;
+  if (CAND && blockIdx.x == 0 && threadIdx.x == 0) {
+    d.moved[0] = 0;
+    d.sstep[0] = d.dstep[0];
+  }
   int i;
   const int b = blk_box(d, i);
   if (b < 0) return;

@@ -49,7 +49,8 @@ def measure(cells, steps, block=50, chunk_particles=4_000_000, tuning=None, log=
     """Run the cells as batches of at most chunk_particles particles (on a
     side stream, the step loop replayed from captured graphs of 10 steps).
     A `tuning` from autotune.tune replaces the batch tile, the graph length
-    and the cell size by its choice.  Returns (eta_eff / eta, standard error
+    and the cell size by its choice (graph length 0: eager steps with
+    neighbour-candidate reuse).  Returns (eta_eff / eta, standard error
     of it) per cell."""
     import torch
     cell_factor, graph_steps = 1.0, 10
@@ -57,14 +58,14 @@ def measure(cells, steps, block=50, chunk_particles=4_000_000, tuning=None, log=
         cell_factor, graph_steps = tuning["cell_factor"], tuning["graph_steps"]
         chunk_particles = tuning["tile"]
     # stress is read every `block` steps: a whole number of graphs
-    block = max(graph_steps, (block // graph_steps) * graph_steps)
+    block = AT.steps_per_call(graph_steps, block)
     stream = torch.cuda.Stream()
     eta_rel = np.empty(len(cells))
     se_rel = np.empty(len(cells))
     for start, stop, n in AT.split(cells, chunk_particles):
         part = cells[start:stop]
         parts, boxes, box_of = W.stack_cells(part)
-        p = dict(part[0][0], cell_factor=float(cell_factor))
+        p = AT.launch_params(part[0][0], cell_factor, graph_steps)
         g = S.System(p, parts, boxes=boxes, box_of=box_of, stream=stream)
         g.set_stress(True)
         g.set_graph(graph_steps)

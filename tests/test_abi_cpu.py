@@ -89,7 +89,6 @@ def test_skin_adds_candidate_rows(lib):
     dict(cell_factor=0.2), dict(cell_factor=-1.0), dict(cell_factor=float("nan")),
     dict(cell_factor=17.0), dict(cell_factor=4.0),  # 4 h cells: fewer than 3 on a 10-site axis
     dict(skin=-0.1), dict(skin=0.76), dict(skin=float("nan")),  # 0 <= skin <= h/2 = 0.75
-    dict(skin=0.3, shear_rate=0.01),  # no reuse across sheared images
 ])
 def test_rejects_bad_params(lib, bad):
     p, parts, _ = W.reverse_poiseuille(n_side=(10, 10, 10))

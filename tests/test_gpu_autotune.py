@@ -22,13 +22,15 @@ def test_tuner_picks_the_fastest_predicted_shape(AT):
     n = sum(c[2]["n"] for c in cells)
     print(f"[case] tune {len(cells)} cells, {n} particles", flush=True)
     res = AT.tune(cells, 1000, sample_steps=10, cell_factors=(0.5, 1.0, 1.3),
-                  graph_steps=(10, 2), tiles=(n // 3, 1 << 22))
+                  graph_steps=(10, 2, 0), tiles=(n // 3, 1 << 22))
     timed = [t for t in res["trials"] if "predicted_s" in t]
-    assert len(timed) == 3 + 1 + 1
+    assert len(timed) == 3 + 2 + 1
     assert res["predicted_s"] == min(t["predicted_s"] for t in timed)
-    assert res["cell_factor"] in (0.5, 1.0, 1.3) and res["graph_steps"] in (2, 10)
+    assert res["cell_factor"] in (0.5, 1.0, 1.3) and res["graph_steps"] in (0, 2, 10)
     assert res["tile"] in (n // 3, 1 << 22)
     assert all(t["step_ms"] > 0 and t["create_s"] > 0 for t in timed)
+    h = cells[0][0]["h"]
+    assert res["skin"] == (AT.REUSE_SKIN_H * h if res["graph_steps"] == 0 else 0.0)
 
 
 def test_batch_tile_and_graph_length_do_not_change_results(AT):
@@ -44,6 +46,23 @@ def test_batch_tile_and_graph_length_do_not_change_results(AT):
                    tuning=dict(cell_factor=1.0, graph_steps=2, tile=n // 3))
     assert np.all(np.isfinite(a[1]))
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_eager_shape_with_reuse_measures_the_same_viscosities(AT):
+    """The eager shape (graph length 0: neighbour-candidate reuse in the
+    sheared cells) computes the same physics: the neighbour sets are exact,
+    only the summation order differs, so over a short run each cell's
+    viscosity agrees with the graph-replayed measurement to within the
+    runs' own standard errors."""
+    from paper_2002_03120_amd import surrogate as SG
+    _, cells = W.viscometer_batch(6, seed=5, side=(10, 14), steps=200)
+    n = sum(c[2]["n"] for c in cells)
+    print(f"[case] measure {len(cells)} cells, graphs and eager with reuse", flush=True)
+    a = SG.measure(cells, 200, block=20, tuning=dict(cell_factor=0.67, graph_steps=2, tile=n))
+    b = SG.measure(cells, 200, block=20, tuning=dict(cell_factor=0.67, graph_steps=0, tile=n))
+    assert np.all(np.isfinite(b[0])) and np.all(np.isfinite(b[1]))
+    print("  eta", np.round(a[0], 3), np.round(b[0], 3), "se", np.round(a[1], 3), flush=True)
+    assert np.all(np.abs(a[0] - b[0]) <= 3.0 * (a[1] + b[1]))
 
 
 def test_single_system_tuner_picks_its_fastest_cell_size(AT):

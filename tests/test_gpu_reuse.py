@@ -170,6 +170,53 @@ def test_batch_of_boxes_with_reuse(S, oracle_lib):
         off += n
 
 
+def test_sheared_batch_with_reuse(S, oracle_lib):
+    """Three Lees-Edwards cells at different shear rates with spheres,
+    contacts and thermal noise, run with a skin: a particle's drift is
+    measured against the flow's and the limit shrinks with the time since
+    the search, so the fastest-sheared cell (the flow's term alone allows
+    some 180 steps there) makes the batch search again.  Each box's state then goes to an oracle of its own, which
+    searches from scratch (its image offset from the step number)."""
+    cells = [W.shear_cell(12, 0.2, 3.0, kBT=5e-3, shear_rate=0.1, seed=61),
+             W.shear_cell(10, 0.0, 0.0, kBT=2e-3, shear_rate=-0.03, seed=62),
+             W.shear_cell(14, 0.3, 2.5, kBT=1e-3, shear_rate=0.05, seed=63)]
+    parts, boxes, box_of = W.stack_cells(cells)
+    print(f"[case] batch of 3 sheared cells, skin 0.3: n={parts['id'].shape[0]}", flush=True)
+    g = S.System(dict(cells[0][0], skin=0.3), parts, boxes=boxes, box_of=box_of)
+    g.step(160)
+    inf = g.info()
+    print(f"  160 steps: {inf[13]} searches, {inf[14]} lists from candidates", flush=True)
+    assert inf[13] >= 2 and inf[14] >= 60
+    pos, vel, ang = (g.read_field(f) for f in ("POS", "VEL", "ANGVEL"))
+    pairs, dts = g.read_contacts()
+    assert g.compute_forces(check=False) == 0
+    rows, cols = g.read_neighbors()
+    fields = {f: g.read_field(f) for f in VECTOR_FIELDS + ["DENS"]}
+    off = 0
+    for b, (p, pp, _info) in enumerate(cells):
+        n = pp["id"].shape[0]
+        st = {k: np.array(v, copy=True) for k, v in pp.items()}
+        st["pos"], st["vel"], st["angvel"] = pos[off:off + n], vel[off:off + n], ang[off:off + n]
+        o = oracle_lib.Oracle(dict(p, itr_start=g.current_step), st)
+        mine = np.all((pairs >= off) & (pairs < off + n), axis=1)
+        if mine.any():
+            o.load_contacts(pairs[mine] - off, dts[mine])
+        assert o.compute_forces(check=False) == 0
+        ro, co = o.read_neighbors()
+        assert np.array_equal(rows[off:off + n + 1] - rows[off], ro), b
+        assert np.array_equal(cols[rows[off]:rows[off + n]] - off, co), b
+        assert np.allclose(fields["DENS"][off:off + n], o.read_field("DENS"), rtol=1e-12, atol=0)
+        worst = 0.0
+        for f in VECTOR_FIELDS:
+            sc = o.read_field(f + "_ABS")
+            err = np.linalg.norm(fields[f][off:off + n] - o.read_field(f), axis=1)
+            tiny = 1e-30 + 1e-12 * (sc.max() if sc.size else 0.0)
+            assert np.all(err <= 1e-5 * sc + tiny), (b, f)
+            worst = max(worst, float((err / (sc + tiny)).max()))
+        print(f"  box {b}: n {n}, nnz {co.size}, worst rel {worst:.1e}", flush=True)
+        off += n
+
+
 def test_candidate_overflow_is_reported(S):
     """Rows too short for the partners (18 within h on this lattice) and for
     the candidates within h + skin (56): the candidate search reports the
