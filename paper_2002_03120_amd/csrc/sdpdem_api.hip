@@ -716,8 +716,10 @@ enum BuildLists { LISTS_SEARCH, LISTS_FILTER, LISTS_FILTERED };
 // The neighbour build; with commit_next >= 0 a force pass with that commit
 // flag follows at once, and the build already issues that pass's sphere
 // records and contacts (which need only the permuted state).  Without a
-// search the particles keep their order and cells.
-void run_build(sdpdem_system* s, hipStream_t st, int commit_next, int lists = LISTS_SEARCH) {
+// search the particles keep their order and cells.  after_drift: the build
+// between a step's two passes (else one ahead of the first pass).
+void run_build(sdpdem_system* s, hipStream_t st, int commit_next, int lists = LISTS_SEARCH,
+               bool after_drift = false) {
   Dev& d = s->d;
   const int nc = d.ncells_all;
   const bool search = lists == LISTS_SEARCH;
@@ -757,7 +759,7 @@ void run_build(sdpdem_system* s, hipStream_t st, int commit_next, int lists = LI
     // inside a graph no step can reuse candidates: the plain search there
     const bool cand = d.reuse && !s->capturing;
     Prof pr(s, SDPDEM_K_NEIGHBORS_DENSITY, st);
-    launch_build_density(d, cand, st);
+    launch_build_density(d, cand, after_drift, st);
     s->cand_valid = cand;
     s->searches += 1;
   } else {
@@ -1184,7 +1186,7 @@ void step_body(sdpdem_system* s, hipStream_t st) {
     }
     if (!(posted ? wait_moved(s) : read_moved_sync(s, st))) lists = LISTS_FILTERED;
   }
-  run_build(s, st, 1, lists);
+  run_build(s, st, 1, lists, true);
   run_pass(s, 2, 1, true, fill2, st);
   if (s->stress) {
     launch_box_stress(d, 1, st);

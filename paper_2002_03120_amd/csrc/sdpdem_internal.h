@@ -167,7 +167,9 @@ struct Dev {
   int* cand_cnt;
   D4* xref;
   int* moved;
-  int64_t* sstep;  // the step of the last search (candidate reuse under shear)
+  // the step whose drift made the positions of the last search (candidate
+  // reuse under shear): a drift at step m is (m - sstep) dt later
+  int64_t* sstep;
   double* rho;
   double* p;
   D4* xp;   // x, y, z, p of the last build: the pressure filter's neighbour record
@@ -242,7 +244,7 @@ void launch_permute(const Dev& d, const D4* spos, const D4* svel, const D4* som,
                     const uint8_t* stype, const int* sgid, hipStream_t st);
 // the cell-grid search; with cand (reuse on) also the candidates within
 // h + skin and the positions they were found at
-void launch_build_density(const Dev& d, bool cand, hipStream_t st);
+void launch_build_density(const Dev& d, bool cand, bool after_drift, hipStream_t st);
 // the lists, density and pressure from the candidates of the last search
 void launch_filter_density(const Dev& d, hipStream_t st);
 // start of a pass: Lees-Edwards offsets of every box for positions at step

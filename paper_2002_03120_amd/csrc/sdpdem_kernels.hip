@@ -1105,6 +1105,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
         // positions, less the flow's x displacement since the search at
         // the reference height; two partners' separations then change by
         // at most twice that plus shear_reach t, which must stay below skin
+        // (t the time between the searched positions and these: across a
+        // sheared face the image offset moved by the rate times L_z t)
         Geo G = geo_of(B);
         G.le_shift = B.le_next;
         min_img_box(G, ex, ey, ez);

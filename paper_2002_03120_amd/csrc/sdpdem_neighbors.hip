@@ -35,12 +35,15 @@ __device__ __forceinline__ void outer_wall_fields(const Dev& d, int i, const D4&
   d.xp[i] = D4{pi.x, pi.y, pi.z, d.p_ref};
 }
 
+// after_drift: the build between the two passes of a step, at the
+// positions the step's drift made; otherwise a build ahead of the first
+// pass, at the positions the previous step's drift made
 template <bool CAND>
-__device__ __forceinline__ void build_density(const Dev& d) {
+__device__ __forceinline__ void build_density(const Dev& d, int after_drift) {
   // a search resets the moved flag: positions are measured from here on
   if (CAND && blockIdx.x == 0 && threadIdx.x == 0) {
     d.moved[0] = 0;
-    d.sstep[0] = d.dstep[0];
+    d.sstep[0] = d.dstep[0] - (after_drift ? 0 : 1);
   }
   int i;
   const int b = blk_box(d, i);
@@ -118,15 +121,15 @@ __device__ __forceinline__ void build_density(const Dev& d) {
 // eight waves per SIMD for the plain search; the candidate search holds
 // more state and spills below 96 registers, so it takes five
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_build_density(Dev d) {
-  build_density<false>(d);
+  build_density<false>(d, 0);
 }
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(5))) void k_build_candidates(Dev d) {
-  build_density<true>(d);
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(5))) void k_build_candidates(Dev d, int after_drift) {
+  build_density<true>(d, after_drift);
 }
 
-void launch_build_density(const Dev& d, bool cand, hipStream_t st) {
+void launch_build_density(const Dev& d, bool cand, bool after_drift, hipStream_t st) {
   if (cand)
-    k_build_candidates<<<d.nblk, BS, 0, st>>>(d);
+    k_build_candidates<<<d.nblk, BS, 0, st>>>(d, after_drift ? 1 : 0);
   else
     k_build_density<<<d.nblk, BS, 0, st>>>(d);
 }

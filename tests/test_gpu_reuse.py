@@ -11,6 +11,8 @@ which searches from scratch: neighbour sets bit for bit, rho and p to
 1e-12, forces to the single-step tolerance, with the library's last lists
 taken from the candidates.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -168,6 +170,43 @@ def test_batch_of_boxes_with_reuse(S, oracle_lib):
         err = np.linalg.norm(fs[off:off + n] - o.read_field("F_SDPD"), axis=1)
         assert np.all(err <= 1e-5 * sc + 1e-30)
         off += n
+
+
+def test_sheared_search_comes_when_the_flow_reaches_the_skin(S):
+    """A fluid lattice in exact affine shear flow (v_x = rate (z - L/2), no
+    noise, no spheres) keeps a centrosymmetric neighbourhood around every
+    particle, so the pair forces cancel to rounding and each drift is the
+    flow's.  The reuse criterion is then decided by its time term alone: a
+    search as soon as the time between the searched positions and the
+    drifted ones reaches skin / (|rate| (h + skin)), i.e. every K =
+    ceil(skin / (|rate| (h + skin) dt)) steps.  The first interval counts
+    from the positions the initial build saw, those of the start of the
+    first step, like every later one (a search between the two passes sees
+    the positions the step's drift made); counting it from the first drift
+    instead would let a pair across the sheared face close in by one step
+    of image offset, rate L_z dt, that the skin does not cover."""
+    rate, dt, skin = 1.5, 5e-3, 0.3
+    p, parts, _ = W.shear_cell(12, 0.0, 0.0, kBT=0.0, shear_rate=rate, dt=dt)
+    K = math.ceil(skin / (abs(rate) * (p["h"] + skin) * dt))
+    frac = skin / (abs(rate) * (p["h"] + skin) * dt) % 1.0
+    assert 0.1 < frac < 0.9  # the threshold falls well between two steps
+    print(f"[case] affine shear lattice n={parts['id'].shape[0]}, rate {rate}, skin {skin}, "
+          f"K {K}", flush=True)
+    g = S.System(dict(p, skin=skin), parts)
+    g.step(1)
+    last = g.info()[13]
+    assert last == 1  # the initial build, ahead of the first pass
+    searched = []
+    for m in range(1, 3 * K + 2):
+        g.step(1)
+        n = g.info()[13]
+        assert n - last in (0, 1)
+        if n > last:
+            searched.append(m)
+        last = n
+    print(f"  searches at steps {searched}", flush=True)
+    g.close()
+    assert searched == [K - 1, 2 * K - 1, 3 * K - 1]
 
 
 def test_sheared_batch_with_reuse(S, oracle_lib):
