@@ -526,6 +526,10 @@ def main():
     if prof:
         roof["valu_busy"] = prof["valu_busy"]
         roof["valu_lane_use"] = prof["lane_use"]
+        # the unit the divergent gathers keep busy: texture addressing, from
+        # the same counter profile
+        if "ta_busy" in prof:
+            roof["ta_busy"] = prof["ta_busy"]
     if prof:
         # the same fraction from the measured HBM bytes of the counter
         # profile (re-fetched partner records included) instead of the
