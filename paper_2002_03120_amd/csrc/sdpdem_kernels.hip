@@ -1018,8 +1018,10 @@ __device__ __forceinline__ void total_force(const Dev& d, const BoxD& B, int i, 
 template <int VELVER, bool RXN, int MOVED = 0>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_integrate(Dev d, int rigid_active, int end_step) {
   // the last pass of a step advances the device step counter (no kernel of
-  // this launch reads it)
-  if (end_step && blockIdx.x == 0 && threadIdx.x == 0) d.dstep[0] += 1;
+  // this launch reads it); only the second half-kick ends a step, and the
+  // drift variants, without this store ahead of their loads, read the box
+  // constants through the scalar cache
+  if (VELVER == 2 && end_step && blockIdx.x == 0 && threadIdx.x == 0) d.dstep[0] += 1;
   int i;
   const int b = blk_box<true>(d, i);
   if (b < 0) return;
@@ -1094,33 +1096,6 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
     v.y = vv[1];
     v.z = vv[2];
     d.pos[i] = p;
-    if (MOVED) {
-      // farther than skin/2 from where the last search saw it: the next
-      // lists need a new search (one atomic per wave, not per particle)
-      const D4 q = d.xref[i];
-      double ex = p.x - q.x, ey = p.y - q.y, ez = p.z - q.z;
-      bool far;
-      if (MOVED == 2 && B.le) {
-        // sheared: the displacement through the images of the drifted
-        // positions, less the flow's x displacement since the search at
-        // the reference height; two partners' separations then change by
-        // at most twice that plus shear_reach t, which must stay below skin
-        // (t the time between the searched positions and these: across a
-        // sheared face the image offset moved by the rate times L_z t)
-        Geo G = geo_of(B);
-        G.le_shift = B.le_next;
-        min_img_box(G, ex, ey, ez);
-        const double t = (double)(d.dstep[0] - d.sstep[0]) * d.dt;
-        ex -= B.shear * (q.z - (B.org[2] + 0.5 * B.L[2])) * t;
-        const double lim = (d.pad - 0.5 * B.shear_reach * t) * (1.0 - 1e-9);
-        far = !(lim > 0.0) || r2_exact(ex, ey, ez) > lim * lim;
-      } else {
-        min_img_box(geo_of(B), ex, ey, ez);
-        far = r2_exact(ex, ey, ez) > d.mv2;
-      }
-      const unsigned long long m = __ballot(far);
-      if (m && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)m) - 1)) atomicOr(d.moved, 1);
-    }
   }
   if (!isfinite(v.x) || !isfinite(v.y) || !isfinite(v.z) || !isfinite(w.x) || !isfinite(w.y) ||
       !isfinite(w.z) || (VELVER == 1 && (!isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z))))
@@ -1137,6 +1112,35 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
     r->wx = (float)w.x;
     r->wy = (float)w.y;
     r->wz = (float)w.z;
+  }
+  // Farther than skin/2 from where the last search saw it: the next lists
+  // need a new search (one atomic per wave, not per particle).  Tested after
+  // the stores, when the velocities are no longer live (the sheared test
+  // needs registers of its own).
+  if (MOVED && VELVER == 1 && (t == T_FLUID || t == T_RIGID)) {
+    const D4 q = d.xref[i];
+    double ex = p.x - q.x, ey = p.y - q.y, ez = p.z - q.z;
+    bool far;
+    if (MOVED == 2 && B.le) {
+      // sheared: the displacement through the images of the drifted
+      // positions, less the flow's x displacement since the search at the
+      // reference height; two partners' separations then change by at most
+      // twice that plus shear_reach ts, which must stay below skin (ts the
+      // time between the searched positions and these: across a sheared
+      // face the image offset moved by the rate times L_z ts)
+      Geo G = geo_of(B);
+      G.le_shift = B.le_next;
+      min_img_box(G, ex, ey, ez);
+      const double ts = (double)(d.dstep[0] - d.sstep[0]) * d.dt;
+      ex -= B.shear * (q.z - (B.org[2] + 0.5 * B.L[2])) * ts;
+      const double lim = (d.pad - 0.5 * B.shear_reach * ts) * (1.0 - 1e-9);
+      far = !(lim > 0.0) || r2_exact(ex, ey, ez) > lim * lim;
+    } else {
+      min_img_box(geo_of(B), ex, ey, ez);
+      far = r2_exact(ex, ey, ez) > d.mv2;
+    }
+    const unsigned long long m = __ballot(far);
+    if (m && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)m) - 1)) atomicOr(d.moved, 1);
   }
 }
 
