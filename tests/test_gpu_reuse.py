@@ -172,7 +172,8 @@ def test_batch_of_boxes_with_reuse(S, oracle_lib):
         off += n
 
 
-def test_sheared_search_comes_when_the_flow_reaches_the_skin(S):
+@pytest.mark.parametrize("start", ["fresh", "compute_forces", "restart"])
+def test_sheared_search_comes_when_the_flow_reaches_the_skin(S, start):
     """A fluid lattice in exact affine shear flow (v_x = rate (z - L/2), no
     noise, no spheres) keeps a centrosymmetric neighbourhood around every
     particle, so the pair forces cancel to rounding and each drift is the
@@ -184,15 +185,27 @@ def test_sheared_search_comes_when_the_flow_reaches_the_skin(S):
     first step, like every later one (a search between the two passes sees
     the positions the step's drift made); counting it from the first drift
     instead would let a pair across the sheared face close in by one step
-    of image offset, rate L_z dt, that the skin does not cover."""
+    of image offset, rate L_z dt, that the skin does not cover.  The same
+    schedule whichever way the first build comes: a new system, a force
+    evaluation ahead of the first step, a restart at a later step."""
     rate, dt, skin = 1.5, 5e-3, 0.3
     p, parts, _ = W.shear_cell(12, 0.0, 0.0, kBT=0.0, shear_rate=rate, dt=dt)
+    if start == "restart":
+        a = S.System(p, parts)
+        a.step(7)
+        parts = {k: np.array(v, copy=True) for k, v in parts.items()}
+        parts["pos"], parts["vel"], parts["angvel"] = (a.read_field(f)
+                                                       for f in ("POS", "VEL", "ANGVEL"))
+        p = dict(p, itr_start=a.current_step)
+        a.close()
     K = math.ceil(skin / (abs(rate) * (p["h"] + skin) * dt))
     frac = skin / (abs(rate) * (p["h"] + skin) * dt) % 1.0
     assert 0.1 < frac < 0.9  # the threshold falls well between two steps
     print(f"[case] affine shear lattice n={parts['id'].shape[0]}, rate {rate}, skin {skin}, "
-          f"K {K}", flush=True)
+          f"K {K}, {start}", flush=True)
     g = S.System(dict(p, skin=skin), parts)
+    if start == "compute_forces":
+        g.compute_forces()
     g.step(1)
     last = g.info()[13]
     assert last == 1  # the initial build, ahead of the first pass
