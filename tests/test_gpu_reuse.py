@@ -172,6 +172,48 @@ def test_batch_of_boxes_with_reuse(S, oracle_lib):
         off += n
 
 
+def _search_steps(g, steps):
+    """Step g one step at a time; the steps (0-based) whose build was a
+    cell-grid search, after the first step's initial build."""
+    g.step(1)
+    last = g.info()[13]
+    assert last == 1  # the initial build, ahead of the first pass
+    searched = []
+    for m in range(1, steps):
+        g.step(1)
+        n = g.info()[13]
+        assert n - last in (0, 1)
+        if n > last:
+            searched.append(m)
+        last = n
+    print(f"  searches at steps {searched}", flush=True)
+    return searched
+
+
+def test_search_comes_when_a_translation_reaches_half_the_skin(S):
+    """A periodic fluid lattice moving as a whole (every velocity the same,
+    no noise) feels no net force: relative velocities vanish and the
+    neighbourhoods stay centrosymmetric.  Each drift moves every particle
+    by |v| dt, so the lists come from the candidates until the distance
+    from the searched positions passes skin/2: a search every K =
+    ceil(skin / (2 |v| dt)) steps, the first interval counted from the
+    positions the initial build saw."""
+    dt, skin = 5e-3, 0.3
+    v = np.array([0.48, -0.2, 0.0])
+    p, parts, _ = W.shear_cell(12, 0.0, 0.0, kBT=0.0, shear_rate=0.0, dt=dt)
+    parts["vel"][:] = v
+    parts["angvel"][:] = 0.0
+    ratio = skin / (2.0 * np.linalg.norm(v) * dt)
+    K = math.ceil(ratio)
+    assert 0.1 < ratio % 1.0 < 0.9  # the threshold falls well between two steps
+    print(f"[case] translating lattice n={parts['id'].shape[0]}, |v| {np.linalg.norm(v):.3f}, "
+          f"skin {skin}, K {K}", flush=True)
+    g = S.System(dict(p, skin=skin), parts)
+    searched = _search_steps(g, 3 * K + 2)
+    g.close()
+    assert searched == [K - 1, 2 * K - 1, 3 * K - 1]
+
+
 @pytest.mark.parametrize("start", ["fresh", "compute_forces", "restart"])
 def test_sheared_search_comes_when_the_flow_reaches_the_skin(S, start):
     """A fluid lattice in exact affine shear flow (v_x = rate (z - L/2), no
@@ -206,18 +248,7 @@ def test_sheared_search_comes_when_the_flow_reaches_the_skin(S, start):
     g = S.System(dict(p, skin=skin), parts)
     if start == "compute_forces":
         g.compute_forces()
-    g.step(1)
-    last = g.info()[13]
-    assert last == 1  # the initial build, ahead of the first pass
-    searched = []
-    for m in range(1, 3 * K + 2):
-        g.step(1)
-        n = g.info()[13]
-        assert n - last in (0, 1)
-        if n > last:
-            searched.append(m)
-        last = n
-    print(f"  searches at steps {searched}", flush=True)
+    searched = _search_steps(g, 3 * K + 2)
     g.close()
     assert searched == [K - 1, 2 * K - 1, 3 * K - 1]
 
