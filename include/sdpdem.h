@@ -108,8 +108,11 @@ typedef struct sdpdem_params {
                               In a sheared box a particle's drift is measured
                               against the flow's, and the limit shrinks by
                               (R_max + h + skin) |shear rate| t / 2 with the
-                              time t since the search (the flow's part of two
-                              partners' approach).  Deciding this reads one
+                              time t between the searched positions and the
+                              drifted ones (the flow's part of two partners'
+                              approach; a build ahead of a step's first pass
+                              saw the positions of the step's start).
+                              Deciding this reads one
                               device word after the first pass of a step (one
                               synchronisation per step); under graph replay
                               every step searches                                */
