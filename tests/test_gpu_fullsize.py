@@ -1,7 +1,8 @@
 """Parity at the full sizes of the measured workloads, in the launch
 configurations the benchmark uses (fluid cells of 0.55 h, the dam break
 also with neighbour-candidate reuse at skin h/15; the viscometer batch at
-0.67 h, its tuner's pick) and at cells of h: the sedimentation box (101,080 particles), the
+0.67 h, its tuner's pick, also stepped with candidate reuse under
+shear) and at cells of h: the sedimentation box (101,080 particles), the
 dam break (1,534,168 particles, 2^20 moving) and the periodic scale box
 (8,388,608 particles).  The oracle evaluates every particle here; neighbour
 sets must match bit for bit."""
@@ -89,3 +90,52 @@ def test_full_viscometer_batch_sampled_boxes(S, oracle_lib):
             tiny = 1e-30 + 1e-12 * (sc.max() if sc.size else 0.0)
             assert np.all(err <= 1e-5 * sc + tiny), (b, f)
         print(f"  box {b}: n={e - a}, {int(ro[-1])} neighbour slots", flush=True)
+
+
+def test_full_viscometer_batch_with_sheared_reuse(S, oracle_lib):
+    """The batch as the benchmark's tuned shape runs it: eager steps with
+    neighbour-candidate reuse under shear (skin 0.1 = h/15), 60 steps, so
+    that the fastest-sheared cells search again while the rest take their
+    lists from candidates.  Three boxes (the smallest, the largest and one
+    drawn at random) then go to the oracle with their state, contacts and
+    step number; the oracle searches from scratch."""
+    shared, cells = W.viscometer_batch(256, seed=0, steps=5000)
+    parts, boxes, box_of = W.stack_cells(cells)
+    print(f"[case] full viscometer batch with reuse, n={parts['id'].shape[0]}", flush=True)
+    g = S.System(dict(shared, cell_factor=0.67, skin=0.1), parts, boxes=boxes, box_of=box_of)
+    assert g.step(60) == 0
+    inf = g.info()
+    print(f"  60 steps: {inf[13]} searches, {inf[14]} lists from candidates", flush=True)
+    assert inf[13] >= 2 and inf[14] >= 30
+    pos, vel, ang = (g.read_field(f) for f in ("POS", "VEL", "ANGVEL"))
+    pairs, dts = g.read_contacts()
+    assert g.compute_forces(check=False) == 0
+    rows, cols = g.read_neighbors()
+    fields = {f: g.read_field(f) for f in VECTOR_FIELDS}
+    sizes = np.array([c[2]["n"] for c in cells])
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    rng = np.random.default_rng(2)
+    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)),
+                   int(rng.integers(len(cells)))})
+    for b in pick:
+        p, pp, _info = cells[b]
+        a, e = int(offs[b]), int(offs[b + 1])
+        st = {k: np.array(v, copy=True) for k, v in pp.items()}
+        st["pos"], st["vel"], st["angvel"] = pos[a:e], vel[a:e], ang[a:e]
+        o = oracle_lib.Oracle(dict(p, itr_start=g.current_step), st)
+        mine = np.all((pairs >= a) & (pairs < e), axis=1)
+        if mine.any():
+            o.load_contacts(pairs[mine] - a, dts[mine])
+        assert o.compute_forces(check=False) == 0
+        ro, co = o.read_neighbors()
+        assert np.array_equal(rows[a:e + 1] - rows[a], ro), b
+        assert np.array_equal(cols[rows[a]:rows[e]] - a, co), b
+        worst = 0.0
+        for f in VECTOR_FIELDS:
+            ov, sc = o.read_field(f), o.read_field(f + "_ABS")
+            err = np.linalg.norm(fields[f][a:e] - ov, axis=1)
+            tiny = 1e-30 + 1e-12 * (sc.max() if sc.size else 0.0)
+            assert np.all(err <= 1e-5 * sc + tiny), (b, f)
+            worst = max(worst, float((err / (sc + tiny)).max()))
+        print(f"  box {b}: n={e - a}, {int(ro[-1])} neighbour slots, worst rel {worst:.1e}",
+              flush=True)
