@@ -229,41 +229,56 @@ def surrogate_leg(n_cells=64, steps=5000, seed=1999, shear=(1e-2, 1e-1)):
     return ev
 
 
-def scale_leg(steps, cell_factor, warmup=2):
+def scale_leg(steps, cell_factor, skin, warmup=2):
     """The scale run: a fully periodic SDPD lattice of 256 x 256 x 128 =
     8,388,608 particles (the reverse-Poiseuille constants, kT = 1e-3, so the
     thermal pair forces are on), timed over `steps` eager steps after
-    `warmup`; the pair kernel timed by HIP events as in the main figure."""
+    `warmup`, with neighbour-candidate reuse at `skin` as in the main figure
+    (and the same steps searching after every drift beside it); the pair
+    kernel timed by HIP events as in the main figure."""
     import torch
 
     from paper_2002_03120_amd import sdpdem as S
     from paper_2002_03120_amd import workloads as W
 
     p, parts, info = W.periodic_scale()
-    g = S.System(dict(p, cell_factor=cell_factor), parts)
-    g.step(warmup)
-    g.set_profiling("fluid_forces", every=PROF_EVERY)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    g.step(steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    k_ms, k_launches = g.kernel_time()
-    nnz = int(g.info()[9])
-    g.close()
-    del g
-    torch.cuda.empty_cache()
+
+    def timed(sk, profile):
+        g = S.System(dict(p, cell_factor=cell_factor, skin=sk), parts)
+        g.step(warmup)
+        if profile:
+            g.set_profiling("fluid_forces", every=PROF_EVERY)
+        inf0 = g.info()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        k = g.kernel_time() if profile else (0.0, 0)
+        inf = g.info()
+        g.close()
+        del g
+        torch.cuda.empty_cache()
+        return wall, k, inf, inf0
+
+    wall, (k_ms, k_launches), inf, inf0 = timed(skin, True)
+    nnz = int(inf[9])
     n = int(info["n"])
     k_avg_s = k_ms / max(k_launches, 1) / 1e3
     res = {
         "particles": n, "steps": steps, "warmup": warmup, "kT": p["kBT"],
-        "cell_factor": cell_factor,
+        "cell_factor": cell_factor, "skin": skin,
         "ms_per_step": round(wall / steps * 1e3, 4),
         "particle_steps_per_s": round(n * steps / wall, 1),
         "pair_interactions_per_s": round(2 * nnz * steps / wall, 1),
         "pair_kernel_ms": round(k_avg_s * 1e3, 4),
         "pair_slots": nnz,
+        "neighbour_searches": int(inf[13] - inf0[13]),
+        "lists_from_candidates": int(inf[14] - inf0[14]),
     }
+    if skin > 0:
+        wall0 = timed(0.0, False)[0]
+        res["ms_per_step_without_reuse"] = round(wall0 / steps * 1e3, 4)
     # With thermal noise the pair kernel is bound by vector-ALU issue: its
     # roofline is VALU lane-instructions per second against the plain issue
     # peak, the instructions per neighbour slot taken from the committed
@@ -590,7 +605,7 @@ def main():
         result["ms_per_step_graph"] = round(graph_ms_per_step(pg, parts, args.steps,
                                                               args.graph_steps), 4)
     if args.scale_steps > 0:
-        result["scale"] = scale_leg(args.scale_steps, args.cell_factor)
+        result["scale"] = scale_leg(args.scale_steps, args.cell_factor, args.skin)
     if args.viscometer_steps > 0:
         result["viscometer"] = viscometer_leg(args.viscometer_steps)
     if args.surrogate_cells > 0:

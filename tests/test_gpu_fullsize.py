@@ -1,11 +1,11 @@
 """Parity at the full sizes of the measured workloads, in the launch
-configurations the benchmark uses (fluid cells of 0.55 h, the dam break
-also with neighbour-candidate reuse at skin h/15; the viscometer batch at
-0.67 h, its tuner's pick, also stepped with candidate reuse under
-shear) and at cells of h: the sedimentation box (101,080 particles), the
-dam break (1,534,168 particles, 2^20 moving) and the periodic scale box
-(8,388,608 particles).  The oracle evaluates every particle here; neighbour
-sets must match bit for bit."""
+configurations the benchmark uses (fluid cells of 0.55 h; the dam break
+and the scale box also stepped with neighbour-candidate reuse at skin
+h/15; the viscometer batch at 0.67 h, its tuner's pick, also stepped with
+candidate reuse under shear) and at cells of h: the sedimentation box
+(101,080 particles), the dam break (1,534,168 particles, 2^20 moving) and
+the periodic scale box (8,388,608 particles).  The oracle evaluates every
+particle of a box it is given; neighbour sets must match bit for bit."""
 import numpy as np
 import pytest
 
@@ -54,6 +54,23 @@ def test_full_dam_break_after_steps_with_reuse(S, oracle_lib):
     inf = g.info()
     print(f"  {inf[13]} searches, {inf[14]} lists from candidates", flush=True)
     assert inf[14] >= 30
+    _hand_over(S, oracle_lib, g, p, parts, VECTOR_FIELDS)
+
+
+def test_full_scale_box_after_steps_with_reuse(S, oracle_lib):
+    """The benchmark's periodic scale box (8,388,608 particles, kT = 1e-3,
+    cells of 0.55 h, skin 0.1 = h/15) after 30 steps from a jittered
+    lattice, every list since the first search taken from its candidates:
+    the oracle, made from its state, searches from scratch."""
+    from test_gpu_reuse import _hand_over
+    p, parts, info = W.CONFIGS["periodic_scale"]()
+    parts = W.perturb(parts, p, jitter=0.05, kT=1e-3, seed=11)
+    print(f"[case] full-size scale box, 30 steps with reuse: n={info['n']}", flush=True)
+    g = S.System(dict(p, cell_factor=0.55, skin=0.1), parts)
+    g.step(30)
+    inf = g.info()
+    print(f"  {inf[13]} searches, {inf[14]} lists from candidates", flush=True)
+    assert inf[14] >= 25
     _hand_over(S, oracle_lib, g, p, parts, VECTOR_FIELDS)
 
 
