@@ -449,7 +449,8 @@ def main():
     ap.add_argument("--viscometer-steps", type=int, default=20,
                     help="timed steps per configuration of the batched-viscometer leg (0: skip)")
     ap.add_argument("--skin", type=float, default=0.1,
-                    help="neighbour-candidate margin (0: sort and search after every drift); "
+                    help="neighbour-candidate margin of the dam break and the scale box (0: sort "
+                         "and search after every drift); "
                          "the default, h/15, is the fastest of 0.05 h, h/15, 0.1 h, 0.15 h, "
                          "0.2 h here")
     ap.add_argument("--surrogate-cells", type=int, default=64,
