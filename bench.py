@@ -163,7 +163,8 @@ def viscometer_leg(k_steps, n_cells=256, run_steps=5000, graph_steps=10, tune=Tr
             "batched_ms_per_step": round(t_tuned * 1e3, 3),
             "batched_runs_per_hour": round(n_cells / (t_tuned * run_steps) * 3600.0, 1),
         }
-    t_plain = sum(timed(p, pp) for p, pp, _info in cells)
+    t_cells = [timed(p, pp) for p, pp, _info in cells]
+    t_plain = sum(t_cells)
     rb = n_cells / (t_batch * run_steps) * 3600.0
     rp = n_cells / (t_plain * run_steps) * 3600.0
     res = {
@@ -180,6 +181,15 @@ def viscometer_leg(k_steps, n_cells=256, run_steps=5000, graph_steps=10, tune=Tr
     if "autotuned" in out:
         res["autotuned"] = out["autotuned"]
         res["autotuned"]["speedup_vs_plain"] = round(out["autotuned"]["batched_runs_per_hour"] / rp, 2)
+        # the plain runs at their own best too: each cell alone at the tuned
+        # cell size and step mode as well, the faster of the two shapes kept
+        # per cell, so that the gain above is the batching's, not the tuning's
+        t_best = sum(min(t0, timed(p, pp, tun["cell_factor"], tun["graph_steps"]))
+                     for (p, pp, _info), t0 in zip(cells, t_cells))
+        rbest = n_cells / (t_best * run_steps) * 3600.0
+        res["autotuned"]["plain_best_runs_per_hour"] = round(rbest, 1)
+        res["autotuned"]["speedup_vs_best_plain"] = round(
+            out["autotuned"]["batched_runs_per_hour"] / rbest, 2)
     return res
 
 
